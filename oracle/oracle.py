@@ -1,0 +1,328 @@
+"""Python side of the CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Thin ctypes wrapper around liboracle.so plus the plain-numpy glue that the
+paper states in closed form: the objective (eq. node_J, eq. discrete_J), its
+normalisation, the chain rule from the local optimality pieces to each control
+kind (eq. optimality, eq. zero_mean_projection, eq. E_substitution), the
+complex-step forward-mode gradient (eq. fAD) and central finite differences.
+
+Only tests/, the smoke check and the benchmark's CPU-baseline leg may import
+this module.  It does not import the HIP package and the HIP package never
+imports it.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+NONE, DIRICHLET, NEUMANN = 0, 1, 2
+CX = np.array([1, 0, -1, 0, 1, -1, -1, 1])
+CY = np.array([0, 1, 0, -1, 1, 1, -1, -1])
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        _LIB = ctypes.CDLL(path)
+        _setup(_LIB)
+    return _LIB
+
+
+class _CProblem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("dx", ctypes.c_double), ("nu", ctypes.c_double),
+        ("E", ctypes.c_void_p), ("active", ctypes.c_void_p), ("bc", ctypes.c_void_p),
+        ("wall", ctypes.c_void_p), ("normal", ctypes.c_void_p), ("g", ctypes.c_void_p),
+        ("gamma_at_boundary", ctypes.c_int),
+    ]
+
+
+_P = ctypes.c_void_p
+_L = ctypes.c_long
+_D = ctypes.c_double
+
+
+def _setup(lib):
+    pp = ctypes.POINTER(_CProblem)
+    lib.orc_step.argtypes = [pp, _P, _P, _P, _P]
+    lib.orc_run.argtypes = [pp, _P, _L]
+    lib.orc_solve.argtypes = [pp, _P, _D, _L, _L, _P, _P, _P, _P, _P]
+    lib.orc_solve_cs.argtypes = [pp, _P, _P, _P, _P, _D, _L, _L, _P, _P, _P, _P, _P, _P]
+    lib.orc_adj_step.argtypes = [pp, _P, _P, _P, _P, _P]
+    lib.orc_adj_solve.argtypes = [pp, _P, _P, _D, _L, _L, _P, _P, _P]
+    lib.orc_source.argtypes = [pp, _P, _D, _P]
+    lib.orc_grad_local.argtypes = [pp, _P, _P, _P, _P]
+    lib.orc_minv.argtypes = [_P]
+    for f in ("orc_step", "orc_run", "orc_solve", "orc_solve_cs", "orc_adj_step", "orc_adj_solve",
+              "orc_source", "orc_grad_local"):
+        getattr(lib, f).restype = ctypes.c_int
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Problem:
+    """A lattice problem for the oracle.
+
+    nx, ny   grid (x fastest);  dx spacing (dt = dx^2, kappa = 1)
+    E        scalar or (ny, nx) Young's modulus;  nu Poisson ratio
+    g        (2, ny, nx) forcing in lattice units (g = dx^2 F)
+    active   (ny, nx) bool/uint8 domain mask (None = periodic torus, all nodes)
+    bc       (8, ny, nx) uint8 link kinds (incoming population f_q at x whose
+             source x - c_q lies outside): 0, DIRICHLET, NEUMANN
+    wall     (2, 8, ny, nx) wall data per link: d_D (Dirichlet) or T in lattice
+             units (Neumann)
+    normal   (2, 8, ny, nx) outward unit normal per Neumann link
+    """
+
+    def __init__(self, nx, ny, dx, E, nu, g, active=None, bc=None, wall=None, normal=None,
+                 gamma_at_boundary=True):
+        self.nx, self.ny, self.dx, self.nu = int(nx), int(ny), float(dx), float(nu)
+        N = self.nx * self.ny
+        self.E = _f64(np.broadcast_to(np.asarray(E, dtype=np.float64), (self.ny, self.nx)))
+        self.g = _f64(g).reshape(2, self.ny, self.nx)
+        self.active = None if active is None else np.ascontiguousarray(active, dtype=np.uint8).reshape(self.ny, self.nx)
+        self.bc = None if bc is None else np.ascontiguousarray(bc, dtype=np.uint8).reshape(8, self.ny, self.nx)
+        self.wall = None if wall is None else _f64(wall).reshape(2, 8, self.ny, self.nx)
+        self.normal = None if normal is None else _f64(normal).reshape(2, 8, self.ny, self.nx)
+        self.gamma_at_boundary = bool(gamma_at_boundary)
+        self.N = N
+        self._c = _CProblem(self.nx, self.ny, self.dx, self.nu, _ptr(self.E), _ptr(self.active),
+                            _ptr(self.bc), _ptr(self.wall), _ptr(self.normal), _ptr(self.g),
+                            int(self.gamma_at_boundary))
+
+    def with_(self, **kw):
+        args = dict(nx=self.nx, ny=self.ny, dx=self.dx, E=self.E, nu=self.nu, g=self.g,
+                    active=self.active, bc=self.bc, wall=self.wall, normal=self.normal,
+                    gamma_at_boundary=self.gamma_at_boundary)
+        args.update(kw)
+        return Problem(**args)
+
+    @property
+    def mask(self):
+        if self.active is None:
+            return np.ones((self.ny, self.nx), dtype=bool)
+        return self.active.astype(bool)
+
+    def zeros(self, comps=8, dtype=np.float64):
+        return np.zeros((comps, self.ny, self.nx), dtype=dtype)
+
+    def cref(self):
+        return ctypes.byref(self._c)
+
+
+# ----------------------------------------------------------------- primal
+
+def step(p, fS):
+    """One step; returns (fS(t+1), d(t), sigma(t) lattice units)."""
+    fS = _f64(fS)
+    out, d, s = p.zeros(8), p.zeros(2), p.zeros(3)
+    _lib().orc_step(p.cref(), _ptr(fS), _ptr(out), _ptr(d), _ptr(s))
+    return out, d, s
+
+
+def run(p, fS, nsteps):
+    f = _f64(fS).copy()
+    _lib().orc_run(p.cref(), _ptr(f), int(nsteps))
+    return f
+
+
+def check_interval(dx):
+    """K = 2 ceil(0.005 / dx^2): pseudo-time window 0.01 (reading C6)."""
+    return 2 * int(np.ceil(0.005 / (dx * dx) - 1e-9))
+
+
+class Solve:
+    pass
+
+
+def solve(p, fS0=None, tol=1e-10, K=None, max_steps=10_000_000):
+    """Steady state (reading C6/C7); tol <= 0 means exactly max_steps steps."""
+    f = p.zeros(8) if fS0 is None else _f64(fS0).copy()
+    K = check_interval(p.dx) if K is None else int(K)
+    dbar, fbar, sbar = p.zeros(2), p.zeros(8), p.zeros(3)
+    steps, res = ctypes.c_long(0), ctypes.c_double(0)
+    rc = _lib().orc_solve(p.cref(), _ptr(f), float(tol), K, int(max_steps), _ptr(dbar), _ptr(fbar),
+                          _ptr(sbar), ctypes.byref(steps), ctypes.byref(res))
+    s = Solve()
+    s.rc, s.f, s.dbar, s.fbar, s.sbar = rc, f, dbar, fbar, sbar
+    s.steps, s.residual, s.K = steps.value, res.value, K
+    return s
+
+
+def solve_cs(p, E_im=None, g_im=None, tol=1e-10, K=None, max_steps=10_000_000):
+    """Complex-step primal solve: returns (dbar, dbar_im) with inputs E + i E_im, g + i g_im."""
+    fr, fi = p.zeros(8), p.zeros(8)
+    K = check_interval(p.dx) if K is None else int(K)
+    E_im = None if E_im is None else _f64(np.broadcast_to(E_im, (p.ny, p.nx)))
+    g_im = None if g_im is None else _f64(g_im).reshape(2, p.ny, p.nx)
+    dr, di = p.zeros(2), p.zeros(2)
+    steps, res = ctypes.c_long(0), ctypes.c_double(0)
+    rc = _lib().orc_solve_cs(p.cref(), _ptr(E_im), _ptr(g_im), _ptr(fr), _ptr(fi), float(tol), K,
+                             int(max_steps), _ptr(dr), _ptr(di), None, None, ctypes.byref(steps),
+                             ctypes.byref(res))
+    return dr, di, rc, steps.value
+
+
+# ----------------------------------------------------------------- objective
+
+def cbar(p, target, obs=None):
+    """Normalisation constant of eq. node_J: sum_obs |d*|^2 dx^2."""
+    m = p.mask if obs is None else (np.asarray(obs, bool) & p.mask)
+    return float(((target ** 2).sum(0) * m).sum() * p.dx * p.dx)
+
+
+def objective(p, d, target, obs=None, normalize=True):
+    """eq. discrete_J: sum_obs 1/2 |d - d*|^2 dx^2 / Cbar."""
+    m = p.mask if obs is None else (np.asarray(obs, bool) & p.mask)
+    c = cbar(p, target, obs) if normalize else 1.0
+    r = (d - target) * m
+    return 0.5 * float((r ** 2).sum()) * p.dx * p.dx / c
+
+
+# ----------------------------------------------------------------- adjoint
+
+def source(p, r, scale):
+    src = p.zeros(8)
+    _lib().orc_source(p.cref(), _ptr(_f64(r)), float(scale), _ptr(src))
+    return src
+
+
+def adj_step(p, phiC, src):
+    out, dphi, ext = p.zeros(8), p.zeros(2), p.zeros(16)
+    _lib().orc_adj_step(p.cref(), _ptr(_f64(phiC)), _ptr(out), _ptr(_f64(src)), _ptr(dphi), _ptr(ext))
+    return out, dphi, ext
+
+
+def adj_solve(p, src, tol=1e-10, K=None, max_steps=10_000_000, phiC0=None):
+    phiC = p.zeros(8) if phiC0 is None else _f64(phiC0).copy()
+    K = check_interval(p.dx) if K is None else int(K)
+    ext = p.zeros(16)
+    steps, res = ctypes.c_long(0), ctypes.c_double(0)
+    rc = _lib().orc_adj_solve(p.cref(), _ptr(phiC), _ptr(_f64(src)), float(tol), K, int(max_steps),
+                              _ptr(ext), ctypes.byref(steps), ctypes.byref(res))
+    s = Solve()
+    s.rc, s.phiC, s.ext, s.steps, s.residual = rc, phiC, ext, steps.value, res.value
+    return s
+
+
+def grad_local(p, fbar, ext, want_E=False):
+    dg = p.zeros(2)
+    dE = p.zeros(1)[0] if want_E else None
+    _lib().orc_grad_local(p.cref(), _ptr(_f64(fbar)), _ptr(_f64(ext)), _ptr(dg), _ptr(dE))
+    return dg, dE
+
+
+def zero_mean(a, mask=None):
+    """eq. zero_mean_projection, per component."""
+    a = np.array(a, dtype=np.float64)
+    if mask is None:
+        return a - a.reshape(a.shape[0], -1).mean(1)[:, None, None]
+    m = np.asarray(mask, bool)
+    out = a.copy()
+    for c in range(a.shape[0]):
+        out[c][m] -= a[c][m].mean()
+    return out
+
+
+class Gradient:
+    pass
+
+
+def objective_and_grad(p, target, kind, control, modes=None, fixed_force=None, obs=None,
+                       normalize=True, tol=1e-10, K=None, max_steps=10_000_000, project=None):
+    """Primal solve, J, adjoint solve and eq. optimality for one control kind.
+
+    kind: 'modes'  (F = sum_i a_i B_i, control a (k,), modes (k, 2, ny, nx))
+          'nodal'  (F = P(alpha), control (2, ny, nx))
+          'E_nodal' (E = control (ny, nx), forcing dx^2 * fixed_force)
+          'E_sq'   (E = alpha^2, control (1,))
+    project: zero-mean projection of nodal force control and gradient
+             (default: on for 'nodal' on periodic problems).
+    """
+    dx2 = p.dx * p.dx
+    if kind == "modes":
+        a = np.asarray(control, dtype=np.float64)
+        F = np.tensordot(a, modes, 1)
+        q = p.with_(g=dx2 * F)
+    elif kind == "nodal":
+        if project is None:
+            project = p.active is None
+        F = zero_mean(control) if project else np.asarray(control, dtype=np.float64)
+        q = p.with_(g=dx2 * F)
+    elif kind == "E_nodal":
+        q = p.with_(E=np.asarray(control, dtype=np.float64), g=dx2 * fixed_force)
+    elif kind == "E_sq":
+        a = float(np.asarray(control).reshape(-1)[0])
+        q = p.with_(E=a * a, g=dx2 * fixed_force)
+    else:
+        raise ValueError(kind)
+    prim = solve(q, tol=tol, K=K, max_steps=max_steps)
+    m = q.mask if obs is None else (np.asarray(obs, bool) & q.mask)
+    c = cbar(q, target, obs) if normalize else 1.0
+    r = (prim.dbar - target) * m
+    J = 0.5 * float((r ** 2).sum()) * dx2 / c
+    src = source(q, r, dx2 / c)
+    adj = adj_solve(q, src, tol=tol, K=K, max_steps=max_steps)
+    dg_adj, dE = grad_local(q, prim.fbar, adj.ext, want_E=kind in ("E_nodal", "E_sq"))
+    # explicit dependence of d on g (half forcing): dJ/dg = r/2 * dx^2/Cbar
+    dJdg = 0.5 * r * dx2 / c + dg_adj
+    dJdF = dx2 * dJdg
+    out = Gradient()
+    out.J, out.prim, out.adj, out.r, out.cbar, out.problem = J, prim, adj, r, c, q
+    if kind == "modes":
+        out.grad = np.array([float((dJdF * b).sum()) for b in modes])
+    elif kind == "nodal":
+        out.grad = zero_mean(dJdF) if project else dJdF
+    elif kind == "E_nodal":
+        out.grad = dE * q.mask
+    else:
+        out.grad = np.array([float((dE * q.mask).sum()) * 2.0 * a])
+    return out
+
+
+def fad_grad_modes(p, target, control, modes, obs=None, normalize=True, tol=1e-10, K=None,
+                   max_steps=10_000_000, h=1e-30):
+    """Forward-mode (eq. fAD) gradient for mode controls: one complex-step primal
+    per control direction; dJ/da_i = Im J(a + i h e_i) / h."""
+    dx2 = p.dx * p.dx
+    a = np.asarray(control, dtype=np.float64)
+    q = p.with_(g=dx2 * np.tensordot(a, modes, 1))
+    m = q.mask if obs is None else (np.asarray(obs, bool) & q.mask)
+    c = cbar(q, target, obs) if normalize else 1.0
+    out = []
+    for i in range(len(a)):
+        dr, di, rc, _ = solve_cs(q, g_im=h * dx2 * modes[i], tol=tol, K=K, max_steps=max_steps)
+        # J(a + i h e_i) = 1/2 sum (r + i h dd)^2 dx^2 / c  ->  Im / h = sum r * dd dx^2 / c
+        out.append(float((((dr - target) * di / h) * m).sum()) * dx2 / c)
+    return np.array(out)
+
+
+def fad_grad_E_sq(p, target, alpha, fixed_force, obs=None, normalize=True, tol=1e-10, K=None,
+                  max_steps=10_000_000, h=1e-30):
+    """Forward-mode gradient for E = alpha^2 via a complex-step primal solve."""
+    dx2 = p.dx * p.dx
+    q = p.with_(E=alpha * alpha, g=dx2 * fixed_force)
+    m = q.mask if obs is None else (np.asarray(obs, bool) & q.mask)
+    c = cbar(q, target, obs) if normalize else 1.0
+    dr, di, rc, _ = solve_cs(q, E_im=np.full((p.ny, p.nx), 2.0 * alpha * h), tol=tol, K=K,
+                             max_steps=max_steps)
+    return float((((dr - target) * di / h) * m).sum()) * dx2 / c
+
+
+def minv():
+    out = np.zeros(64)
+    _lib().orc_minv(_ptr(out))
+    return out.reshape(8, 8)

@@ -1,0 +1,150 @@
+"""Benchmark: FP64 primal + adjoint solid-LBM sweeps and time-to-gradient on one MI355X.
+
+Workload: periodic two-amplitude force identification on the unit torus at
+N = 1024 (E = 1, nu = 0.3, body force A1 b1 + A2 b2, target the continuum
+displacement of A* = (0.7, 0.3)), gradient at the L-BFGS start A = (0.1, 0.1).
+One step = one objective_and_grad call: cold primal solve to residual 1e-10,
+J, adjoint solve to 1e-10, gradient dJ/dA (all on the GPU, inputs resident).
+
+value = MLUPS over all primal + adjoint sweeps of the timed steps
+(cells x sweeps / wall seconds / 1e6).  The roofline object is for the
+dominant kernel (the primal sweep): algorithmic 144 B/node/sweep x nodes /
+the average sweep duration measured with HIP events on the library's stream
+during the timed steps.  cpu_baseline = the CPU oracle timed on a bounded
+sample of the same workload on one host core.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_NODE = 144.0      # 8 pops read + 8 written (8 B each) + 2 forcing / residual reads
+PEAK_GBS = 8000.0           # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    return ap.parse_args()
+
+
+def cpu_baseline(n, steps, a):
+    """Oracle sweeps on a bounded sample: `steps` primal and `steps` adjoint
+    sweeps of the same N x N workload on one core."""
+    from oracle import oracle as O
+    from paper_2609_31347_amd import inputs as I
+    modes = I.two_mode_basis(n)
+    tgt = I.two_mode_target(n)
+    p = O.Problem(n, n, 1.0 / n, 1.0, 0.3, np.tensordot(a, modes, 1) / n ** 2)
+    f = p.zeros(8)
+    t0 = time.perf_counter()
+    f = O.run(p, f, steps)
+    t1 = time.perf_counter()
+    _, d, _ = O.step(p, f)
+    src = O.source(p, d - tgt, (1.0 / n ** 2) / O.cbar(p, tgt))
+    ph = p.zeros(8)
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        ph = O.adj_step(p, ph, src)[0]
+    t3 = time.perf_counter()
+    cells = n * n
+    mlups = 2 * steps * cells / ((t1 - t0) + (t3 - t2)) / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} primal + {steps} adjoint oracle sweeps of the {n}x{n} workload "
+                      f"(single-threaded C, -O2 -ffp-contract=off)",
+            "primal_mlups": round(steps * cells / (t1 - t0) / 1e6, 3),
+            "adjoint_mlups": round(steps * cells / (t3 - t2) / 1e6, 3)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
+              f"decomposition is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2609_31347_amd import inputs as I
+    from paper_2609_31347_amd import slbm as S
+
+    torch.cuda.set_device(0)
+    n = args.n
+    modes = I.two_mode_basis(n)
+    tgt = I.two_mode_target(n)
+    prob = dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC, target=tgt,
+                control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes, tol=args.tol,
+                max_steps=50_000_000, stream=torch.cuda.current_stream().cuda_stream)
+    ctx = S.solid_lbm_init(prob)
+    a = torch.tensor([0.1, 0.1], dtype=torch.float64, device="cuda")
+    grad = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    for _ in range(args.warmup):
+        S.objective_and_grad(ctx, a, grad=grad)
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc, J, _, pi, ai = S.objective_and_grad(ctx, a, grad=grad)
+        rec.append((rc, J, pi.as_dict(), ai.as_dict()))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    cells = n * n
+    sweeps = sum(r[2]["sweeps"] + r[3]["sweeps"] for r in rec)
+    p_sweeps = sum(r[2]["sweeps"] for r in rec)
+    a_sweeps = sum(r[3]["sweeps"] for r in rec)
+    p_ms = sum(r[2]["device_ms"] for r in rec)
+    a_ms = sum(r[3]["device_ms"] for r in rec)
+    mlups = sweeps * cells / wall / 1e6
+    t_primal = p_ms / p_sweeps * 1e-3          # s per primal sweep (device, events)
+    t_adj = a_ms / a_sweeps * 1e-3
+    ach = BYTES_PER_NODE * cells / t_primal / 1e9
+    ach_adj = BYTES_PER_NODE * cells / t_adj / 1e9
+    out = {
+        "metric": "FP64 MLUPS primal+adjoint (%HBM roofline); time-to-gradient at res 1e-10",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"periodic two-amplitude force identification, {n}x{n} torus, E=1, nu=0.3, "
+                               f"gradient at A=(0.1,0.1), primal+adjoint to residual {args.tol:g}",
+                   "grid": [n, n], "tol": args.tol, "control": "FORCE_MODES"},
+        "time_to_gradient_s": round(wall / args.steps, 4),
+        "primal": {"sweeps": rec[-1][2]["sweeps"], "steps": rec[-1][2]["steps"],
+                   "mlups": round(cells / t_primal / 1e6, 1), "converged": rec[-1][2]["converged"]},
+        "adjoint": {"sweeps": rec[-1][3]["sweeps"], "steps": rec[-1][3]["steps"],
+                    "mlups": round(cells / t_adj / 1e6, 1), "converged": rec[-1][3]["converged"],
+                    "achieved_GBs": round(ach_adj, 1), "frac": round(ach_adj / PEAK_GBS, 4)},
+        "J": rec[-1][1],
+        "grad": [float(x) for x in grad.cpu().numpy()],
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_primal<false,false,false> (periodic primal sweep)",
+                     "bytes_per_node": BYTES_PER_NODE, "nodes_per_launch": cells,
+                     "avg_sweep_us": round(t_primal * 1e6, 3)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, np.array([0.1, 0.1]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * solid_lbm.h -- C ABI of the MI355X solid lattice-Boltzmann library.
+ *
+ * The library solves the steady linear-elastic state of a D2Q8 moment-space
+ * lattice-Boltzmann scheme (paper Sec. "LBM scheme for solids": eq. moments to
+ * eq. local_stream, appendix matrix M and relaxation-time table) to a
+ * pseudo-time fixed point (eq. primal_fixed_point), evaluates the discrete
+ * objective (eq. node_J, eq. discrete_J), runs the discrete adjoint fixed-point
+ * iteration (eq. adjoint_streaming, eq. adjoint_collision, eq.
+ * adjoint_iteration, eq. adjoint_init; Algorithm "ALBM") and assembles the
+ * gradient of the objective w.r.t. the control (eq. optimality).
+ *
+ * Conventions
+ *  - Every number is IEEE double.  Fields are SoA, component-major, x fastest:
+ *      a[c * nx * ny + iy * nx + ix].
+ *    Per-link fields use c * 8 + q as the component (q in the direction order
+ *    Q of eq. direction_order: (1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1)).
+ *  - Units: diffusive scaling dt = dx^2, kappa = 1, so lattice moduli equal
+ *    the physical ones; the forcing is g = dx^2 F (eq. forcing); stresses and
+ *    tractions in lattice units are dx times the physical ones.
+ *  - Pointers marked "host" must be host memory.  Pointers passed with
+ *    ptr_kind = SLBM_PTR_DEVICE must be device memory of the context's GPU
+ *    (e.g. a torch CUDA tensor's data_ptr()); SLBM_PTR_HOST means host memory.
+ *  - Ownership: the library copies every input it needs during the call and
+ *    never keeps a caller pointer; outputs are written into caller memory.
+ *  - Errors: negative return codes leave the context unchanged and set the
+ *    message returned by solid_lbm_last_error().  A positive code (only
+ *    SLBM_NOT_CONVERGED) means the outputs were written but the solve stopped
+ *    at max_steps before the residual reached tol.
+ *  - Threading: one context per host thread at a time; all work of a context
+ *    is queued on its stream (problem.stream, NULL = the default stream) and
+ *    every call returns after that stream has drained.
+ */
+#ifndef SOLID_LBM_H
+#define SOLID_LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SLBM_OK = 0,
+    SLBM_NOT_CONVERGED = 1,
+    SLBM_EINVAL = -1,     /* bad sizes, moduli, flags, or a plate touching the box edge */
+    SLBM_ENOMEM = -2,     /* device allocation failed */
+    SLBM_EHIP = -3,       /* a HIP runtime call failed (message holds the HIP error) */
+    SLBM_ESTATE = -4,     /* call order: adjoint before a converged primal, etc. */
+    SLBM_ENONFINITE = -5  /* non-finite control or input field */
+};
+
+/* Domain kinds: periodic torus (Sec. "Problem formulation": Omega = T^2) or a
+ * plate given as a node mask inside a box, with Dirichlet / Neumann links. */
+enum { SLBM_PERIODIC = 0, SLBM_MASKED = 1 };
+
+/* Control kinds (Table "overview_cases" and the controls of the benchmarks):
+ *  FORCE_MODES   F = sum_i a_i B_i(x)           control: n_modes doubles
+ *  FORCE_NODAL   F(x_n) = P(alpha)(x_n)         control: 2 * nx * ny doubles
+ *                (P = eq. zero_mean_projection when zero_mean_projection != 0)
+ *  E_NODAL       E(x_n) = alpha(x_n)            control: nx * ny doubles
+ *  E_SCALAR_SQ   E = alpha^2 (eq. E_substitution) control: 1 double          */
+enum { SLBM_CTRL_FORCE_MODES = 0, SLBM_CTRL_FORCE_NODAL = 1, SLBM_CTRL_E_NODAL = 2,
+       SLBM_CTRL_E_SCALAR_SQ = 3 };
+
+enum { SLBM_PTR_HOST = 0, SLBM_PTR_DEVICE = 1 };
+
+/* Link kinds of link_bc. */
+enum { SLBM_LINK_INTERIOR = 0, SLBM_LINK_DIRICHLET = 1, SLBM_LINK_NEUMANN = 2 };
+
+/* Fields readable with solid_lbm_get_field (sizes in doubles). */
+enum {
+    SLBM_FIELD_DISP = 0,      /* 2N: converged two-step-averaged displacement d   */
+    SLBM_FIELD_STRESS = 1,    /* 3N: (sxx, syy, sxy) lattice units of the averaged state */
+    SLBM_FIELD_ADJ_DISP = 2,  /* 2N: adjoint displacement of the averaged adjoint  */
+    SLBM_FIELD_POPS = 3,      /* 8N: current primal post-streaming populations f^S */
+    SLBM_FIELD_ADJ_POPS = 4,  /* 8N: current adjoint post-collision populations phi^C */
+    SLBM_FIELD_RESIDUAL = 5,  /* 2N: r = d - d* on the observation set (0 elsewhere) */
+    SLBM_FIELD_CUR_DISP = 6   /* 2N: bared displacement of the current state f^S   */
+};
+
+typedef struct slbm_ctx slbm_ctx; /* opaque; owns all device buffers */
+
+/*
+ * Problem description.  All pointers are host memory, read during
+ * solid_lbm_init only.  N = nx * ny.
+ */
+typedef struct {
+    int32_t nx, ny;            /* nodes per direction (>= 3 each) */
+    double dx;                 /* lattice spacing (> 0); dt = dx^2 */
+    double E, nu;              /* uniform Young's modulus (> 0) and Poisson ratio
+                                  (-1 < nu < 1); E ignored for E controls */
+    int32_t domain;            /* SLBM_PERIODIC or SLBM_MASKED */
+    const uint8_t *node_mask;  /* MASKED: N bytes, 1 = node of the domain.  No
+                                  domain node may lie on the box edge. */
+    const uint8_t *link_bc;    /* MASKED: 8N bytes [q * N + n]: kind of the link
+                                  carrying f_q into node n from n - c_q; must be
+                                  non-zero exactly when n - c_q is outside */
+    const double *link_wall;   /* MASKED: 16N [(c * 8 + q) * N + n]: wall value per
+                                  cut link: d_D (Dirichlet) or T (Neumann), lattice units */
+    const double *link_normal; /* MASKED: 16N: outward unit normal per Neumann link */
+    const double *fixed_force; /* 2N body force F for the E controls (NULL = 0) */
+    const double *target;      /* 2N target displacement d* (required) */
+    const uint8_t *obs_mask;   /* N bytes observation set (NULL = all domain nodes) */
+    int32_t control_kind;      /* SLBM_CTRL_* */
+    int32_t n_modes;           /* FORCE_MODES: number of modes k (1..64) */
+    const double *force_modes; /* FORCE_MODES: k * 2N mode fields B_i */
+    int32_t zero_mean_projection; /* FORCE_NODAL on PERIODIC: project control and
+                                     gradient (eq. zero_mean_projection); 1 = on */
+    int32_t normalize_objective;  /* 1: divide J by Cbar of eq. node_J; 0: plain 1/2 L2 */
+    double tol;                /* residual tolerance (e.g. 1e-10); <= 0: run max_steps */
+    int64_t max_steps;         /* step limit per solve (>= 1) */
+    int32_t check_interval;    /* K of the residual ||d(t) - d(t-K)|| / ||d(t)||;
+                                  0 -> 2 * ceil(0.005 / dx^2) (even K) */
+    void *stream;              /* hipStream_t for all work (NULL = default stream) */
+} slbm_problem;
+
+typedef struct {
+    int64_t steps;     /* step index t at which the residual test passed (or stopped) */
+    int64_t sweeps;    /* lattice sweeps executed, including the averaging step */
+    double residual;   /* last residual */
+    double wall_s;     /* wall time of the solve (host clock, stream drained) */
+    double device_ms;  /* device time of the sweep loop: HIP events recorded on the
+                          context's stream before the first and after the last sweep */
+    int32_t converged; /* 1 if residual < tol */
+} slbm_solve_info;
+
+/*
+ * Creates a context for one problem on the current HIP device: validates and
+ * copies every input, allocates all device buffers (populations in two
+ * SoA buffers of 8 planes, forcing, target, observation mask, plate records).
+ * Returns SLBM_OK and *out, or a negative code (then *out = NULL).
+ */
+int solid_lbm_init(const slbm_problem *problem, slbm_ctx **out);
+
+/*
+ * Primal solve to steady state (eq. primal_fixed_point) for the given control:
+ * control -> forcing or moduli, pseudo-time march from f^S(0) (cold: all
+ * zero, eq. discrete_G closed by f^S(0) of d_0 = 0; warm: the equilibrium
+ * populations of init_disp (2N)), residual test every K steps, then the
+ * two-step average d = (d(t) + d(t+1)) / 2.  Leaves the averaged state, d,
+ * r = d - d* and J in the context.  control / init_disp are read according to
+ * ptr_kind; init_disp may be NULL.  info may be NULL.
+ */
+int primal_solve(slbm_ctx *ctx, const double *control, const double *init_disp,
+                 int32_t ptr_kind, slbm_solve_info *info);
+
+/*
+ * Adjoint solve (Algorithm "ALBM"): from phi^C(0) = 0 iterate
+ * phi^S = S^T phi^C, phi^C = (dC/df)^T phi^S - (dJ/df)^T at the converged
+ * primal state, residual test on the adjoint displacement every K steps, then
+ * the two-step average.  Requires a completed primal_solve (else
+ * SLBM_ESTATE).  info may be NULL.
+ */
+int adjoint_solve(slbm_ctx *ctx, slbm_solve_info *info);
+
+/*
+ * Objective and gradient for one control: primal_solve (cold start) + J +
+ * adjoint_solve + eq. optimality.  *J (host) receives the objective; grad
+ * (length n_modes, 2N, N or 1 by control kind; NULL = J only, no adjoint)
+ * is written according to ptr_kind.  primal_info / adjoint_info may be NULL.
+ */
+int objective_and_grad(slbm_ctx *ctx, const double *control, double *J, double *grad,
+                       int32_t ptr_kind, slbm_solve_info *primal_info,
+                       slbm_solve_info *adjoint_info);
+
+/* ---- helpers ---- */
+
+/* Sets the forcing/moduli from a control (as primal_solve) and resets the
+ * primal state to f^S(0) (cold, or warm from init_disp); no stepping. */
+int solid_lbm_set_control(slbm_ctx *ctx, const double *control, const double *init_disp,
+                          int32_t ptr_kind);
+
+/* Advances the current primal state by n >= 0 steps (fixed-step mode). */
+int solid_lbm_run_steps(slbm_ctx *ctx, int64_t n);
+
+/* Resets the adjoint to phi^C = 0 and advances it by n >= 0 steps using the
+ * residual of the last primal_solve (fixed-step mode). */
+int solid_lbm_run_adjoint_steps(slbm_ctx *ctx, int64_t n);
+
+/* Copies a field (SLBM_FIELD_*) into out (host or device per ptr_kind). */
+int solid_lbm_get_field(slbm_ctx *ctx, int32_t which, double *out, int32_t ptr_kind);
+
+/* Timing helper: runs n primal (adjoint = 0) or adjoint (adjoint = 1) sweeps
+ * on the current state and returns the device time of those sweeps in
+ * *ms (HIP events recorded on the context's stream around them). */
+int solid_lbm_time_sweeps(slbm_ctx *ctx, int32_t adjoint, int64_t n, double *ms);
+
+/* Message of the last error on ctx (or of the last failed init if ctx is NULL). */
+const char *solid_lbm_last_error(const slbm_ctx *ctx);
+
+/* Frees every device buffer of ctx (NULL is a no-op). */
+void solid_lbm_destroy(slbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOLID_LBM_H */

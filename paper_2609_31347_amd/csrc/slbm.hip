@@ -1,0 +1,909 @@
+// C-ABI implementation of the MI355X solid lattice-Boltzmann library.
+// Host orchestration of the HIP kernels in slbm_kernels.h: problem validation
+// and upload, the pseudo-time loops with device-side convergence flags, the
+// objective and the gradient assembly per control kind.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "solid_lbm.h"
+#include "slbm_kernels.h"
+
+using namespace slbm;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+}  // namespace
+
+struct slbm_ctx {
+    // problem
+    int nx = 0, ny = 0;
+    int64_t N = 0;
+    double dx = 0, dx2 = 0, E = 0, nu = 0, tol = 0, inv_nx = 0;
+    int64_t max_steps = 0;
+    int64_t K = 0;
+    int kind = 0, nmodes = 0, project = 0, normalize = 1;
+    bool masked = false;
+    int nb = 0;  // boundary records
+    double cbar = 1.0;
+    hipStream_t stream = nullptr;
+    // device buffers
+    double* fbuf[2] = {nullptr, nullptr};
+    double* abuf[2] = {nullptr, nullptr};
+    double *g = nullptr, *Efield = nullptr, *target = nullptr, *snap = nullptr, *dbar = nullptr,
+           *r = nullptr, *fbar = nullptr, *dJdF = nullptr, *dJdE = nullptr, *adisp = nullptr,
+           *modes = nullptr, *fixedF = nullptr, *work = nullptr, *partial = nullptr, *scal = nullptr,
+           *bjac = nullptr, *ctrl = nullptr;
+    uint8_t* obs = nullptr;
+    int32_t* code = nullptr;
+    BNode* bnodes = nullptr;
+    Status* status = nullptr;
+    Status* h_status = nullptr;  // pinned, 2 slots
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int64_t nblk = 0;  // blocks of one sweep
+    int64_t pcap = 0;  // capacity of the partial-sum buffer in blocks
+    // state
+    int prim_cur = 0;       // buffer holding f^C(t-1) of the current primal state
+    bool prim_valid = false;
+    bool prim_done = false; // a completed primal_solve (adjoint inputs ready)
+    int adj_cur = 0;
+    bool adj_done = false;
+    bool efield_on = false; // E_NODAL: kernels read the E plane
+    double E_cur = 0;       // uniform E of the current control
+    double alpha_sq = 0;    // E_SCALAR_SQ control value
+    double J = 0;
+    std::string err;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+int fail(slbm_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    else g_init_error = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, SLBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int dalloc(slbm_ctx* c, void** p, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, SLBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    c->allocs.push_back(*p);
+    return SLBM_OK;
+}
+
+// eq. gamma divides by tau_s - tau_f, tau_s = 2K/(1+theta) = 3E/(4(1-nu))
+bool gamma_ok(double E, double nu) { return std::fabs(0.75 * E / (1.0 - nu) - kTauF) > 1e-12; }
+
+inline unsigned grid_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+bool finite_all(const double* a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+int fill(slbm_ctx* c, double* a, int64_t n, double v)
+{
+    hipLaunchKernelGGL(k_fill, dim3(grid_of(n)), dim3(kBlock), 0, c->stream, a, n, v);
+    HIPCHK(c, hipGetLastError());
+    return SLBM_OK;
+}
+
+// Relaxation keep-factors of a uniform material on the host.
+Relax<double> host_relax(double E, double nu) { return relax_from_E<double>(E, nu, false); }
+
+SweepArgs base_args(slbm_ctx* c)
+{
+    SweepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.code = c->code;
+    a.bnodes = c->bnodes;
+    a.bjac = c->bjac;
+    a.snap = c->snap;
+    a.partial = c->partial;
+    a.status = c->status;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.N = c->N;
+    Relax<double> r = host_relax(c->E_cur, c->nu);
+    a.k11 = r.k11;
+    a.ks = r.ks;
+    a.kd = r.kd;
+    a.E0 = c->E_cur;
+    a.nu = c->nu;
+    a.E = c->efield_on ? c->Efield : nullptr;
+    return a;
+}
+
+void launch_sweep(slbm_ctx* c, bool adjoint, const SweepArgs& a, bool check)
+{
+    int sel = (c->masked ? 4 : 0) | (c->efield_on ? 2 : 0) | (check ? 1 : 0);
+    dim3 grid(grid_of(c->N)), block(kBlock);
+    double inv = c->inv_nx;
+#define SL_CASE(i, M, EF, CH)                                                                        \
+    case i:                                                                                          \
+        if (adjoint) hipLaunchKernelGGL((k_adjoint<M, EF, CH>), grid, block, 0, c->stream, a, inv);  \
+        else hipLaunchKernelGGL((k_primal<M, EF, CH>), grid, block, 0, c->stream, a, inv);           \
+        break;
+    switch (sel) {
+        SL_CASE(0, false, false, false)
+        SL_CASE(1, false, false, true)
+        SL_CASE(2, false, true, false)
+        SL_CASE(3, false, true, true)
+        SL_CASE(4, true, false, false)
+        SL_CASE(5, true, false, true)
+        SL_CASE(6, true, true, false)
+        SL_CASE(7, true, true, true)
+    }
+#undef SL_CASE
+}
+
+// Runs sweeps with indices 0 .. last (inclusive) from buffer parity `start`,
+// checking every K steps when tol > 0; stops at the first passing test.
+// Returns the step index t of the final state whose successor was also
+// produced (the last executed sweep has index t).
+int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, int64_t* t_out,
+             double* res_out, bool* conv_out, double* dev_ms = nullptr)
+{
+    double** bufs = adjoint ? c->abuf : c->fbuf;
+    hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(1), 0, c->stream, c->status);
+    HIPCHK(c, hipGetLastError());
+    SweepArgs a = base_args(c);
+    if (adjoint) {
+        a.g = c->r;
+        a.scale = c->dx2 / c->cbar;
+    } else {
+        a.g = c->g;
+    }
+    const int64_t K = c->K;
+    int64_t s = 0;
+    int chunk = 0;
+    bool stopped = false;
+    HIPCHK(c, hipEventRecord(c->t0, c->stream));
+    while (s <= last && !stopped) {
+        int64_t end = use_tol ? std::min(last, (s / K + 1) * K - 1) : last;
+        if (!use_tol && end - s > 4096) end = s + 4095;
+        for (; s <= end; ++s) {
+            bool check = use_tol && s > 0 && s % K == 0;
+            int cur = (start + (int)(s & 1)) & 1;
+            a.src = bufs[cur];
+            a.dst = bufs[cur ^ 1];
+            launch_sweep(c, adjoint, a, check);
+            if (check)
+                hipLaunchKernelGGL(k_residual, dim3(1), dim3(kBlock), 0, c->stream, c->partial, c->nblk,
+                                   c->status, c->tol, s);
+        }
+        HIPCHK(c, hipGetLastError());
+        if (use_tol) {
+            int slot = chunk & 1;
+            HIPCHK(c, hipMemcpyAsync(&c->h_status[slot], c->status, sizeof(Status), hipMemcpyDeviceToHost,
+                                     c->stream));
+            HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
+            if (chunk >= 1) {
+                HIPCHK(c, hipEventSynchronize(c->ev[slot ^ 1]));
+                if (c->h_status[slot ^ 1].stop) stopped = true;
+            }
+            ++chunk;
+        }
+    }
+    HIPCHK(c, hipEventRecord(c->t1, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (dev_ms) {
+        float f = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&f, c->t0, c->t1));
+        *dev_ms = f;
+    }
+    Status st;
+    HIPCHK(c, hipMemcpy(&st, c->status, sizeof(Status), hipMemcpyDeviceToHost));
+    if (use_tol && st.stop) {
+        *t_out = st.t_conv;
+        *conv_out = true;
+    } else {
+        *t_out = last;
+        *conv_out = false;
+    }
+    *res_out = st.res;
+    return SLBM_OK;
+}
+
+int sum_partials(slbm_ctx* c, double* out_host)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, c->stream, c->partial, c->nblk, c->scal);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(out_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SLBM_OK;
+}
+
+// sum_i a[i] * w[i] over n entries (w null: plain sum), deterministic
+int dot(slbm_ctx* c, const double* a, const double* w, int64_t n, double* out_host)
+{
+    int64_t nb = (n + kBlock - 1) / kBlock;
+    if (nb > c->pcap) return fail(c, SLBM_EINVAL, "internal: reduction too large");
+    hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)nb), dim3(kBlock), 0, c->stream, a, w, n, c->partial);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, c->stream, c->partial, nb, c->scal);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(out_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SLBM_OK;
+}
+
+int copy_in(slbm_ctx* c, void* dst, const void* src, size_t bytes, int ptr_kind)
+{
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes,
+                             ptr_kind == SLBM_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             c->stream));
+    return SLBM_OK;
+}
+
+int copy_out(slbm_ctx* c, void* dst, const void* src, size_t bytes, int ptr_kind)
+{
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes,
+                             ptr_kind == SLBM_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SLBM_OK;
+}
+
+int64_t control_len(const slbm_ctx* c)
+{
+    switch (c->kind) {
+        case SLBM_CTRL_FORCE_MODES: return c->nmodes;
+        case SLBM_CTRL_FORCE_NODAL: return 2 * c->N;
+        case SLBM_CTRL_E_NODAL: return c->N;
+        default: return 1;
+    }
+}
+
+// Control -> forcing / moduli (eq. forcing, eq. zero_mean_projection,
+// eq. E_substitution).  The control is staged in c->ctrl.
+int apply_control(slbm_ctx* c, const double* control, int ptr_kind)
+{
+    int64_t len = control_len(c);
+    if (!control) return fail(c, SLBM_EINVAL, "control is NULL");
+    std::vector<double> h(len);
+    if (ptr_kind == SLBM_PTR_DEVICE) {
+        HIPCHK(c, hipMemcpyAsync(h.data(), control, len * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::memcpy(h.data(), control, len * sizeof(double));
+    }
+    if (!finite_all(h.data(), len)) return fail(c, SLBM_ENONFINITE, "control has non-finite entries");
+    switch (c->kind) {
+        case SLBM_CTRL_FORCE_MODES: {
+            HIPCHK(c, hipMemcpyAsync(c->ctrl, h.data(), len * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            hipLaunchKernelGGL(k_force_modes, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->modes,
+                               c->ctrl, c->nmodes, 2 * c->N, c->dx2, c->g);
+            HIPCHK(c, hipGetLastError());
+            if (c->masked) {
+                hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->g,
+                                   (const double*)nullptr, c->code, c->N, 1.0, c->g);
+                HIPCHK(c, hipGetLastError());
+            }
+            c->E_cur = c->E;
+            c->efield_on = false;
+            break;
+        }
+        case SLBM_CTRL_FORCE_NODAL: {
+            HIPCHK(c, hipMemcpyAsync(c->ctrl, h.data(), len * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            const double* mean = nullptr;
+            if (c->project) {
+                double m[2];
+                for (int k = 0; k < 2; ++k) {
+                    int rc = dot(c, c->ctrl + k * c->N, nullptr, c->N, &m[k]);
+                    if (rc) return rc;
+                    m[k] /= (double)c->N;
+                }
+                HIPCHK(c, hipMemcpyAsync(c->work, m, 2 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                mean = c->work;
+            }
+            hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->ctrl, mean,
+                               c->masked ? c->code : (const int32_t*)nullptr, c->N, c->dx2, c->g);
+            HIPCHK(c, hipGetLastError());
+            c->E_cur = c->E;
+            c->efield_on = false;
+            break;
+        }
+        case SLBM_CTRL_E_NODAL: {
+            for (int64_t i = 0; i < len; ++i) {
+                if (!(h[i] > 0.0)) return fail(c, SLBM_EINVAL, "E control must be > 0 everywhere");
+                if (c->masked && !gamma_ok(h[i], c->nu))
+                    return fail(c, SLBM_EINVAL, "tau_s = tau_f: the boundary coefficient gamma is undefined");
+            }
+            HIPCHK(c, hipMemcpyAsync(c->Efield, h.data(), len * sizeof(double), hipMemcpyHostToDevice,
+                                     c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->g, c->fixedF, 2 * c->N * sizeof(double), hipMemcpyDeviceToDevice,
+                                     c->stream));
+            c->efield_on = true;
+            c->E_cur = h[0];
+            break;
+        }
+        default: {
+            double a = h[0];
+            if (a == 0.0) return fail(c, SLBM_EINVAL, "E = alpha^2 must be > 0");
+            if (c->masked && !gamma_ok(a * a, c->nu))
+                return fail(c, SLBM_EINVAL, "tau_s = tau_f: the boundary coefficient gamma is undefined");
+            c->alpha_sq = a;
+            c->E_cur = a * a;
+            c->efield_on = false;
+            HIPCHK(c, hipMemcpyAsync(c->g, c->fixedF, 2 * c->N * sizeof(double), hipMemcpyDeviceToDevice,
+                                     c->stream));
+            break;
+        }
+    }
+    // the staged host copy of the control must outlive its upload
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SLBM_OK;
+}
+
+int reset_primal(slbm_ctx* c, const double* init_disp, int ptr_kind)
+{
+    int rc;
+    if ((rc = fill(c, c->fbuf[0], 8 * c->N, 0.0))) return rc;
+    if ((rc = fill(c, c->fbuf[1], 8 * c->N, 0.0))) return rc;
+    const double* d0 = nullptr;
+    if (init_disp) {
+        if ((rc = copy_in(c, c->work, init_disp, 2 * c->N * sizeof(double), ptr_kind))) return rc;
+        d0 = c->work;
+    }
+    hipLaunchKernelGGL(k_init_state, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->fbuf[0], d0, c->g,
+                       c->masked ? c->code : (const int32_t*)nullptr, c->nx, c->ny, c->N, c->inv_nx, c->snap);
+    HIPCHK(c, hipGetLastError());
+    c->prim_cur = 0;
+    c->prim_valid = true;
+    c->prim_done = false;
+    c->adj_done = false;
+    return SLBM_OK;
+}
+
+int finalize_primal(slbm_ctx* c, int X)
+{
+    if (c->masked)
+        hipLaunchKernelGGL(k_primal_finalize<true>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream,
+                           c->fbuf[X], c->fbuf[X ^ 1], c->g, c->code, c->target, c->obs, c->nx, c->ny, c->N,
+                           c->inv_nx, c->dbar, c->r, c->fbar, c->partial);
+    else
+        hipLaunchKernelGGL(k_primal_finalize<false>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream,
+                           c->fbuf[X], c->fbuf[X ^ 1], c->g, c->code, c->target, c->obs, c->nx, c->ny, c->N,
+                           c->inv_nx, c->dbar, c->r, c->fbar, c->partial);
+    HIPCHK(c, hipGetLastError());
+    double s;
+    int rc = sum_partials(c, &s);
+    if (rc) return rc;
+    c->J = 0.5 * s * c->dx2 / c->cbar;
+    return SLBM_OK;
+}
+
+int do_primal(slbm_ctx* c, slbm_solve_info* info)
+{
+    auto w0 = std::chrono::steady_clock::now();
+    int64_t t;
+    double res;
+    bool conv;
+    bool use_tol = c->tol > 0.0;
+    double dms = 0.0;
+    int rc = run_loop(c, false, c->prim_cur, c->max_steps, use_tol, &t, &res, &conv, &dms);
+    if (rc) return rc;
+    int X = (c->prim_cur + (int)(t & 1)) & 1;  // buffer holding f^C(t-1)
+    if ((rc = finalize_primal(c, X))) return rc;
+    c->prim_cur = X ^ 1;  // current state: f^S(t+1)
+    c->prim_done = true;
+    c->adj_done = false;
+    auto w1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->steps = t;
+        info->sweeps = t + 1;
+        info->residual = use_tol ? res : 0.0;
+        info->wall_s = std::chrono::duration<double>(w1 - w0).count();
+        info->device_ms = dms;
+        info->converged = conv ? 1 : 0;
+    }
+    return (use_tol && !conv) ? SLBM_NOT_CONVERGED : SLBM_OK;
+}
+
+int adjoint_prepare(slbm_ctx* c)
+{
+    int rc;
+    if ((rc = fill(c, c->abuf[0], 8 * c->N, 0.0))) return rc;
+    if ((rc = fill(c, c->abuf[1], 8 * c->N, 0.0))) return rc;
+    if ((rc = fill(c, c->snap, 2 * c->N, 0.0))) return rc;
+    if (c->masked && c->nb > 0) {
+        hipLaunchKernelGGL(k_boundary_jacobian, dim3((c->nb + 63) / 64), dim3(64), 0, c->stream, c->bnodes, c->nb,
+                           c->efield_on ? c->Efield : (const double*)nullptr, c->E_cur, c->nu, c->bjac);
+        HIPCHK(c, hipGetLastError());
+    }
+    c->adj_cur = 0;
+    return SLBM_OK;
+}
+
+int do_adjoint(slbm_ctx* c, slbm_solve_info* info)
+{
+    if (!c->prim_done) return fail(c, SLBM_ESTATE, "adjoint_solve needs a completed primal_solve");
+    auto w0 = std::chrono::steady_clock::now();
+    int rc = adjoint_prepare(c);
+    if (rc) return rc;
+    int64_t t;
+    double res;
+    bool conv;
+    bool use_tol = c->tol > 0.0;
+    double dms = 0.0;
+    if ((rc = run_loop(c, true, 0, c->max_steps, use_tol, &t, &res, &conv, &dms))) return rc;
+    int X = (int)(t & 1);  // buffer holding phi^C(t)
+    bool wantE = c->kind == SLBM_CTRL_E_NODAL || c->kind == SLBM_CTRL_E_SCALAR_SQ;
+    double scale = c->dx2 / c->cbar;
+    if (c->masked)
+        hipLaunchKernelGGL(k_adjoint_finalize<true>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->abuf[X],
+                           c->abuf[X ^ 1], c->code, c->bnodes, c->fbar, c->r, c->g,
+                           c->efield_on ? c->Efield : (const double*)nullptr, c->E_cur, c->nu, wantE ? 1 : 0,
+                           c->nx, c->ny, c->N, c->inv_nx, scale, c->dx2, c->dJdF, c->dJdE, c->adisp);
+    else
+        hipLaunchKernelGGL(k_adjoint_finalize<false>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->abuf[X],
+                           c->abuf[X ^ 1], c->code, c->bnodes, c->fbar, c->r, c->g,
+                           c->efield_on ? c->Efield : (const double*)nullptr, c->E_cur, c->nu, wantE ? 1 : 0,
+                           c->nx, c->ny, c->N, c->inv_nx, scale, c->dx2, c->dJdF, c->dJdE, c->adisp);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->adj_cur = X ^ 1;
+    c->adj_done = true;
+    auto w1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->steps = t;
+        info->sweeps = t + 1;
+        info->residual = use_tol ? res : 0.0;
+        info->wall_s = std::chrono::duration<double>(w1 - w0).count();
+        info->device_ms = dms;
+        info->converged = conv ? 1 : 0;
+    }
+    return (use_tol && !conv) ? SLBM_NOT_CONVERGED : SLBM_OK;
+}
+
+// Gradient per control kind from the local pieces dJdF / dJdE.
+int assemble_grad(slbm_ctx* c, double* grad, int ptr_kind)
+{
+    int rc;
+    switch (c->kind) {
+        case SLBM_CTRL_FORCE_MODES: {
+            std::vector<double> h(c->nmodes);
+            for (int m = 0; m < c->nmodes; ++m)
+                if ((rc = dot(c, c->dJdF, c->modes + (int64_t)m * 2 * c->N, 2 * c->N, &h[m]))) return rc;
+            if (ptr_kind == SLBM_PTR_DEVICE) {
+                HIPCHK(c, hipMemcpyAsync(grad, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
+                                         c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+            } else {
+                std::memcpy(grad, h.data(), h.size() * sizeof(double));
+            }
+            return SLBM_OK;
+        }
+        case SLBM_CTRL_FORCE_NODAL: {
+            if (c->project) {
+                double m[2];
+                for (int k = 0; k < 2; ++k) {
+                    if ((rc = dot(c, c->dJdF + k * c->N, nullptr, c->N, &m[k]))) return rc;
+                    m[k] /= (double)c->N;
+                }
+                HIPCHK(c, hipMemcpyAsync(c->work, m, 2 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->dJdF,
+                                   (const double*)c->work, (const int32_t*)nullptr, c->N, 1.0, c->dJdF);
+                HIPCHK(c, hipGetLastError());
+            }
+            return copy_out(c, grad, c->dJdF, 2 * c->N * sizeof(double), ptr_kind);
+        }
+        case SLBM_CTRL_E_NODAL:
+            return copy_out(c, grad, c->dJdE, c->N * sizeof(double), ptr_kind);
+        default: {
+            double s;
+            if ((rc = dot(c, c->dJdE, nullptr, c->N, &s))) return rc;
+            double gsc = s * 2.0 * c->alpha_sq;
+            if (ptr_kind == SLBM_PTR_DEVICE) {
+                HIPCHK(c, hipMemcpyAsync(grad, &gsc, sizeof(double), hipMemcpyHostToDevice, c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+            } else {
+                grad[0] = gsc;
+            }
+            return SLBM_OK;
+        }
+    }
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+
+extern "C" {
+
+int solid_lbm_init(const slbm_problem* p, slbm_ctx** out)
+{
+    if (!out) return fail(nullptr, SLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(nullptr, SLBM_EINVAL, "problem is NULL");
+    if (p->nx < 3 || p->ny < 3) return fail(nullptr, SLBM_EINVAL, "nx, ny must be >= 3");
+    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(nullptr, SLBM_EINVAL, "grid too large");
+    if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(nullptr, SLBM_EINVAL, "dx must be > 0");
+    if (!(p->nu > -1.0 && p->nu < 1.0)) return fail(nullptr, SLBM_EINVAL, "nu must lie in (-1, 1)");
+    bool econtrol = p->control_kind == SLBM_CTRL_E_NODAL || p->control_kind == SLBM_CTRL_E_SCALAR_SQ;
+    if (p->control_kind < 0 || p->control_kind > 3) return fail(nullptr, SLBM_EINVAL, "unknown control_kind");
+    if (!econtrol && (!(p->E > 0.0) || !std::isfinite(p->E))) return fail(nullptr, SLBM_EINVAL, "E must be > 0");
+    if (p->domain != SLBM_PERIODIC && p->domain != SLBM_MASKED) return fail(nullptr, SLBM_EINVAL, "unknown domain");
+    if (!p->target) return fail(nullptr, SLBM_EINVAL, "target is NULL");
+    if (p->max_steps < 1) return fail(nullptr, SLBM_EINVAL, "max_steps must be >= 1");
+    if (p->check_interval < 0) return fail(nullptr, SLBM_EINVAL, "check_interval must be >= 0");
+    if (p->control_kind == SLBM_CTRL_FORCE_MODES && (p->n_modes < 1 || p->n_modes > 64 || !p->force_modes))
+        return fail(nullptr, SLBM_EINVAL, "FORCE_MODES needs 1..64 force_modes");
+    bool masked = p->domain == SLBM_MASKED;
+    if (masked && (!p->node_mask || !p->link_bc || !p->link_wall))
+        return fail(nullptr, SLBM_EINVAL, "MASKED needs node_mask, link_bc and link_wall");
+
+    const int nx = p->nx, ny = p->ny;
+    const int64_t N = (int64_t)nx * ny;
+    if (!finite_all(p->target, 2 * N)) return fail(nullptr, SLBM_ENONFINITE, "target has non-finite entries");
+    if (p->fixed_force && !finite_all(p->fixed_force, 2 * N))
+        return fail(nullptr, SLBM_ENONFINITE, "fixed_force has non-finite entries");
+    if (p->force_modes && p->control_kind == SLBM_CTRL_FORCE_MODES &&
+        !finite_all(p->force_modes, (int64_t)p->n_modes * 2 * N))
+        return fail(nullptr, SLBM_ENONFINITE, "force_modes has non-finite entries");
+
+    // plate: node codes and boundary records
+    std::vector<int32_t> code(N, 0);
+    std::vector<BNode> bn;
+    bool any_neumann = false;
+    if (masked) {
+        for (int64_t n = 0; n < N; ++n) code[n] = p->node_mask[n] ? 0 : -1;
+        for (int ix = 0; ix < nx; ++ix)
+            if (code[ix] >= 0 || code[(int64_t)(ny - 1) * nx + ix] >= 0)
+                return fail(nullptr, SLBM_EINVAL, "a domain node lies on the box edge");
+        for (int iy = 0; iy < ny; ++iy)
+            if (code[(int64_t)iy * nx] >= 0 || code[(int64_t)iy * nx + nx - 1] >= 0)
+                return fail(nullptr, SLBM_EINVAL, "a domain node lies on the box edge");
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix) {
+                int64_t n = (int64_t)iy * nx + ix;
+                if (code[n] < 0) continue;
+                BNode b;
+                std::memset(&b, 0, sizeof(b));
+                b.cell = (int32_t)n;
+                for (int q = 0; q < 8; ++q) {
+                    int64_t m = (int64_t)(iy - cy(q)) * nx + (ix - cx(q));
+                    bool outside = code[m] < 0;
+                    uint8_t kind = p->link_bc[(int64_t)q * N + n];
+                    if (outside != (kind != 0))
+                        return fail(nullptr, SLBM_EINVAL, "link_bc must be non-zero exactly on cut links");
+                    if (!outside) continue;
+                    if (kind != SLBM_LINK_DIRICHLET && kind != SLBM_LINK_NEUMANN)
+                        return fail(nullptr, SLBM_EINVAL, "unknown link kind");
+                    b.cut |= 1u << q;
+                    if (kind == SLBM_LINK_DIRICHLET) b.dirichlet |= 1u << q;
+                    else any_neumann = true;
+                    for (int k = 0; k < 2; ++k) {
+                        b.wall[q][k] = p->link_wall[(int64_t)(k * 8 + q) * N + n];
+                        b.nrm[q][k] = p->link_normal ? p->link_normal[(int64_t)(k * 8 + q) * N + n] : 0.0;
+                        if (!std::isfinite(b.wall[q][k]) || !std::isfinite(b.nrm[q][k]))
+                            return fail(nullptr, SLBM_ENONFINITE, "non-finite wall data");
+                    }
+                }
+                if (b.cut) {
+                    code[n] = (int32_t)bn.size() + 1;
+                    bn.push_back(b);
+                }
+            }
+        if (any_neumann && !p->link_normal) return fail(nullptr, SLBM_EINVAL, "Neumann links need link_normal");
+    }
+
+    slbm_ctx* c = new slbm_ctx();
+    c->nx = nx;
+    c->ny = ny;
+    c->N = N;
+    c->dx = p->dx;
+    c->dx2 = p->dx * p->dx;
+    c->E = p->E;
+    c->nu = p->nu;
+    c->tol = p->tol;
+    c->inv_nx = 1.0 / nx;
+    c->max_steps = p->max_steps;
+    c->K = p->check_interval > 0 ? p->check_interval
+                                 : 2 * (int64_t)std::ceil(0.005 / (c->dx2) - 1e-9);
+    if (c->K < 1) c->K = 1;
+    c->kind = p->control_kind;
+    c->nmodes = p->n_modes;
+    c->project = (p->control_kind == SLBM_CTRL_FORCE_NODAL && !masked && p->zero_mean_projection) ? 1 : 0;
+    c->normalize = p->normalize_objective ? 1 : 0;
+    c->masked = masked;
+    c->nb = (int)bn.size();
+    c->stream = (hipStream_t)p->stream;
+    c->E_cur = p->E;
+    c->nblk = (N + kBlock - 1) / kBlock;
+    c->pcap = (2 * N + kBlock - 1) / kBlock + 2;
+
+    // Cbar (eq. node_J) on the host, over the observation set
+    double cb = 0.0;
+    for (int64_t n = 0; n < N; ++n) {
+        bool in = (!masked || code[n] >= 0) && (!p->obs_mask || p->obs_mask[n]);
+        if (in) cb += p->target[n] * p->target[n] + p->target[N + n] * p->target[N + n];
+    }
+    cb *= c->dx2;
+    if (c->normalize) {
+        if (!(cb > 0.0)) {
+            delete c;
+            return fail(nullptr, SLBM_EINVAL, "normalize_objective needs a non-zero target");
+        }
+        c->cbar = cb;
+    } else {
+        c->cbar = 1.0;
+    }
+    if (!econtrol && masked && !gamma_ok(p->E, p->nu)) {
+        delete c;
+        return fail(nullptr, SLBM_EINVAL, "tau_s = tau_f: the boundary coefficient gamma is undefined");
+    }
+
+    int rc = SLBM_OK;
+#define A(ptr, bytes)                                 \
+    do {                                              \
+        if (!rc) {                                    \
+            void* q_ = nullptr;                       \
+            rc = dalloc(c, &q_, (bytes));             \
+            *(ptr) = (decltype(*(ptr)))q_;            \
+        }                                             \
+    } while (0)
+    const size_t P8 = 8 * N * sizeof(double), P2 = 2 * N * sizeof(double), P1 = N * sizeof(double);
+    A(&c->fbuf[0], P8);
+    A(&c->fbuf[1], P8);
+    A(&c->abuf[0], P8);
+    A(&c->abuf[1], P8);
+    A(&c->fbar, P8);
+    A(&c->g, P2);
+    A(&c->target, P2);
+    A(&c->snap, P2);
+    A(&c->dbar, P2);
+    A(&c->r, P2);
+    A(&c->dJdF, P2);
+    A(&c->adisp, P2);
+    A(&c->work, P8 > 1024 ? P8 : 1024);
+    A(&c->dJdE, P1);
+    A(&c->Efield, P1);
+    A(&c->fixedF, P2);
+    A(&c->partial, (size_t)c->pcap * 2 * sizeof(double));
+    A(&c->scal, 64);
+    A(&c->ctrl, (size_t)std::max<int64_t>(2 * N, 64) * sizeof(double));
+    A(&c->status, sizeof(Status));
+    if (c->kind == SLBM_CTRL_FORCE_MODES) A(&c->modes, (size_t)c->nmodes * P2);
+    if (masked) {
+        A(&c->code, N * sizeof(int32_t));
+        A(&c->bnodes, std::max<size_t>(1, bn.size()) * sizeof(BNode));
+        A(&c->bjac, std::max<size_t>(1, bn.size()) * 128 * sizeof(double));
+    }
+    if (p->obs_mask) A(&c->obs, N);
+#undef A
+    if (rc) {
+        solid_lbm_destroy(c);
+        return fail(nullptr, rc, "device allocation failed");
+    }
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (rc) return;
+        hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = SLBM_EHIP;
+    };
+    up(c->target, p->target, P2);
+    if (p->fixed_force) {
+        std::vector<double> gf(2 * N);
+        for (int64_t i = 0; i < 2 * N; ++i) {
+            int64_t n = i % N;
+            bool in = !masked || code[n] >= 0;
+            gf[i] = in ? c->dx2 * p->fixed_force[i] : 0.0;
+        }
+        up(c->fixedF, gf.data(), P2);
+    } else if (!rc) {
+        if (hipMemset(c->fixedF, 0, P2) != hipSuccess) rc = SLBM_EHIP;
+    }
+    if (c->kind == SLBM_CTRL_FORCE_MODES) up(c->modes, p->force_modes, (size_t)c->nmodes * P2);
+    if (masked) {
+        up(c->code, code.data(), N * sizeof(int32_t));
+        if (!bn.empty()) up(c->bnodes, bn.data(), bn.size() * sizeof(BNode));
+    }
+    if (p->obs_mask) up(c->obs, p->obs_mask, N);
+    if (!rc && hipMemset(c->g, 0, P2) != hipSuccess) rc = SLBM_EHIP;
+    if (!rc && hipHostMalloc((void**)&c->h_status, 2 * sizeof(Status), hipHostMallocDefault) != hipSuccess)
+        rc = SLBM_EHIP;
+    if (!rc && (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess ||
+                hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess))
+        rc = SLBM_EHIP;
+    if (rc) {
+        solid_lbm_destroy(c);
+        return fail(nullptr, rc, "upload failed");
+    }
+    *out = c;
+    return SLBM_OK;
+}
+
+int solid_lbm_set_control(slbm_ctx* c, const double* control, const double* init_disp, int32_t ptr_kind)
+{
+    if (!c) return SLBM_EINVAL;
+    int rc = apply_control(c, control, ptr_kind);
+    if (rc) return rc;
+    return reset_primal(c, init_disp, ptr_kind);
+}
+
+int primal_solve(slbm_ctx* c, const double* control, const double* init_disp, int32_t ptr_kind,
+                 slbm_solve_info* info)
+{
+    if (!c) return SLBM_EINVAL;
+    int rc = solid_lbm_set_control(c, control, init_disp, ptr_kind);
+    if (rc) return rc;
+    return do_primal(c, info);
+}
+
+int adjoint_solve(slbm_ctx* c, slbm_solve_info* info)
+{
+    if (!c) return SLBM_EINVAL;
+    return do_adjoint(c, info);
+}
+
+int objective_and_grad(slbm_ctx* c, const double* control, double* J, double* grad, int32_t ptr_kind,
+                       slbm_solve_info* pinfo, slbm_solve_info* ainfo)
+{
+    if (!c) return SLBM_EINVAL;
+    if (!J) return fail(c, SLBM_EINVAL, "J is NULL");
+    int rc = primal_solve(c, control, nullptr, ptr_kind, pinfo);
+    if (rc < 0) return rc;
+    int warn = rc;
+    *J = c->J;
+    if (!grad) return warn;
+    rc = do_adjoint(c, ainfo);
+    if (rc < 0) return rc;
+    if (rc > 0) warn = rc;
+    rc = assemble_grad(c, grad, ptr_kind);
+    if (rc < 0) return rc;
+    return warn;
+}
+
+int solid_lbm_run_steps(slbm_ctx* c, int64_t n)
+{
+    if (!c) return SLBM_EINVAL;
+    if (!c->prim_valid) return fail(c, SLBM_ESTATE, "no primal state: call solid_lbm_set_control first");
+    if (n < 0) return fail(c, SLBM_EINVAL, "n must be >= 0");
+    if (n == 0) return SLBM_OK;
+    int64_t t;
+    double res;
+    bool conv;
+    int rc = run_loop(c, false, c->prim_cur, n - 1, false, &t, &res, &conv);
+    if (rc) return rc;
+    c->prim_cur = (c->prim_cur + (int)(n & 1)) & 1;
+    c->prim_done = false;
+    return SLBM_OK;
+}
+
+int solid_lbm_run_adjoint_steps(slbm_ctx* c, int64_t n)
+{
+    if (!c) return SLBM_EINVAL;
+    if (!c->prim_done) return fail(c, SLBM_ESTATE, "adjoint steps need a completed primal_solve");
+    if (n < 0) return fail(c, SLBM_EINVAL, "n must be >= 0");
+    int rc = adjoint_prepare(c);
+    if (rc) return rc;
+    if (n == 0) return SLBM_OK;
+    int64_t t;
+    double res;
+    bool conv;
+    if ((rc = run_loop(c, true, 0, n - 1, false, &t, &res, &conv))) return rc;
+    c->adj_cur = (int)(n & 1);
+    return SLBM_OK;
+}
+
+int solid_lbm_get_field(slbm_ctx* c, int32_t which, double* out, int32_t ptr_kind)
+{
+    if (!c) return SLBM_EINVAL;
+    if (!out) return fail(c, SLBM_EINVAL, "out is NULL");
+    const int64_t N = c->N;
+    switch (which) {
+        case SLBM_FIELD_DISP:
+        case SLBM_FIELD_RESIDUAL:
+        case SLBM_FIELD_STRESS:
+            if (!c->prim_done) return fail(c, SLBM_ESTATE, "no completed primal_solve");
+            if (which == SLBM_FIELD_DISP) return copy_out(c, out, c->dbar, 2 * N * sizeof(double), ptr_kind);
+            if (which == SLBM_FIELD_RESIDUAL) return copy_out(c, out, c->r, 2 * N * sizeof(double), ptr_kind);
+            hipLaunchKernelGGL(k_stress, dim3(grid_of(N)), dim3(kBlock), 0, c->stream, c->fbar, c->g,
+                               c->masked ? c->code : (const int32_t*)nullptr, c->bnodes,
+                               c->efield_on ? c->Efield : (const double*)nullptr, c->E_cur, c->nu, N, c->work);
+            HIPCHK(c, hipGetLastError());
+            return copy_out(c, out, c->work, 3 * N * sizeof(double), ptr_kind);
+        case SLBM_FIELD_ADJ_DISP:
+            if (!c->adj_done) return fail(c, SLBM_ESTATE, "no completed adjoint_solve");
+            return copy_out(c, out, c->adisp, 2 * N * sizeof(double), ptr_kind);
+        case SLBM_FIELD_POPS:
+        case SLBM_FIELD_CUR_DISP: {
+            if (!c->prim_valid) return fail(c, SLBM_ESTATE, "no primal state");
+            double* pops = which == SLBM_FIELD_POPS ? c->work : nullptr;
+            double* disp = which == SLBM_FIELD_CUR_DISP ? c->work : nullptr;
+            if (c->masked)
+                hipLaunchKernelGGL(k_gather_state<true>, dim3(grid_of(N)), dim3(kBlock), 0, c->stream,
+                                   c->fbuf[c->prim_cur], c->g, c->code, c->nx, c->ny, N, c->inv_nx, pops, disp);
+            else
+                hipLaunchKernelGGL(k_gather_state<false>, dim3(grid_of(N)), dim3(kBlock), 0, c->stream,
+                                   c->fbuf[c->prim_cur], c->g, c->code, c->nx, c->ny, N, c->inv_nx, pops, disp);
+            HIPCHK(c, hipGetLastError());
+            if (pops) return copy_out(c, out, pops, 8 * N * sizeof(double), ptr_kind);
+            return copy_out(c, out, disp, 2 * N * sizeof(double), ptr_kind);
+        }
+        case SLBM_FIELD_ADJ_POPS:
+            return copy_out(c, out, c->abuf[c->adj_cur], 8 * N * sizeof(double), ptr_kind);
+        default:
+            return fail(c, SLBM_EINVAL, "unknown field");
+    }
+}
+
+int solid_lbm_time_sweeps(slbm_ctx* c, int32_t adjoint, int64_t n, double* ms)
+{
+    if (!c || !ms) return SLBM_EINVAL;
+    if (n < 1) return fail(c, SLBM_EINVAL, "n must be >= 1");
+    if (adjoint && !c->prim_done) return fail(c, SLBM_ESTATE, "adjoint sweeps need a completed primal_solve");
+    if (!adjoint && !c->prim_valid) return fail(c, SLBM_ESTATE, "no primal state");
+    if (adjoint && !c->adj_done) {
+        int rc = adjoint_prepare(c);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(1), 0, c->stream, c->status);
+    SweepArgs a = base_args(c);
+    a.g = adjoint ? c->r : c->g;
+    a.scale = c->dx2 / c->cbar;
+    double** bufs = adjoint ? c->abuf : c->fbuf;
+    int cur = adjoint ? c->adj_cur : c->prim_cur;
+    HIPCHK(c, hipEventRecord(c->t0, c->stream));
+    for (int64_t s = 0; s < n; ++s) {
+        a.src = bufs[cur];
+        a.dst = bufs[cur ^ 1];
+        launch_sweep(c, adjoint != 0, a, false);
+        cur ^= 1;
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(c->t1, c->stream));
+    HIPCHK(c, hipEventSynchronize(c->t1));
+    float f = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&f, c->t0, c->t1));
+    *ms = f;
+    if (adjoint) {
+        c->adj_cur = cur;
+    } else {
+        c->prim_cur = cur;
+        c->prim_done = false;
+    }
+    return SLBM_OK;
+}
+
+const char* solid_lbm_last_error(const slbm_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+void solid_lbm_destroy(slbm_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    for (hipEvent_t e : {c->ev[0], c->ev[1], c->t0, c->t1})
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,531 @@
+// HIP kernels of the solid lattice-Boltzmann primal and adjoint sweeps (gfx950).
+//
+// Data layout (HBM): populations in two SoA buffers of 8 planes of N = nx*ny
+// doubles each, x fastest.  The primal buffer holds post-collision populations
+// f^C(t-1) indexed by their source node, so one sweep *pulls* f^S_q(x, t) =
+// f^C_q(x - c_q, t-1) (eq. local_stream), collides (eq. local_collide) and
+// writes f^C(x, t) at x: every plane is one shifted, contiguous stream, 64 B
+// read + 64 B written per node plus the 16 B forcing (144 B/node/step).
+// Plate nodes outside the domain are never written by their own thread; the
+// slot (x - c_q, q) of a cut link instead receives the closure value computed
+// by the boundary node x, so the pull stays branch-free.
+// The adjoint buffer holds phi^C(t) indexed like f^S; one adjoint sweep pulls
+// phi^S_q(x) = phi^C_q(x + c_q) (eq. adjoint_streaming, S^T = S^{-1}) and applies
+// the transposed collision minus the objective source (eq. adjoint_collision).
+// Slots of nodes outside the domain stay zero, which makes the transpose of the
+// closures' dropped outgoing populations exact.
+#pragma once
+#include "slbm_device.h"
+
+namespace slbm {
+
+constexpr int kBlock = 256;
+
+// Convergence status shared by the sweeps of one solve (device memory).
+struct Status {
+    int32_t stop;      // set once the residual test passed: later sweeps return at once
+    int32_t pad;
+    int64_t t_conv;    // step index of the passing test
+    int64_t t_last;    // step index of the last test
+    double res;        // last residual
+};
+
+struct SweepArgs {
+    const double* __restrict__ src;   // 8 planes
+    double* __restrict__ dst;         // 8 planes
+    const double* __restrict__ g;     // 2 planes forcing (primal) or r (adjoint)
+    const double* __restrict__ E;     // 1 plane Young's modulus (E field) or null
+    const int32_t* __restrict__ code; // masked: -1 outside, 0 bulk, k+1 boundary record k
+    const BNode* __restrict__ bnodes;
+    const double* __restrict__ bjac;  // adjoint: 128 doubles per boundary node
+    double* __restrict__ snap;        // check sweeps: 2 planes, d(t - K)
+    double* __restrict__ partial;     // check sweeps: 2 doubles per block
+    const Status* __restrict__ status;
+    int32_t nx, ny;
+    int64_t N;
+    double k11, ks, kd;               // uniform material relaxation keep-factors
+    double E0, nu;                    // uniform E (boundary records) and Poisson ratio
+    double scale;                     // adjoint: s = dx^2 / Cbar
+};
+
+__device__ __forceinline__ void block_sum2(double a, double b, double* out)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    __shared__ double sa[kBlock / 64], sb[kBlock / 64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { sa[w] = a; sb[w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0, y = 0.0;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) { x += sa[i]; y += sb[i]; }
+        out[0] = x;
+        out[1] = y;
+    }
+}
+
+// Row index of a linear cell index without an integer division.
+__device__ __forceinline__ int row_of(int64_t n, int nx, double inv_nx)
+{
+    int iy = (int)((double)n * inv_nx);
+    int64_t base = (int64_t)iy * nx;
+    if (base > n) { --iy; base -= nx; }
+    if (base + nx <= n) ++iy;
+    return iy;
+}
+
+// Source index of direction q for a pull from x - s*c_q (s = +1 primal, -1 adjoint).
+// ix/iy wrapped periodically (plates never touch the box edge).
+__device__ __forceinline__ void neighbours(int ix, int iy, int nx, int ny, int64_t idx[8], int sgn)
+{
+    int xm = ix == 0 ? nx - 1 : ix - 1, xp = ix == nx - 1 ? 0 : ix + 1;
+    int ym = iy == 0 ? ny - 1 : iy - 1, yp = iy == ny - 1 ? 0 : iy + 1;
+    int64_t rY = (int64_t)iy * nx, rM = (int64_t)ym * nx, rP = (int64_t)yp * nx;
+    if (sgn > 0) {  // x - c_q
+        idx[0] = rY + xm; idx[1] = rM + ix; idx[2] = rY + xp; idx[3] = rP + ix;
+        idx[4] = rM + xm; idx[5] = rM + xp; idx[6] = rP + xp; idx[7] = rP + xm;
+    } else {        // x + c_q
+        idx[0] = rY + xp; idx[1] = rP + ix; idx[2] = rY + xm; idx[3] = rM + ix;
+        idx[4] = rP + xp; idx[5] = rP + xm; idx[6] = rM + xm; idx[7] = rM + xp;
+    }
+}
+
+// ---------------------------------------------------------------- primal sweep
+template <bool MASKED, bool EFIELD, bool CHECK>
+__global__ __launch_bounds__(kBlock) void k_primal(SweepArgs a, double inv_nx)
+{
+    if (a.status->stop) return;
+    int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double num = 0.0, den = 0.0;
+    if (n < a.N) {
+        int code = MASKED ? a.code[n] : 0;
+        if (code >= 0) {
+            int iy = row_of(n, a.nx, inv_nx);
+            int ix = (int)(n - (int64_t)iy * a.nx);
+            int64_t idx[8];
+            neighbours(ix, iy, a.nx, a.ny, idx, +1);
+            const int64_t N = a.N;
+            double f[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) f[q] = a.src[q * N + idx[q]];
+            double gx = a.g[n], gy = a.g[N + n];
+            double d0, d1;
+            if (!MASKED || code == 0) {
+                double k11 = a.k11, ks = a.ks, kd = a.kd;
+                if (EFIELD) {
+                    Relax<double> r = relax_from_E<double>(a.E[n], a.nu, false);
+                    k11 = r.k11; ks = r.ks; kd = r.kd;
+                }
+                collide_bulk(f, gx, gy, k11, ks, kd, d0, d1);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) a.dst[q * N + n] = f[q];
+            } else {
+                const BNode* bn = a.bnodes + (code - 1);
+                Relax<double> r = relax_from_E<double>(EFIELD ? a.E[n] : a.E0, a.nu, true);
+                double gg[2] = {gx, gy}, fC[8], h[8], mb[5];
+                node_map<double>(f, gg, r, bn, true, fC, h, mb);
+                d0 = mb[0];
+                d1 = mb[1];
+                int64_t back[8];
+                neighbours(ix, iy, a.nx, a.ny, back, +1);
+                uint32_t cut = bn->cut;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    a.dst[q * N + n] = fC[q];
+                    if ((cut >> q) & 1u) a.dst[q * N + back[q]] = h[q];
+                }
+            }
+            if (CHECK) {
+                double s0 = a.snap[n], s1 = a.snap[N + n];
+                num = (d0 - s0) * (d0 - s0) + (d1 - s1) * (d1 - s1);
+                den = d0 * d0 + d1 * d1;
+                a.snap[n] = d0;
+                a.snap[N + n] = d1;
+            }
+        }
+    }
+    if (CHECK) block_sum2(num, den, a.partial + 2 * (int64_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------- adjoint sweep
+template <bool MASKED, bool EFIELD, bool CHECK>
+__global__ __launch_bounds__(kBlock) void k_adjoint(SweepArgs a, double inv_nx)
+{
+    if (a.status->stop) return;
+    int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double num = 0.0, den = 0.0;
+    if (n < a.N) {
+        int code = MASKED ? a.code[n] : 0;
+        if (code >= 0) {
+            int iy = row_of(n, a.nx, inv_nx);
+            int ix = (int)(n - (int64_t)iy * a.nx);
+            int64_t idx[8];
+            neighbours(ix, iy, a.nx, a.ny, idx, -1);
+            const int64_t N = a.N;
+            double p[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) p[q] = a.src[q * N + idx[q]];
+            double srx = a.scale * a.g[n], sry = a.scale * a.g[N + n];
+            if (CHECK) {
+                double d0 = (p[0] - p[2]) + (p[4] - p[5]) + (p[7] - p[6]);
+                double d1 = (p[1] - p[3]) + (p[4] + p[5]) - (p[6] + p[7]);
+                double s0 = a.snap[n], s1 = a.snap[N + n];
+                num = (d0 - s0) * (d0 - s0) + (d1 - s1) * (d1 - s1);
+                den = d0 * d0 + d1 * d1;
+                a.snap[n] = d0;
+                a.snap[N + n] = d1;
+            }
+            if (!MASKED || code == 0) {
+                double k11 = a.k11, ks = a.ks, kd = a.kd;
+                if (EFIELD) {
+                    Relax<double> r = relax_from_E<double>(a.E[n], a.nu, false);
+                    k11 = r.k11; ks = r.ks; kd = r.kd;
+                }
+                adj_collide_bulk(p, srx, sry, k11, ks, kd);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) a.dst[q * N + n] = p[q];
+            } else {
+                // transposed extended map: out_p = sum_r jac[r][p] ext_r - src_p,
+                // ext = (routed regular slots, own slots of the cut links)
+                const BNode* bn = a.bnodes + (code - 1);
+                const double* J = a.bjac + (int64_t)(code - 1) * 128;
+                double ext[16];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    ext[q] = p[q];
+                    ext[8 + q] = ((bn->cut >> q) & 1u) ? a.src[q * N + n] : 0.0;
+                }
+                for (int pp = 0; pp < 8; ++pp) {
+                    double s = 0.0;
+                    for (int r = 0; r < 16; ++r) s += J[r * 8 + pp] * ext[r];
+                    a.dst[pp * N + n] = s - (srx * cx(pp) + sry * cy(pp));
+                }
+            }
+        }
+    }
+    if (CHECK) block_sum2(num, den, a.partial + 2 * (int64_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------- reductions
+// Sums nblk pairs of partials in a fixed order (deterministic), tests r < tol.
+__global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ partial, int64_t nblk,
+                                                    Status* st, double tol, int64_t t)
+{
+    if (st->stop) return;
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < nblk; i += kBlock) {
+        a += partial[2 * i];
+        b += partial[2 * i + 1];
+    }
+    __shared__ double out[2];
+    block_sum2(a, b, out);
+    if (threadIdx.x == 0) {
+        double num = out[0], den = out[1];
+        double r = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+        st->res = r;
+        st->t_last = t;
+        if (r < tol) {
+            st->stop = 1;
+            st->t_conv = t;
+        }
+    }
+}
+
+__global__ void k_status_reset(Status* st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->stop = 0;
+        st->pad = 0;
+        st->t_conv = -1;
+        st->t_last = -1;
+        st->res = INFINITY;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double* __restrict__ a, int64_t n, double v)
+{
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// partial[b] = sum over the block of a[i] * w[i] (w may be null: plain sum), ncomp planes of N
+__global__ __launch_bounds__(kBlock) void k_dot_partial(const double* __restrict__ a,
+                                                       const double* __restrict__ w, int64_t n,
+                                                       double* __restrict__ partial)
+{
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double s = 0.0;
+    if (i < n) s = w ? a[i] * w[i] : a[i];
+    block_sum2(s, 0.0, partial + 2 * (int64_t)blockIdx.x);
+}
+
+// out[0] = sum of partial[2 i] (fixed order)
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partial, int64_t nblk,
+                                                        double* __restrict__ out)
+{
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < nblk; i += kBlock) a += partial[2 * i];
+    __shared__ double o[2];
+    block_sum2(a, 0.0, o);
+    if (threadIdx.x == 0) out[0] = o[0];
+}
+
+// ---------------------------------------------------------------- control -> forcing
+// g = dx^2 sum_i alpha_i B_i
+__global__ __launch_bounds__(kBlock) void k_force_modes(const double* __restrict__ modes,
+                                                       const double* __restrict__ alpha, int k,
+                                                       int64_t n2, double dx2, double* __restrict__ g)
+{
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n2) return;
+    double s = 0.0;
+    for (int m = 0; m < k; ++m) s += alpha[m] * modes[m * n2 + i];
+    g[i] = dx2 * s;
+}
+
+// out[c*N+i] = scale * (a[c*N+i] - mean[c]) for masked-in nodes (mask null = all), else 0
+__global__ __launch_bounds__(kBlock) void k_axpb2(const double* __restrict__ a, const double* __restrict__ mean,
+                                                 const int32_t* __restrict__ code, int64_t N, double scale,
+                                                 double* __restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= 2 * N) return;
+    int64_t n = i % N;
+    int c = (int)(i / N);
+    bool in = code ? code[n] >= 0 : true;
+    double m = mean ? mean[c] : 0.0;
+    out[i] = in ? scale * (a[i] - m) : 0.0;
+}
+
+// ---------------------------------------------------------------- initial state
+// f^S(0) = populations whose moments are N (d0 - g/2) (equilibrium with bared
+// displacement d0; d0 = 0 gives the cold start f = 0), stored pulled-from so the
+// first sweep gathers it: buf[q][x - c_q] = f^S_q(x, 0).  snap = d(0).
+__global__ __launch_bounds__(kBlock) void k_init_state(double* __restrict__ buf, const double* __restrict__ d0,
+                                                      const double* __restrict__ g,
+                                                      const int32_t* __restrict__ code, int nx, int ny,
+                                                      int64_t N, double inv_nx, double* __restrict__ snap)
+{
+    int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= N) return;
+    if (code && code[n] < 0) {
+        snap[n] = 0.0;
+        snap[N + n] = 0.0;
+        return;
+    }
+    double gx = g[n], gy = g[N + n];
+    double ux = (d0 ? d0[n] : 0.0) - (d0 ? 0.5 * gx : 0.0);
+    double uy = (d0 ? d0[N + n] : 0.0) - (d0 ? 0.5 * gy : 0.0);
+    int iy = row_of(n, nx, inv_nx);
+    int ix = (int)(n - (int64_t)iy * nx);
+    int64_t idx[8];
+    neighbours(ix, iy, nx, ny, idx, +1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        double W = q < 4 ? 1.0 / 3.0 : 1.0 / 12.0;
+        buf[q * N + idx[q]] = W * (cx(q) * ux + cy(q) * uy);
+    }
+    snap[n] = ux + 0.5 * gx;
+    snap[N + n] = uy + 0.5 * gy;
+}
+
+// ---------------------------------------------------------------- finalize primal
+// From X = f^C(t-1) and Y = f^C(t): f^S(t), f^S(t+1) by pulls, the two-step
+// averages fbar, dbar, the residual r = dbar - d* on the observation set and
+// per-block sums of |r|^2.
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_primal_finalize(
+    const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ g,
+    const int32_t* __restrict__ code, const double* __restrict__ target, const uint8_t* __restrict__ obs,
+    int nx, int ny, int64_t N, double inv_nx, double* __restrict__ dbar, double* __restrict__ r,
+    double* __restrict__ fbar, double* __restrict__ partial)
+{
+    int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double s = 0.0;
+    if (n < N) {
+        bool in = MASKED ? code[n] >= 0 : true;
+        if (in) {
+            int iy = row_of(n, nx, inv_nx);
+            int ix = (int)(n - (int64_t)iy * nx);
+            int64_t idx[8];
+            neighbours(ix, iy, nx, ny, idx, +1);
+            double fa[8], fb[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                fa[q] = X[q * N + idx[q]];
+                fb[q] = Y[q * N + idx[q]];
+                fbar[q * N + n] = 0.5 * (fa[q] + fb[q]);
+            }
+            double gx = g[n], gy = g[N + n];
+            double a0 = (fa[0] - fa[2]) + (fa[4] - fa[5]) + (fa[7] - fa[6]) + 0.5 * gx;
+            double a1 = (fa[1] - fa[3]) + (fa[4] + fa[5]) - (fa[6] + fa[7]) + 0.5 * gy;
+            double b0 = (fb[0] - fb[2]) + (fb[4] - fb[5]) + (fb[7] - fb[6]) + 0.5 * gx;
+            double b1 = (fb[1] - fb[3]) + (fb[4] + fb[5]) - (fb[6] + fb[7]) + 0.5 * gy;
+            double d0 = 0.5 * (a0 + b0), d1 = 0.5 * (a1 + b1);
+            dbar[n] = d0;
+            dbar[N + n] = d1;
+            bool o = obs ? obs[n] != 0 : true;
+            double r0 = o ? d0 - target[n] : 0.0, r1 = o ? d1 - target[N + n] : 0.0;
+            r[n] = r0;
+            r[N + n] = r1;
+            s = r0 * r0 + r1 * r1;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) fbar[q * N + n] = 0.0;
+            dbar[n] = dbar[N + n] = 0.0;
+            r[n] = r[N + n] = 0.0;
+        }
+    }
+    block_sum2(s, 0.0, partial + 2 * (int64_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------- boundary Jacobians
+// jac[r][p] = d out_r / d f_p of the extended node map (fC rows 0..7, closure
+// rows 8..15) of every boundary node: the map is affine in f, so its linear
+// part (zero forcing, zero walls) applied to unit vectors is the Jacobian.
+__global__ __launch_bounds__(64) void k_boundary_jacobian(const BNode* __restrict__ bnodes, int nb,
+                                                         const double* __restrict__ E, double E0, double nu,
+                                                         double* __restrict__ jac)
+{
+    int b = blockIdx.x * 64 + threadIdx.x;
+    if (b >= nb) return;
+    const BNode* bn = bnodes + b;
+    Relax<double> r = relax_from_E<double>(E ? E[bn->cell] : E0, nu, true);
+    double* J = jac + (int64_t)b * 128;
+    for (int p = 0; p < 8; ++p) {
+        double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        e[p] = 1.0;
+        double g0[2] = {0.0, 0.0}, fC[8], h[8], mb[5];
+        node_map<double>(e, g0, r, bn, false, fC, h, mb);
+        for (int q = 0; q < 8; ++q) {
+            J[q * 8 + p] = fC[q];
+            J[(8 + q) * 8 + p] = h[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- finalize adjoint + gradient
+// From X = phi^C(t), Y = phi^C(t+1): averaged routed adjoint, then eq. optimality
+// locally:  dJ/dF = dx^2 (s r / 2 - (dC/dg)^T phi^S)   and, for E controls,
+//           dJ/dE = -(dC/dE)^T phi^S  (forward-mode dual number through the node map
+//           at the averaged primal state fbar).
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_adjoint_finalize(
+    const double* __restrict__ X, const double* __restrict__ Y, const int32_t* __restrict__ code,
+    const BNode* __restrict__ bnodes, const double* __restrict__ fbar, const double* __restrict__ r,
+    const double* __restrict__ g, const double* __restrict__ E, double E0, double nu, int want_E,
+    int nx, int ny, int64_t N, double inv_nx, double scale, double dx2, double* __restrict__ dJdF,
+    double* __restrict__ dJdE, double* __restrict__ adisp)
+{
+    int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= N) return;
+    int c = MASKED ? code[n] : 0;
+    if (c < 0) {
+        dJdF[n] = dJdF[N + n] = 0.0;
+        if (want_E) dJdE[n] = 0.0;
+        adisp[n] = adisp[N + n] = 0.0;
+        return;
+    }
+    int iy = row_of(n, nx, inv_nx);
+    int ix = (int)(n - (int64_t)iy * nx);
+    int64_t idx[8];
+    neighbours(ix, iy, nx, ny, idx, -1);
+    double ext[16];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ext[q] = 0.5 * (X[q * N + idx[q]] + Y[q * N + idx[q]]);
+    const BNode* bn = c > 0 ? bnodes + (c - 1) : nullptr;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        ext[8 + q] = (bn && ((bn->cut >> q) & 1u)) ? 0.5 * (X[q * N + n] + Y[q * N + n]) : 0.0;
+    adisp[n] = (ext[0] - ext[2]) + (ext[4] - ext[5]) + (ext[7] - ext[6]);
+    adisp[N + n] = (ext[1] - ext[3]) + (ext[4] + ext[5]) - (ext[6] + ext[7]);
+    double rx = r[n], ry = r[N + n];
+    double Eh = E ? E[n] : E0;
+    double Btx, Bty;
+    if (!bn) {
+        double psi[7];
+        adj_moments(ext, psi);
+        Btx = psi[0] + 0.5 * kTheta * psi[5];
+        Bty = psi[1] + 0.5 * kTheta * psi[6];
+    } else {
+        Relax<double> rl = relax_from_E<double>(Eh, nu, true);
+        double z[8] = {0, 0, 0, 0, 0, 0, 0, 0}, fC[8], h[8], mb[5];
+        double gx1[2] = {1.0, 0.0}, gy1[2] = {0.0, 1.0};
+        node_map<double>(z, gx1, rl, bn, false, fC, h, mb);
+        Btx = 0.0;
+        for (int q = 0; q < 8; ++q) Btx += ext[q] * fC[q] + ext[8 + q] * h[q];
+        node_map<double>(z, gy1, rl, bn, false, fC, h, mb);
+        Bty = 0.0;
+        for (int q = 0; q < 8; ++q) Bty += ext[q] * fC[q] + ext[8 + q] * h[q];
+    }
+    dJdF[n] = dx2 * (0.5 * scale * rx - Btx);
+    dJdF[N + n] = dx2 * (0.5 * scale * ry - Bty);
+    if (want_E) {
+        Dual f[8], gd[2], fC[8], h[8], mb[5];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) f[q] = Dual(fbar[q * N + n]);
+        gd[0] = Dual(g[n]);
+        gd[1] = Dual(g[N + n]);
+        Relax<Dual> rl = relax_from_E<Dual>(Dual(Eh, 1.0), nu, bn != nullptr);
+        node_map<Dual>(f, gd, rl, bn, true, fC, h, mb);
+        double s = 0.0;
+        for (int q = 0; q < 8; ++q) s += ext[q] * fC[q].d + (bn ? ext[8 + q] * h[q].d : 0.0);
+        dJdE[n] = -s;
+    }
+}
+
+// Current populations f^S of the primal state (pull from the buffer) and their
+// bared displacement; plain copies for nodes outside (zeros).
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_gather_state(const double* __restrict__ X,
+                                                        const double* __restrict__ g,
+                                                        const int32_t* __restrict__ code, int nx, int ny,
+                                                        int64_t N, double inv_nx, double* __restrict__ pops,
+                                                        double* __restrict__ disp)
+{
+    int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= N) return;
+    bool in = MASKED ? code[n] >= 0 : true;
+    int iy = row_of(n, nx, inv_nx);
+    int ix = (int)(n - (int64_t)iy * nx);
+    int64_t idx[8];
+    neighbours(ix, iy, nx, ny, idx, +1);
+    double f[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) f[q] = in ? X[q * N + idx[q]] : 0.0;
+    if (pops)
+        for (int q = 0; q < 8; ++q) pops[q * N + n] = f[q];
+    if (disp) {
+        disp[n] = in ? (f[0] - f[2]) + (f[4] - f[5]) + (f[7] - f[6]) + 0.5 * g[n] : 0.0;
+        disp[N + n] = in ? (f[1] - f[3]) + (f[4] + f[5]) - (f[6] + f[7]) + 0.5 * g[N + n] : 0.0;
+    }
+}
+
+// Bared stress (lattice units) of the averaged state fbar (eq. stress_from_moments).
+__global__ __launch_bounds__(kBlock) void k_stress(const double* __restrict__ fbar, const double* __restrict__ g,
+                                                  const int32_t* __restrict__ code,
+                                                  const BNode* __restrict__ bnodes,
+                                                  const double* __restrict__ E, double E0, double nu,
+                                                  int64_t N, double* __restrict__ out)
+{
+    int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= N) return;
+    int c = code ? code[n] : 0;
+    if (c < 0) {
+        out[n] = out[N + n] = out[2 * N + n] = 0.0;
+        return;
+    }
+    double f[8], gg[2] = {g[n], g[N + n]}, fC[8], h[8], mb[5];
+    for (int q = 0; q < 8; ++q) f[q] = fbar[q * N + n];
+    Relax<double> r = relax_from_E<double>(E ? E[n] : E0, nu, c > 0);
+    node_map<double>(f, gg, r, nullptr, false, fC, h, mb);
+    out[n] = -0.5 * (mb[3] + mb[4]);
+    out[N + n] = -0.5 * (mb[3] - mb[4]);
+    out[2 * N + n] = -mb[2];
+}
+
+}  // namespace slbm

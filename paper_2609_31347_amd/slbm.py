@@ -1,0 +1,240 @@
+"""Python binding of the HIP solid-LBM library (argument marshalling only).
+
+Every function has the name of the C entry point it calls (include/solid_lbm.h);
+all work runs in libslbm.so.  Arrays may be numpy arrays (host) or torch CUDA
+tensors (device pointers are passed through, no copies).  If the library has
+not been built the import of this module raises: there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslbm.so")
+
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ESTATE, ENONFINITE = 0, 1, -1, -2, -3, -4, -5
+PERIODIC, MASKED = 0, 1
+CTRL_FORCE_MODES, CTRL_FORCE_NODAL, CTRL_E_NODAL, CTRL_E_SCALAR_SQ = 0, 1, 2, 3
+PTR_HOST, PTR_DEVICE = 0, 1
+FIELD_DISP, FIELD_STRESS, FIELD_ADJ_DISP, FIELD_POPS, FIELD_ADJ_POPS, FIELD_RESIDUAL, FIELD_CUR_DISP = range(7)
+FIELD_COMPS = {FIELD_DISP: 2, FIELD_STRESS: 3, FIELD_ADJ_DISP: 2, FIELD_POPS: 8, FIELD_ADJ_POPS: 8,
+               FIELD_RESIDUAL: 2, FIELD_CUR_DISP: 2}
+EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_grad", "solid_lbm_set_control",
+           "solid_lbm_run_steps", "solid_lbm_run_adjoint_steps", "solid_lbm_get_field",
+           "solid_lbm_time_sweeps", "solid_lbm_last_error", "solid_lbm_destroy")
+
+
+class SlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"solid_lbm error {code}: {msg}")
+        self.code = code
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double),
+        ("E", ctypes.c_double), ("nu", ctypes.c_double), ("domain", ctypes.c_int32),
+        ("node_mask", ctypes.c_void_p), ("link_bc", ctypes.c_void_p), ("link_wall", ctypes.c_void_p),
+        ("link_normal", ctypes.c_void_p), ("fixed_force", ctypes.c_void_p), ("target", ctypes.c_void_p),
+        ("obs_mask", ctypes.c_void_p), ("control_kind", ctypes.c_int32), ("n_modes", ctypes.c_int32),
+        ("force_modes", ctypes.c_void_p), ("zero_mean_projection", ctypes.c_int32),
+        ("normalize_objective", ctypes.c_int32), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
+        ("check_interval", ctypes.c_int32), ("stream", ctypes.c_void_p),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("sweeps", ctypes.c_int64), ("residual", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("device_ms", ctypes.c_double), ("converged", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, pp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)
+    info = ctypes.POINTER(SolveInfo)
+    lib.solid_lbm_init.argtypes = [ctypes.POINTER(_Problem), pp]
+    lib.primal_solve.argtypes = [P, P, P, ctypes.c_int32, info]
+    lib.adjoint_solve.argtypes = [P, info]
+    lib.objective_and_grad.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, ctypes.c_int32, info, info]
+    lib.solid_lbm_set_control.argtypes = [P, P, P, ctypes.c_int32]
+    lib.solid_lbm_run_steps.argtypes = [P, ctypes.c_int64]
+    lib.solid_lbm_run_adjoint_steps.argtypes = [P, ctypes.c_int64]
+    lib.solid_lbm_get_field.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32]
+    lib.solid_lbm_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    lib.solid_lbm_last_error.argtypes = [P]
+    lib.solid_lbm_last_error.restype = ctypes.c_char_p
+    lib.solid_lbm_destroy.argtypes = [P]
+    lib.solid_lbm_destroy.restype = None
+    for f in EXPORTS[:-2]:
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+LIB = _load()
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _arg(a, keep, dtype=np.float64):
+    """(pointer, ptr_kind) of an array; host arrays are made contiguous and kept alive."""
+    if a is None:
+        return None, PTR_HOST
+    if _is_torch(a):
+        if a.is_cuda:
+            if not a.is_contiguous():
+                raise ValueError("device tensors must be contiguous")
+            return a.data_ptr(), PTR_DEVICE
+        a = a.numpy()
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    keep.append(arr)
+    return arr.ctypes.data, PTR_HOST
+
+
+class Context:
+    """Owns one slbm_ctx (freed by solid_lbm_destroy or on garbage collection)."""
+
+    def __init__(self, handle, problem):
+        self.handle = handle
+        self.nx, self.ny = problem["nx"], problem["ny"]
+        self.N = self.nx * self.ny
+        self.control_kind = problem.get("control_kind", CTRL_FORCE_MODES)
+        self.n_modes = problem.get("n_modes", 0)
+
+    def grad_len(self):
+        return {CTRL_FORCE_MODES: self.n_modes, CTRL_FORCE_NODAL: 2 * self.N, CTRL_E_NODAL: self.N,
+                CTRL_E_SCALAR_SQ: 1}[self.control_kind]
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            LIB.solid_lbm_destroy(self.handle)
+            self.handle = None
+
+
+def _check(ctx, rc):
+    if rc < 0:
+        msg = LIB.solid_lbm_last_error(ctx.handle if ctx is not None else None)
+        raise SlbmError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def solid_lbm_init(problem):
+    """problem: dict with the fields of slbm_problem (arrays as numpy)."""
+    keep = []
+    p = _Problem()
+    p.nx, p.ny = int(problem["nx"]), int(problem["ny"])
+    p.dx = float(problem["dx"])
+    p.E, p.nu = float(problem.get("E", 1.0)), float(problem["nu"])
+    p.domain = int(problem.get("domain", PERIODIC))
+    for name, dt in (("node_mask", np.uint8), ("link_bc", np.uint8), ("link_wall", np.float64),
+                     ("link_normal", np.float64), ("fixed_force", np.float64), ("target", np.float64),
+                     ("obs_mask", np.uint8), ("force_modes", np.float64)):
+        v = problem.get(name)
+        if v is not None:
+            ptr, kind = _arg(v, keep, dt)
+            if kind != PTR_HOST:
+                raise ValueError(f"{name} must be host memory")
+            setattr(p, name, ptr)
+    p.control_kind = int(problem.get("control_kind", CTRL_FORCE_MODES))
+    p.n_modes = int(problem.get("n_modes", 0))
+    p.zero_mean_projection = int(problem.get("zero_mean_projection", 1))
+    p.normalize_objective = int(problem.get("normalize_objective", 1))
+    p.tol = float(problem.get("tol", 1e-10))
+    p.max_steps = int(problem.get("max_steps", 10_000_000))
+    p.check_interval = int(problem.get("check_interval", 0))
+    p.stream = problem.get("stream")
+    h = ctypes.c_void_p()
+    rc = LIB.solid_lbm_init(ctypes.byref(p), ctypes.byref(h))
+    if rc < 0:
+        raise SlbmError(rc, LIB.solid_lbm_last_error(None).decode())
+    return Context(h, dict(problem))
+
+
+def primal_solve(ctx, control, init_disp=None):
+    keep = []
+    cp, kind = _arg(control, keep)
+    ip, kind2 = _arg(init_disp, keep)
+    if init_disp is not None and kind2 != kind:
+        raise ValueError("control and init_disp must live in the same memory kind")
+    info = SolveInfo()
+    rc = _check(ctx, LIB.primal_solve(ctx.handle, cp, ip, kind, ctypes.byref(info)))
+    return rc, info
+
+
+def adjoint_solve(ctx):
+    info = SolveInfo()
+    rc = _check(ctx, LIB.adjoint_solve(ctx.handle, ctypes.byref(info)))
+    return rc, info
+
+
+def objective_and_grad(ctx, control, grad=None, want_grad=True):
+    """Returns (rc, J, grad, primal_info, adjoint_info).  grad: optional output
+    array/tensor (device tensors are written in place); allocated on the host
+    when not given."""
+    keep = []
+    cp, kind = _arg(control, keep)
+    out = None
+    gp = None
+    if want_grad:
+        if grad is None:
+            out = np.zeros(ctx.grad_len())
+            gp = out.ctypes.data
+            gkind = PTR_HOST
+        else:
+            out = grad
+            if _is_torch(grad) and grad.is_cuda:
+                gp, gkind = grad.data_ptr(), PTR_DEVICE
+            else:
+                gp, gkind = grad.ctypes.data, PTR_HOST
+        if gkind != kind:
+            raise ValueError("control and grad must live in the same memory kind")
+    J = ctypes.c_double()
+    pi, ai = SolveInfo(), SolveInfo()
+    rc = _check(ctx, LIB.objective_and_grad(ctx.handle, cp, ctypes.byref(J), gp, kind, ctypes.byref(pi),
+                                            ctypes.byref(ai)))
+    return rc, J.value, out, pi, ai
+
+
+def solid_lbm_set_control(ctx, control, init_disp=None):
+    keep = []
+    cp, kind = _arg(control, keep)
+    ip, _ = _arg(init_disp, keep)
+    return _check(ctx, LIB.solid_lbm_set_control(ctx.handle, cp, ip, kind))
+
+
+def solid_lbm_run_steps(ctx, n):
+    return _check(ctx, LIB.solid_lbm_run_steps(ctx.handle, int(n)))
+
+
+def solid_lbm_run_adjoint_steps(ctx, n):
+    return _check(ctx, LIB.solid_lbm_run_adjoint_steps(ctx.handle, int(n)))
+
+
+def solid_lbm_get_field(ctx, which, out=None):
+    comps = FIELD_COMPS[which]
+    if out is None:
+        out = np.zeros((comps, ctx.ny, ctx.nx))
+    if _is_torch(out) and out.is_cuda:
+        _check(ctx, LIB.solid_lbm_get_field(ctx.handle, which, out.data_ptr(), PTR_DEVICE))
+    else:
+        _check(ctx, LIB.solid_lbm_get_field(ctx.handle, which, out.ctypes.data, PTR_HOST))
+    return out
+
+
+def solid_lbm_time_sweeps(ctx, adjoint, n):
+    ms = ctypes.c_double()
+    _check(ctx, LIB.solid_lbm_time_sweeps(ctx.handle, int(adjoint), int(n), ctypes.byref(ms)))
+    return ms.value
+
+
+def solid_lbm_destroy(ctx):
+    if ctx.handle:
+        LIB.solid_lbm_destroy(ctx.handle)
+        ctx.handle = None

@@ -1,0 +1,97 @@
+"""The C-ABI library loads and exports every entry point its header declares,
+and rejects bad problems on the host (no GPU needed: validation runs before
+any device call)."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2609_31347_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_2609_31347_amd import slbm
+    return slbm
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "solid_lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(S):
+    names = declared()
+    assert len(names) >= 11
+    out = subprocess.run(["nm", "-D", "--defined-only", S.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if " T " in l)
+    for n in names:
+        assert n in exported, n
+        assert hasattr(S.LIB, n)
+    assert set(S.EXPORTS) == set(names)
+
+
+def base_problem(**kw):
+    n = 8
+    p = dict(nx=n, ny=n, dx=1 / n, E=1.0, nu=0.3, domain=0, target=np.ones((2, n, n)),
+             control_kind=1, tol=1e-10, max_steps=100)
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(nx=2), -1), (dict(dx=0.0), -1), (dict(nu=1.0), -1), (dict(nu=-1.5), -1), (dict(E=-1.0), -1),
+    (dict(control_kind=7), -1), (dict(max_steps=0), -1), (dict(check_interval=-3), -1),
+    (dict(domain=5), -1), (dict(control_kind=0, n_modes=0), -1), (dict(target=None), -1),
+    (dict(domain=1), -1),
+])
+def test_init_rejects_bad_problems(S, bad, code):
+    p = base_problem(**bad)
+    with pytest.raises(S.SlbmError) as e:
+        S.solid_lbm_init(p)
+    assert e.value.code == code
+    assert str(e.value)
+
+
+def test_init_rejects_non_finite_target(S):
+    t = np.ones((2, 8, 8))
+    t[1, 3, 3] = np.nan
+    with pytest.raises(S.SlbmError) as e:
+        S.solid_lbm_init(base_problem(target=t))
+    assert e.value.code == S.ENONFINITE
+
+
+def test_init_rejects_inconsistent_plate(S):
+    from paper_2609_31347_amd import inputs as I
+    pd = I.paper_plate(16)
+    p = dict(nx=pd["nx"], ny=pd["ny"], dx=pd["dx"], E=0.1, nu=0.7, domain=1,
+             node_mask=pd["active"].astype(np.uint8), link_bc=pd["bc"].copy(), link_wall=pd["wall"],
+             link_normal=pd["normal"], target=pd["target"], control_kind=1)
+    p["link_bc"][0][pd["active"] & (pd["bc"][0] == 0)] = 1          # a link into an inside node
+    with pytest.raises(S.SlbmError) as e:
+        S.solid_lbm_init(p)
+    assert e.value.code == S.EINVAL and "cut links" in str(e.value)
+    edge = pd["active"].astype(np.uint8).copy()
+    edge[0, 5] = 1
+    with pytest.raises(S.SlbmError) as e:
+        S.solid_lbm_init(dict(p, node_mask=edge, link_bc=pd["bc"]))
+    assert "box edge" in str(e.value)
+
+
+def test_binding_refuses_to_run_without_library(tmp_path):
+    """The product path has no CPU fallback: a missing library is an ImportError."""
+    code = ("import sys, importlib.util; spec = importlib.util.spec_from_file_location('s', sys.argv[1]);"
+            "m = importlib.util.module_from_spec(spec); m.__file__ = sys.argv[2]\n"
+            "import os\nsrc = open(sys.argv[1]).read().replace('HERE = os.path.dirname(os.path.abspath(__file__))',"
+            " 'HERE = sys.argv[2]')\n"
+            "try:\n    exec(compile(src, 'slbm', 'exec'), {'__name__': 's', 'sys': sys})\nexcept ImportError as e:\n"
+            "    print('IMPORTERROR', e)\n")
+    out = subprocess.run(["python", "-c", code, os.path.join(ROOT, "paper_2609_31347_amd", "slbm.py"),
+                          str(tmp_path)], capture_output=True, text=True)
+    assert "IMPORTERROR" in out.stdout

@@ -1,0 +1,270 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI (needs a GPU).
+
+Tolerances: displacement and populations after a fixed number of steps
+<= 1e-12 relative max-norm; gradients <= 1e-10 relative max-norm (for
+converged solves both sides stop at the same check step, so the remaining
+difference is rounding order).  Sizes span several 256-node blocks with a
+ragged tail; full benchmark sizes are checked step-by-step against the
+oracle's single step and against the Fourier closed form.
+"""
+import numpy as np
+import pytest
+
+from paper_2609_31347_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL_D = 1e-12
+TOL_G = 1e-10
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_31347_amd import slbm
+    return slbm
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def periodic_problem(nx, ny, dx, E, nu, target, kind, **kw):
+    d = dict(nx=nx, ny=ny, dx=dx, E=E, nu=nu, domain=0, target=target, control_kind=kind)
+    d.update(kw)
+    return d
+
+
+def plate_problem(S, pd, kind, **kw):
+    d = dict(nx=pd["nx"], ny=pd["ny"], dx=pd["dx"], E=pd["E"], nu=pd["nu"], domain=S.MASKED,
+             node_mask=pd["active"].astype(np.uint8), link_bc=pd["bc"], link_wall=pd["wall"],
+             link_normal=pd["normal"], target=pd["target"], control_kind=kind)
+    d.update(kw)
+    return d
+
+
+def oracle_problem(orc, p, g, E=None):
+    if p.get("domain", 0) == 1:
+        return orc.Problem(p["nx"], p["ny"], p["dx"], p["E"] if E is None else E, p["nu"], g,
+                           active=p["node_mask"], bc=p["link_bc"], wall=p["link_wall"],
+                           normal=p["link_normal"])
+    return orc.Problem(p["nx"], p["ny"], p["dx"], p["E"] if E is None else E, p["nu"], g)
+
+
+# ---------------------------------------------------------------- fixed steps
+
+@pytest.mark.parametrize("nx,ny,steps", [(100, 37, 500), (33, 70, 301)])
+def test_primal_fixed_steps_periodic(S, orc, nx, ny, steps):
+    dx = 1.0 / 64
+    F = I.grf(nx, ny, dx, 0.05, 0.1, 11, comps=2) * 50.0
+    tgt = np.zeros((2, ny, nx))
+    tgt[0, 0, 0] = 1.0
+    p = periodic_problem(nx, ny, dx, 1.0, 0.3, tgt, S.CTRL_FORCE_NODAL, zero_mean_projection=0)
+    ctx = S.solid_lbm_init(p)
+    S.solid_lbm_set_control(ctx, F)
+    S.solid_lbm_run_steps(ctx, steps)
+    pops = S.solid_lbm_get_field(ctx, S.FIELD_POPS)
+    disp = S.solid_lbm_get_field(ctx, S.FIELD_CUR_DISP)
+    q = oracle_problem(orc, p, dx * dx * F)
+    f = orc.run(q, q.zeros(8), steps)
+    _, d, _ = orc.step(q, f)
+    assert rel(pops, f) < TOL_D
+    assert rel(disp, d) < TOL_D
+
+
+def test_primal_warm_start_matches_oracle(S, orc):
+    n = 48
+    modes = I.two_mode_basis(n)
+    tgt = I.two_mode_target(n)
+    p = periodic_problem(n, n, 1 / n, 1.0, 0.3, tgt, S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes)
+    ctx = S.solid_lbm_init(p)
+    a = np.array([0.4, -0.2])
+    d0 = 0.9 * tgt
+    S.solid_lbm_set_control(ctx, a, d0)
+    S.solid_lbm_run_steps(ctx, 123)
+    g = np.tensordot(a, modes, 1) / n ** 2
+    q = oracle_problem(orc, p, g)
+    Minv = orc.minv()
+    u = d0 - 0.5 * g          # populations of N (d0 - g/2): bared displacement d0
+    f0 = np.einsum("qb,byx->qyx", Minv[:, [0, 1, 5, 6]], np.stack([u[0], u[1], u[0] / 3, u[1] / 3]))
+    f = orc.run(q, f0, 123)
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_POPS), f) < TOL_D
+
+
+def test_adjoint_fixed_steps_periodic(S, orc):
+    nx, ny, dx = 40, 29, 1.0 / 40
+    F = I.grf(nx, ny, dx, 0.05, 0.1, 2, comps=2)
+    tgt = I.grf(nx, ny, dx, 1e-6, 0.15, 3, comps=2)
+    p = periodic_problem(nx, ny, dx, 0.8, 0.25, tgt, S.CTRL_FORCE_NODAL, tol=0.0, max_steps=200)
+    ctx = S.solid_lbm_init(p)
+    S.primal_solve(ctx, F)
+    r = S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL)
+    S.solid_lbm_run_adjoint_steps(ctx, 150)
+    phi = S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS)
+    q = oracle_problem(orc, p, dx * dx * orc.zero_mean(F))
+    cb = orc.cbar(q, tgt)
+    src = orc.source(q, r, dx * dx / cb)
+    ph = q.zeros(8)
+    for _ in range(150):
+        ph = orc.adj_step(q, ph, src)[0]
+    assert rel(phi, ph) < TOL_D
+
+
+# ---------------------------------------------------------------- converged gradients
+
+def test_config1_objective_and_gradient(S, orc):
+    """Two-amplitude force identification at N = 32 (E = 1, nu = 0.3), solved
+    to residual 1e-10: J and dJ/dA against the oracle."""
+    n = 32
+    modes = I.two_mode_basis(n)
+    tgt = I.two_mode_target(n)
+    p = periodic_problem(n, n, 1 / n, 1.0, 0.3, tgt, S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes,
+                         tol=1e-10)
+    ctx = S.solid_lbm_init(p)
+    a = np.array([0.1, 0.1])
+    rc, J, grad, pi, ai = S.objective_and_grad(ctx, a)
+    q = oracle_problem(orc, p, np.zeros((2, n, n)))
+    G = orc.objective_and_grad(q, tgt, "modes", a, modes=modes, tol=1e-10)
+    assert rc == 0 and pi.converged and ai.converged
+    assert pi.steps == G.prim.steps and ai.steps == G.adj.steps
+    assert abs(J - G.J) / G.J < TOL_D
+    assert rel(grad, G.grad) < TOL_G
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_DISP), G.prim.dbar) < TOL_D
+
+
+@pytest.mark.parametrize("nx,ny", [(24, 24), (37, 20)])
+def test_nodal_force_gradient_periodic(S, orc, nx, ny):
+    dx = 1.0 / 24
+    tgt = I.grf(nx, ny, dx, 1e-6, 0.15, 5, comps=2)
+    alpha = I.grf(nx, ny, dx, 0.05, 0.1, 6, comps=2) + 0.3
+    p = periodic_problem(nx, ny, dx, 1.0, 0.3, tgt, S.CTRL_FORCE_NODAL, tol=1e-10)
+    ctx = S.solid_lbm_init(p)
+    rc, J, grad, pi, ai = S.objective_and_grad(ctx, alpha)
+    q = oracle_problem(orc, p, np.zeros((2, ny, nx)))
+    G = orc.objective_and_grad(q, tgt, "nodal", alpha, tol=1e-10)
+    assert abs(J - G.J) / G.J < TOL_D
+    assert rel(grad.reshape(2, ny, nx), G.grad) < TOL_G
+
+
+def test_E_controls_periodic(S, orc):
+    n = 20
+    sol = I.paper_periodic(n)
+    base = periodic_problem(n, n, 1 / n, 0.11, 0.8, sol["d"], S.CTRL_E_SCALAR_SQ, fixed_force=sol["F"],
+                            tol=1e-11)
+    ctx = S.solid_lbm_init(base)
+    alpha = np.array([np.sqrt(0.15)])
+    rc, J, grad, _, _ = S.objective_and_grad(ctx, alpha)
+    q = oracle_problem(orc, base, np.zeros((2, n, n)), E=0.11)
+    G = orc.objective_and_grad(q, sol["d"], "E_sq", alpha, fixed_force=sol["F"], tol=1e-11)
+    assert abs(J - G.J) / G.J < TOL_D
+    assert rel(grad, G.grad) < TOL_G
+    E = 0.11 * (1.0 + 0.3 * np.tanh(I.grf(n, n, 1 / n, 0.5, 0.2, 9)[0]))
+    pe = dict(base, control_kind=S.CTRL_E_NODAL)
+    ctx = S.solid_lbm_init(pe)
+    rc, J, grad, _, _ = S.objective_and_grad(ctx, E)
+    G = orc.objective_and_grad(q, sol["d"], "E_nodal", E, fixed_force=sol["F"], tol=1e-11)
+    assert abs(J - G.J) / G.J < TOL_D
+    assert rel(grad.reshape(n, n), G.grad) < TOL_G
+
+
+# ---------------------------------------------------------------- plate
+
+@pytest.fixture(scope="module")
+def plate16():
+    return I.paper_plate(16)
+
+
+def test_plate_fixed_steps(S, orc, plate16):
+    pd = plate16
+    p = plate_problem(S, pd, S.CTRL_FORCE_NODAL)
+    ctx = S.solid_lbm_init(p)
+    S.solid_lbm_set_control(ctx, pd["F"])
+    S.solid_lbm_run_steps(ctx, 400)
+    q = oracle_problem(orc, p, pd["F"] * pd["dx"] ** 2 * pd["active"])
+    f = orc.run(q, q.zeros(8), 400)
+    _, d, _ = orc.step(q, f)
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_POPS), f) < TOL_D
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_CUR_DISP), d) < TOL_D
+
+
+def test_plate_converged_stress_and_force_gradient(S, orc, plate16):
+    pd = plate16
+    p = plate_problem(S, pd, S.CTRL_FORCE_NODAL, tol=1e-11)
+    ctx = S.solid_lbm_init(p)
+    F = pd["F"] * 1.1
+    rc, J, grad, pi, ai = S.objective_and_grad(ctx, F)
+    q = oracle_problem(orc, p, np.zeros((2, pd["ny"], pd["nx"])))
+    G = orc.objective_and_grad(q, pd["target"], "nodal", F, tol=1e-11, project=False)
+    assert pi.steps == G.prim.steps
+    assert abs(J - G.J) / G.J < TOL_D
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_DISP), G.prim.dbar) < TOL_D
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_STRESS), G.prim.sbar) < 1e-11
+    assert rel(grad.reshape(2, pd["ny"], pd["nx"]), G.grad) < TOL_G
+
+
+def test_plate_E_gradients(S, orc, plate16):
+    pd = plate16
+    p = plate_problem(S, pd, S.CTRL_E_SCALAR_SQ, fixed_force=pd["F"], tol=1e-11)
+    ctx = S.solid_lbm_init(p)
+    alpha = np.array([np.sqrt(0.15)])
+    rc, J, grad, _, _ = S.objective_and_grad(ctx, alpha)
+    q = oracle_problem(orc, p, np.zeros((2, pd["ny"], pd["nx"])))
+    G = orc.objective_and_grad(q, pd["target"], "E_sq", alpha, fixed_force=pd["F"], tol=1e-11)
+    assert abs(J - G.J) / G.J < TOL_D
+    assert rel(grad, G.grad) < TOL_G
+    E = np.where(pd["active"], 0.1 + 0.04 * pd["X"], 0.1)
+    ctx = S.solid_lbm_init(dict(p, control_kind=S.CTRL_E_NODAL))
+    rc, J, grad, _, _ = S.objective_and_grad(ctx, E)
+    G = orc.objective_and_grad(q, pd["target"], "E_nodal", E, fixed_force=pd["F"], tol=1e-11)
+    assert abs(J - G.J) / G.J < TOL_D
+    assert rel(grad.reshape(pd["ny"], pd["nx"]), G.grad) < TOL_G
+
+
+# ---------------------------------------------------------------- full size
+
+def test_full_size_single_step_matches_oracle_step(S, orc):
+    """N = 1024 periodic (the benchmark grid, same launch shape): the GPU state
+    after t and t+1 steps agrees with the oracle's one step applied to the GPU
+    state at t, at every node."""
+    n = 1024
+    modes = I.two_mode_basis(n)
+    tgt = I.two_mode_target(n)
+    p = periodic_problem(n, n, 1 / n, 1.0, 0.3, tgt, S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes)
+    ctx = S.solid_lbm_init(p)
+    a = np.array([0.1, 0.1])
+    S.solid_lbm_set_control(ctx, a)
+    S.solid_lbm_run_steps(ctx, 1000)
+    f_t = S.solid_lbm_get_field(ctx, S.FIELD_POPS)
+    S.solid_lbm_run_steps(ctx, 1)
+    f_t1 = S.solid_lbm_get_field(ctx, S.FIELD_POPS)
+    q = oracle_problem(orc, p, np.tensordot(a, modes, 1) / n ** 2)
+    ref, _, _ = orc.step(q, f_t)
+    assert rel(f_t1, ref) < 1e-14
+
+
+def test_full_size_converged_matches_closed_form(S):
+    """N = 1024 benchmark workload solved to 1e-10: J, d and dJ/dA against the
+    Fourier closed form of the exact fixed point (property valid at any size)."""
+    from oracle import fourier as Fo
+    n = 1024
+    modes = I.two_mode_basis(n)
+    tgt = I.two_mode_target(n)
+    p = periodic_problem(n, n, 1 / n, 1.0, 0.3, tgt, S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes,
+                         tol=1e-10)
+    ctx = S.solid_lbm_init(p)
+    a = np.array([0.1, 0.1])
+    rc, J, grad, pi, ai = S.objective_and_grad(ctx, a)
+    assert rc == 0
+    dx2 = 1.0 / n ** 2
+    H = Fo.transfer(n, n, 1.0, 0.3)
+    d = Fo.steady_disp(dx2 * np.tensordot(a, modes, 1), 1.0, 0.3, H)
+    cb = (tgt ** 2).sum() * dx2
+    Jx = 0.5 * ((d - tgt) ** 2).sum() * dx2 / cb
+    gg = Fo.grad_g(d - tgt, 1.0, 0.3, H) * dx2 / cb
+    gx = np.array([(gg * dx2 * m).sum() for m in modes])
+    # residual 1e-10 on a mode decaying by lambda^K per check leaves ~1e-10 relative error
+    assert abs(J - Jx) / Jx < 1e-8
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_DISP), d) < 1e-8
+    assert rel(grad, gx) < 1e-7

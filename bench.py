@@ -26,6 +26,11 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_NODE = 144.0      # 8 pops read + 8 written (8 B each) + 2 forcing / residual reads
 PEAK_GBS = 8000.0           # MI355X HBM3E
+# Bytes per launch of the primal sweep kernel (k_primal<false,false,false>) at
+# N = 1024 from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (calibrated with a
+# plain device copy); profiles/hbm_counters_primal_adjoint_periodic.md.  Set to
+# None whenever the kernel changes until the counters are taken again.
+TRAFFIC_BYTES = {1024: (85171.6 + 65536.0) * 1024}
 
 
 def parse():
@@ -37,7 +42,51 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--mode", choices=("gradient", "sweeps"), default="gradient",
+                    help="sweeps: time fixed counts of primal/adjoint sweeps and a reference copy "
+                         "(for rocprofv3 kernel traces and counters)")
+    ap.add_argument("--sweeps", type=int, default=200)
     return ap.parse_args()
+
+
+def sweeps_mode(args):
+    """Fixed sweep counts on the workload grid, timed with HIP events on the
+    library's stream, plus a plain device copy of the same byte count as one
+    sweep's population traffic (reference for the HBM counters)."""
+    import torch
+    from paper_2609_31347_amd import inputs as I
+    from paper_2609_31347_amd import slbm as S
+    torch.cuda.set_device(0)
+    n = args.n
+    modes = I.two_mode_basis(n)
+    tgt = I.two_mode_target(n)
+    ctx = S.solid_lbm_init(dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC, target=tgt,
+                                control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes, tol=0.0,
+                                max_steps=10, stream=torch.cuda.current_stream().cuda_stream))
+    a = np.array([0.1, 0.1])
+    S.primal_solve(ctx, a)                       # 10 fixed steps: gives the adjoint its inputs
+    S.solid_lbm_time_sweeps(ctx, 0, 20)          # warm-up
+    S.solid_lbm_time_sweeps(ctx, 1, 20)
+    ms_p = S.solid_lbm_time_sweeps(ctx, 0, args.sweeps)
+    ms_a = S.solid_lbm_time_sweeps(ctx, 1, args.sweeps)
+    cells = n * n
+    src = torch.empty(8 * cells, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.sweeps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_c = ev0.elapsed_time(ev1)
+    out = {"mode": "sweeps", "grid": [n, n], "sweeps": args.sweeps,
+           "primal_us": round(ms_p / args.sweeps * 1e3, 3), "adjoint_us": round(ms_a / args.sweeps * 1e3, 3),
+           "primal_GBs": round(BYTES_PER_NODE * cells / (ms_p / args.sweeps * 1e-3) / 1e9, 1),
+           "adjoint_GBs": round(BYTES_PER_NODE * cells / (ms_a / args.sweeps * 1e-3) / 1e9, 1),
+           "copy_bytes": 16 * 8 * cells, "copy_us": round(ms_c / args.sweeps * 1e3, 3),
+           "copy_GBs": round(16 * 8 * cells / (ms_c / args.sweeps * 1e-3) / 1e9, 1)}
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(n, steps, a):
@@ -70,6 +119,8 @@ def cpu_baseline(n, steps, a):
 
 def main():
     args = parse()
+    if args.mode == "sweeps":
+        return sweeps_mode(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
               f"decomposition is a design note, not built)", file=sys.stderr)
@@ -136,7 +187,7 @@ def main():
         "J": rec[-1][1],
         "grad": [float(x) for x in grad.cpu().numpy()],
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach / PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get(n),
                      "kernel": "k_primal<false,false,false> (periodic primal sweep)",
                      "bytes_per_node": BYTES_PER_NODE, "nodes_per_launch": cells,
                      "avg_sweep_us": round(t_primal * 1e6, 3)},

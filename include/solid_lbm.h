@@ -183,7 +183,8 @@ int solid_lbm_get_field(slbm_ctx *ctx, int32_t which, double *out, int32_t ptr_k
 
 /* Timing helper: runs n primal (adjoint = 0) or adjoint (adjoint = 1) sweeps
  * on the current state and returns the device time of those sweeps in
- * *ms (HIP events recorded on the context's stream around them). */
+ * *ms (HIP events recorded on the context's stream around them).  The state
+ * advances; the outputs of the last completed solve stay as they were. */
 int solid_lbm_time_sweeps(slbm_ctx *ctx, int32_t adjoint, int64_t n, double *ms);
 
 /* Message of the last error on ctx (or of the last failed init if ctx is NULL). */

@@ -883,12 +883,10 @@ int solid_lbm_time_sweeps(slbm_ctx* c, int32_t adjoint, int64_t n, double* ms)
     float f = 0.f;
     HIPCHK(c, hipEventElapsedTime(&f, c->t0, c->t1));
     *ms = f;
-    if (adjoint) {
-        c->adj_cur = cur;
-    } else {
-        c->prim_cur = cur;
-        c->prim_done = false;
-    }
+    // timing advances the state but leaves the outputs of the last completed
+    // solve (d, r, averaged populations) untouched
+    if (adjoint) c->adj_cur = cur;
+    else c->prim_cur = cur;
     return SLBM_OK;
 }
 

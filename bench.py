@@ -26,11 +26,11 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_NODE = 144.0      # 8 pops read + 8 written (8 B each) + 2 forcing / residual reads
 PEAK_GBS = 8000.0           # MI355X HBM3E
-# Bytes per launch of the primal sweep kernel (k_primal<false,false,false>) at
-# N = 1024 from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (calibrated with a
-# plain device copy); profiles/hbm_counters_primal_adjoint_periodic.md.  Set to
-# None whenever the kernel changes until the counters are taken again.
-TRAFFIC_BYTES = {1024: (85171.6 + 65536.0) * 1024}
+# Measured HBM bytes per launch of the dominant kernel, keyed by (N, T, H), from
+# rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors of a plain device copy);
+# see profiles/.  Entries are dropped whenever the kernel changes.
+TRAFFIC_BYTES = {(1024, 8, 24): (2.0 * 121596.3 + 65536.0) * 1024,
+                 (2048, 8, 48): (2.0 * 381713.5 + 262144.0) * 1024}
 
 
 def parse():
@@ -46,6 +46,8 @@ def parse():
                     help="sweeps: time fixed counts of primal/adjoint sweeps and a reference copy "
                          "(for rocprofv3 kernel traces and counters)")
     ap.add_argument("--sweeps", type=int, default=200)
+    ap.add_argument("--fuse", type=int, default=-1, help="time steps fused per launch (-1 automatic)")
+    ap.add_argument("--rows", type=int, default=0, help="rows per wave of fused launches (0 automatic)")
     return ap.parse_args()
 
 
@@ -63,6 +65,7 @@ def sweeps_mode(args):
     ctx = S.solid_lbm_init(dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC, target=tgt,
                                 control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes, tol=0.0,
                                 max_steps=10, stream=torch.cuda.current_stream().cuda_stream))
+    S.solid_lbm_set_tuning(ctx, args.fuse, args.rows)
     a = np.array([0.1, 0.1])
     S.primal_solve(ctx, a)                       # 10 fixed steps: gives the adjoint its inputs
     S.solid_lbm_time_sweeps(ctx, 0, 20)          # warm-up
@@ -80,7 +83,7 @@ def sweeps_mode(args):
     ev1.record()
     torch.cuda.synchronize()
     ms_c = ev0.elapsed_time(ev1)
-    out = {"mode": "sweeps", "grid": [n, n], "sweeps": args.sweeps,
+    out = {"mode": "sweeps", "grid": [n, n], "sweeps": args.sweeps, "fuse": args.fuse, "rows": args.rows,
            "primal_us": round(ms_p / args.sweeps * 1e3, 3), "adjoint_us": round(ms_a / args.sweeps * 1e3, 3),
            "primal_GBs": round(BYTES_PER_NODE * cells / (ms_p / args.sweeps * 1e-3) / 1e9, 1),
            "adjoint_GBs": round(BYTES_PER_NODE * cells / (ms_a / args.sweeps * 1e-3) / 1e9, 1),
@@ -137,6 +140,10 @@ def main():
                 control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes, tol=args.tol,
                 max_steps=50_000_000, stream=torch.cuda.current_stream().cuda_stream)
     ctx = S.solid_lbm_init(prob)
+    from paper_2609_31347_amd import autotune
+    props = torch.cuda.get_device_properties(0)
+    tune = autotune.autotune(ctx, prob, np.array([0.1, 0.1]),
+                             device=f"{getattr(props, 'gcnArchName', '')}:{props.name}")
     a = torch.tensor([0.1, 0.1], dtype=torch.float64, device="cuda")
     grad = torch.zeros(2, dtype=torch.float64, device="cuda")
 
@@ -158,8 +165,9 @@ def main():
     p_ms = sum(r[2]["device_ms"] for r in rec)
     a_ms = sum(r[3]["device_ms"] for r in rec)
     mlups = sweeps * cells / wall / 1e6
-    t_primal = p_ms / p_sweeps * 1e-3          # s per primal sweep (device, events)
+    t_primal = p_ms / p_sweeps * 1e-3          # s per primal time step (device, events)
     t_adj = a_ms / a_sweeps * 1e-3
+    T, H = tune["T"], tune["H"]
     ach = BYTES_PER_NODE * cells / t_primal / 1e9
     ach_adj = BYTES_PER_NODE * cells / t_adj / 1e9
     out = {
@@ -187,10 +195,16 @@ def main():
         "J": rec[-1][1],
         "grad": [float(x) for x in grad.cpu().numpy()],
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get(n),
-                     "kernel": "k_primal<false,false,false> (periodic primal sweep)",
-                     "bytes_per_node": BYTES_PER_NODE, "nodes_per_launch": cells,
-                     "avg_sweep_us": round(t_primal * 1e6, 3)},
+                     "frac": round(ach / PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get((n, T, H)),
+                     "kernel": (f"k_sweep_tb<{T},false> (primal sweep, {T} time steps per launch, "
+                                f"{H} rows per wave)" if T > 1 else "k_primal<false,false,false> (primal sweep)"),
+                     "bytes_per_node_step": BYTES_PER_NODE, "node_steps_per_launch": cells * max(T, 1),
+                     "avg_step_us": round(t_primal * 1e6, 3),
+                     "note": "achieved = algorithmic bytes of the single-step scheme (144 B per node and "
+                             "time step) over the measured time; fused launches reuse data across their T "
+                             "steps in registers, so frac can exceed 1 while the HBM traffic (traffic, "
+                             "bytes per launch) stays below the peak"},
+        "tuning": {"T": T, "H": H, "cached": tune["cached"], "candidates_us": tune.get("us")},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, np.array([0.1, 0.1]))

@@ -187,6 +187,14 @@ int solid_lbm_get_field(slbm_ctx *ctx, int32_t which, double *out, int32_t ptr_k
  * advances; the outputs of the last completed solve stay as they were. */
 int solid_lbm_time_sweeps(slbm_ctx *ctx, int32_t adjoint, int64_t n, double *ms);
 
+/* Launch shape of the sweeps.  steps_per_launch: -1 automatic (default), 0 or
+ * 1 = one time step per launch, 2/4/6/8 = that many time steps fused in one
+ * launch (periodic, uniform-material problems; other problems always use one
+ * step per launch).  rows_per_wave: rows each wave of a fused launch covers
+ * (0 = automatic).  Results do not depend on these settings beyond rounding
+ * order. */
+int solid_lbm_set_tuning(slbm_ctx *ctx, int32_t steps_per_launch, int32_t rows_per_wave);
+
 /* Message of the last error on ctx (or of the last failed init if ctx is NULL). */
 const char *solid_lbm_last_error(const slbm_ctx *ctx);
 

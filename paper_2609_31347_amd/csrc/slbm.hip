@@ -48,6 +48,8 @@ struct slbm_ctx {
     Status* h_status = nullptr;  // pinned, 2 slots
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr;
+    int tb_T = -1;     // steps fused per launch (0/1: single-step sweeps; -1: automatic)
+    int tb_H = 0;      // rows per wave of the fused sweeps (0: automatic)
     int64_t nblk = 0;  // blocks of one sweep
     int64_t pcap = 0;  // capacity of the partial-sum buffer in blocks
     // state
@@ -160,12 +162,64 @@ void launch_sweep(slbm_ctx* c, bool adjoint, const SweepArgs& a, bool check)
 #undef SL_CASE
 }
 
+// Steps fused per launch for this context (1 = single-step sweeps only): the
+// fused kernels cover the periodic, uniform-material bulk.
+int fused_steps(const slbm_ctx* c)
+{
+    if (c->masked || c->efield_on) return 1;
+    int T = c->tb_T;
+    if (T < 0) T = 8;
+    if (T != 2 && T != 4 && T != 6 && T != 8) return 1;
+    return T;
+}
+
+int fused_rows(const slbm_ctx* c, int T)
+{
+    if (c->tb_H > 0) return std::min(c->tb_H, c->ny);
+    // measured on MI355X (periodic 1024^2 and 2048^2): 24 rows per wave up to
+    // ~1.5k rows, 48 beyond; the autotuner refines this per problem
+    int H = c->ny <= 1536 ? 24 : 48;
+    if (H < 2 * T) H = 2 * T;
+    return std::min(H, c->ny);
+}
+
+void launch_fused(slbm_ctx* c, bool adjoint, const SweepArgs& s, int T)
+{
+    TBArgs a;
+    a.src = s.src;
+    a.dst = s.dst;
+    a.g = s.g;
+    a.status = c->status;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.N = c->N;
+    a.k11 = s.k11;
+    a.ks = s.ks;
+    a.kd = s.kd;
+    a.scale = s.scale;
+    a.H = fused_rows(c, T);
+    int V = 64 - 2 * T;
+    dim3 grid((unsigned)((c->nx + V - 1) / V), (unsigned)((c->ny + a.H - 1) / a.H)), block(64);
+#define TB_CASE(TT)                                                                                   \
+    case TT:                                                                                          \
+        if (adjoint) hipLaunchKernelGGL((k_sweep_tb<TT, true>), grid, block, 0, c->stream, a);        \
+        else hipLaunchKernelGGL((k_sweep_tb<TT, false>), grid, block, 0, c->stream, a);               \
+        break;
+    switch (T) {
+        TB_CASE(2)
+        TB_CASE(4)
+        TB_CASE(6)
+        TB_CASE(8)
+    }
+#undef TB_CASE
+}
+
 // Runs sweeps with indices 0 .. last (inclusive) from buffer parity `start`,
 // checking every K steps when tol > 0; stops at the first passing test.
 // Returns the step index t of the final state whose successor was also
 // produced (the last executed sweep has index t).
 int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, int64_t* t_out,
-             double* res_out, bool* conv_out, double* dev_ms = nullptr)
+             double* res_out, bool* conv_out, double* dev_ms = nullptr, int* x_out = nullptr)
 {
     double** bufs = adjoint ? c->abuf : c->fbuf;
     hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(1), 0, c->stream, c->status);
@@ -182,18 +236,38 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
     int chunk = 0;
     bool stopped = false;
     HIPCHK(c, hipEventRecord(c->t0, c->stream));
+    // buffer holding the input of sweep s; check sweeps and the final sweep are
+    // single-step launches, runs of plain sweeps between them are fused by T
+    int cur = start;
+    const int T = fused_steps(c);
+    std::vector<std::pair<int64_t, int>> checks;  // (step, input buffer) of every check sweep
+    int last_in = start;
     while (s <= last && !stopped) {
         int64_t end = use_tol ? std::min(last, (s / K + 1) * K - 1) : last;
-        if (!use_tol && end - s > 4096) end = s + 4095;
-        for (; s <= end; ++s) {
+        if (!use_tol && end - s > 4096 * T) end = s + 4096 * T - 1;
+        while (s <= end) {
             bool check = use_tol && s > 0 && s % K == 0;
-            int cur = (start + (int)(s & 1)) & 1;
+            // plain sweeps available for fusing: up to `end`, never the final sweep
+            int64_t plain = std::min(end, last - 1) - s + 1;
+            if (!check && T > 1 && plain >= T) {
+                a.src = bufs[cur];
+                a.dst = bufs[cur ^ 1];
+                launch_fused(c, adjoint, a, T);
+                cur ^= 1;
+                s += T;
+                continue;
+            }
             a.src = bufs[cur];
             a.dst = bufs[cur ^ 1];
             launch_sweep(c, adjoint, a, check);
-            if (check)
+            if (check) {
                 hipLaunchKernelGGL(k_residual, dim3(1), dim3(kBlock), 0, c->stream, c->partial, c->nblk,
                                    c->status, c->tol, s);
+                checks.emplace_back(s, cur);
+            }
+            if (s == last) last_in = cur;
+            cur ^= 1;
+            ++s;
         }
         HIPCHK(c, hipGetLastError());
         if (use_tol) {
@@ -220,9 +294,15 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
     if (use_tol && st.stop) {
         *t_out = st.t_conv;
         *conv_out = true;
+        int xin = -1;
+        for (auto& ck : checks)
+            if (ck.first == st.t_conv) xin = ck.second;
+        if (xin < 0) return fail(c, SLBM_EHIP, "internal: converged step without a check sweep");
+        if (x_out) *x_out = xin;
     } else {
         *t_out = last;
         *conv_out = false;
+        if (x_out) *x_out = last_in;
     }
     *res_out = st.res;
     return SLBM_OK;
@@ -406,9 +486,9 @@ int do_primal(slbm_ctx* c, slbm_solve_info* info)
     bool conv;
     bool use_tol = c->tol > 0.0;
     double dms = 0.0;
-    int rc = run_loop(c, false, c->prim_cur, c->max_steps, use_tol, &t, &res, &conv, &dms);
+    int X = 0;  // buffer holding f^C(t-1)
+    int rc = run_loop(c, false, c->prim_cur, c->max_steps, use_tol, &t, &res, &conv, &dms, &X);
     if (rc) return rc;
-    int X = (c->prim_cur + (int)(t & 1)) & 1;  // buffer holding f^C(t-1)
     if ((rc = finalize_primal(c, X))) return rc;
     c->prim_cur = X ^ 1;  // current state: f^S(t+1)
     c->prim_done = true;
@@ -451,8 +531,8 @@ int do_adjoint(slbm_ctx* c, slbm_solve_info* info)
     bool conv;
     bool use_tol = c->tol > 0.0;
     double dms = 0.0;
-    if ((rc = run_loop(c, true, 0, c->max_steps, use_tol, &t, &res, &conv, &dms))) return rc;
-    int X = (int)(t & 1);  // buffer holding phi^C(t)
+    int X = 0;  // buffer holding phi^C(t)
+    if ((rc = run_loop(c, true, 0, c->max_steps, use_tol, &t, &res, &conv, &dms, &X))) return rc;
     bool wantE = c->kind == SLBM_CTRL_E_NODAL || c->kind == SLBM_CTRL_E_SCALAR_SQ;
     double scale = c->dx2 / c->cbar;
     if (c->masked)
@@ -789,9 +869,10 @@ int solid_lbm_run_steps(slbm_ctx* c, int64_t n)
     int64_t t;
     double res;
     bool conv;
-    int rc = run_loop(c, false, c->prim_cur, n - 1, false, &t, &res, &conv);
+    int X = 0;
+    int rc = run_loop(c, false, c->prim_cur, n - 1, false, &t, &res, &conv, nullptr, &X);
     if (rc) return rc;
-    c->prim_cur = (c->prim_cur + (int)(n & 1)) & 1;
+    c->prim_cur = X ^ 1;
     c->prim_done = false;
     return SLBM_OK;
 }
@@ -807,8 +888,9 @@ int solid_lbm_run_adjoint_steps(slbm_ctx* c, int64_t n)
     int64_t t;
     double res;
     bool conv;
-    if ((rc = run_loop(c, true, 0, n - 1, false, &t, &res, &conv))) return rc;
-    c->adj_cur = (int)(n & 1);
+    int X = 0;
+    if ((rc = run_loop(c, true, 0, n - 1, false, &t, &res, &conv, nullptr, &X))) return rc;
+    c->adj_cur = X ^ 1;
     return SLBM_OK;
 }
 
@@ -870,11 +952,18 @@ int solid_lbm_time_sweeps(slbm_ctx* c, int32_t adjoint, int64_t n, double* ms)
     a.scale = c->dx2 / c->cbar;
     double** bufs = adjoint ? c->abuf : c->fbuf;
     int cur = adjoint ? c->adj_cur : c->prim_cur;
+    const int T = fused_steps(c);
     HIPCHK(c, hipEventRecord(c->t0, c->stream));
-    for (int64_t s = 0; s < n; ++s) {
+    for (int64_t s = 0; s < n;) {
         a.src = bufs[cur];
         a.dst = bufs[cur ^ 1];
-        launch_sweep(c, adjoint != 0, a, false);
+        if (T > 1 && n - s >= T) {
+            launch_fused(c, adjoint != 0, a, T);
+            s += T;
+        } else {
+            launch_sweep(c, adjoint != 0, a, false);
+            ++s;
+        }
         cur ^= 1;
     }
     HIPCHK(c, hipGetLastError());
@@ -887,6 +976,18 @@ int solid_lbm_time_sweeps(slbm_ctx* c, int32_t adjoint, int64_t n, double* ms)
     // solve (d, r, averaged populations) untouched
     if (adjoint) c->adj_cur = cur;
     else c->prim_cur = cur;
+    return SLBM_OK;
+}
+
+int solid_lbm_set_tuning(slbm_ctx* c, int32_t steps_per_launch, int32_t rows_per_wave)
+{
+    if (!c) return SLBM_EINVAL;
+    if (!(steps_per_launch == -1 || steps_per_launch == 0 || steps_per_launch == 1 || steps_per_launch == 2 ||
+          steps_per_launch == 4 || steps_per_launch == 6 || steps_per_launch == 8))
+        return fail(c, SLBM_EINVAL, "steps_per_launch must be -1 (automatic), 0, 1, 2, 4, 6 or 8");
+    if (rows_per_wave < 0) return fail(c, SLBM_EINVAL, "rows_per_wave must be >= 0");
+    c->tb_T = steps_per_launch;
+    c->tb_H = rows_per_wave;
     return SLBM_OK;
 }
 

@@ -529,3 +529,191 @@ __global__ __launch_bounds__(kBlock) void k_stress(const double* __restrict__ fb
 }
 
 }  // namespace slbm
+
+namespace slbm {
+
+// ---------------------------------------------------------------- temporally blocked sweeps
+// T fused time steps of the periodic, uniform-material bulk sweep (primal or
+// adjoint) per launch.  One 64-lane wave owns a strip of 64 consecutive
+// columns (64 - 2T of them written, T halo columns on each side) and H output
+// rows, and marches down the rows of the strip with a pipeline of T levels:
+// level k computes step t+k-1 for row r-k while level 0 loads row r.  The pull
+// of row y at level k reads level k-1 at rows y-1 (two iterations back), y
+// (one back) and y+1 (this iteration); these are kept in registers, and the
+// x-neighbours come from the adjacent lanes by shuffles.  Every node is read
+// once and written once per T steps (plus the halo), instead of once per step.
+// The arithmetic per node and step is the single-step kernels' own
+// (collide_bulk / adj_collide_bulk), so the result equals T single sweeps.
+struct TBArgs {
+    const double* __restrict__ src;
+    double* __restrict__ dst;
+    const double* __restrict__ g;   // primal: forcing; adjoint: r
+    const Status* __restrict__ status;
+    int32_t nx, ny, H;
+    int64_t N;
+    double k11, ks, kd, scale;
+};
+
+// Whole-wave lane shifts of a double: up = value of lane l-1, down = value of
+// lane l+1 (the end lanes keep their own value; they are halo lanes).
+// DPP wave_shr:1 / wave_shl:1 moves (no LDS crossbar) unless built with
+// SLBM_TB_DPP=0 (then ds_bpermute shuffles); SLBM_TB_UNROLL=2 runs two rows per
+// loop trip so the scheduler can overlap their independent levels.
+#ifndef SLBM_TB_DPP
+#define SLBM_TB_DPP 1
+#endif
+#ifndef SLBM_TB_UNROLL
+#define SLBM_TB_UNROLL 2
+#endif
+__device__ __forceinline__ double lane_up(double v)
+{
+#if SLBM_TB_DPP
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);  // wave_shr:1
+    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+#else
+    return __shfl_up(v, 1);
+#endif
+}
+__device__ __forceinline__ double lane_down(double v)
+{
+#if SLBM_TB_DPP
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);  // wave_shl:1
+    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+#else
+    return __shfl_down(v, 1);
+#endif
+}
+
+__device__ __forceinline__ int wrapi(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// One pipeline step of a strip: `o` holds row r as loaded (level 0) and
+// returns level T's output (row r - T).
+template <int T, bool ADJ>
+__device__ __forceinline__ void tb_row(double (&p2)[T][3], double (&p1a)[T][3], double (&p1b)[T][2],
+                                       double (&o)[8], const TBArgs& a, int r, int x)
+{
+    constexpr int A0 = ADJ ? 3 : 1, A1 = ADJ ? 6 : 4, A2 = ADJ ? 7 : 5;   // planes pulled from row y-1
+    const int64_t N = a.N;
+#pragma unroll
+    for (int k = 1; k <= T; ++k) {
+        // pull of row y = r - k from level k-1
+        double f[8];
+        if (!ADJ) {
+            f[0] = lane_up(p1b[k - 1][0]);     // (1,0)   from x-1, row y
+            f[2] = lane_down(p1b[k - 1][1]);   // (-1,0)  from x+1, row y
+            f[1] = p2[k - 1][0];               // (0,1)   row y-1
+            f[4] = lane_up(p2[k - 1][1]);      // (1,1)   x-1, row y-1
+            f[5] = lane_down(p2[k - 1][2]);    // (-1,1)  x+1, row y-1
+            f[3] = o[3];                       // (0,-1)  row y+1
+            f[6] = lane_down(o[6]);            // (-1,-1) x+1, row y+1
+            f[7] = lane_up(o[7]);              // (1,-1)  x-1, row y+1
+        } else {
+            f[0] = lane_down(p1b[k - 1][0]);   // from x+1, row y
+            f[2] = lane_up(p1b[k - 1][1]);     // from x-1, row y
+            f[3] = p2[k - 1][0];               // (0,-1)  row y-1
+            f[6] = lane_up(p2[k - 1][1]);      // (-1,-1) x-1, row y-1
+            f[7] = lane_down(p2[k - 1][2]);    // (1,-1)  x+1, row y-1
+            f[1] = o[1];                       // (0,1)   row y+1
+            f[4] = lane_down(o[4]);            // (1,1)   x+1, row y+1
+            f[5] = lane_up(o[5]);              // (-1,1)  x-1, row y+1
+        }
+        // level k-1 history advances by one row
+        p2[k - 1][0] = p1a[k - 1][0];
+        p2[k - 1][1] = p1a[k - 1][1];
+        p2[k - 1][2] = p1a[k - 1][2];
+        p1a[k - 1][0] = o[A0];
+        p1a[k - 1][1] = o[A1];
+        p1a[k - 1][2] = o[A2];
+        p1b[k - 1][0] = o[0];
+        p1b[k - 1][1] = o[2];
+        const int64_t gi = (int64_t)wrapi(r - k, a.ny) * a.nx + x;
+        if (!ADJ) {
+            double d0, d1;
+            collide_bulk(f, a.g[gi], a.g[N + gi], a.k11, a.ks, a.kd, d0, d1);
+        } else {
+            adj_collide_bulk(f, a.scale * a.g[gi], a.scale * a.g[N + gi], a.k11, a.ks, a.kd);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o[q] = f[q];
+    }
+}
+
+template <int T, bool ADJ>
+__global__ __launch_bounds__(64) void k_sweep_tb(TBArgs a)
+{
+    if (a.status->stop) return;
+    constexpr int V = 64 - 2 * T;
+    const int lane = threadIdx.x;
+    const int nx = a.nx, ny = a.ny;
+    const int64_t N = a.N;
+    const int xs = blockIdx.x * V - T + lane;           // unwrapped column of this lane
+    const int x = wrapi(xs, nx);
+    const bool out_lane = lane >= T && lane < 64 - T && xs < nx;
+    const int y0 = blockIdx.y * a.H;
+    const int y1 = min(y0 + a.H, ny);
+    // histories of level k's outputs (k = 0..T-1): p2 = row two back, p1 = row one back.
+    // primal: rows y-1 feed planes {1,4,5}, rows y+1 feed {3,6,7};
+    // adjoint: rows y-1 feed {3,6,7}, rows y+1 feed {1,4,5}.
+    double p2[T][3], p1a[T][3], p1b[T][2];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        p2[k][0] = p2[k][1] = p2[k][2] = 0.0;
+        p1a[k][0] = p1a[k][1] = p1a[k][2] = 0.0;
+        p1b[k][0] = p1b[k][1] = 0.0;
+    }
+    const int iters = (y1 - y0) + 2 * T;
+    int r = y0 - T;
+    auto load = [&](int row, double (&v)[8]) {
+        const int64_t base = (int64_t)wrapi(row, ny) * nx + x;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = a.src[q * N + base];
+    };
+    auto store = [&](int row, const double (&v)[8]) {
+        const int yo = row - T;
+        if (out_lane && yo >= y0 && yo < y1) {
+            const int64_t base = (int64_t)yo * nx + x;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a.dst[q * N + base] = v[q];
+        }
+    };
+#if SLBM_TB_UNROLL >= 2
+    // two rows per trip: the second row's early levels overlap the first's late ones
+    int it = 0;
+    for (; it + 1 < iters; it += 2, r += 2) {
+        double o0[8], o1[8];
+        load(r, o0);
+        load(r + 1, o1);
+        tb_row<T, ADJ>(p2, p1a, p1b, o0, a, r, x);
+        store(r, o0);
+        tb_row<T, ADJ>(p2, p1a, p1b, o1, a, r + 1, x);
+        store(r + 1, o1);
+    }
+    if (it < iters) {
+        double o0[8];
+        load(r, o0);
+        tb_row<T, ADJ>(p2, p1a, p1b, o0, a, r, x);
+        store(r, o0);
+    }
+#else
+    double nxt[8];
+    load(r, nxt);
+    for (int it = 0; it < iters; ++it, ++r) {
+        double o[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o[q] = nxt[q];
+        if (it + 1 < iters) load(r + 1, nxt);
+        tb_row<T, ADJ>(p2, p1a, p1b, o, a, r, x);
+        store(r, o);
+    }
+#endif
+}
+
+}  // namespace slbm

@@ -22,7 +22,7 @@ FIELD_COMPS = {FIELD_DISP: 2, FIELD_STRESS: 3, FIELD_ADJ_DISP: 2, FIELD_POPS: 8,
                FIELD_RESIDUAL: 2, FIELD_CUR_DISP: 2}
 EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_grad", "solid_lbm_set_control",
            "solid_lbm_run_steps", "solid_lbm_run_adjoint_steps", "solid_lbm_get_field",
-           "solid_lbm_time_sweeps", "solid_lbm_last_error", "solid_lbm_destroy")
+           "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_last_error", "solid_lbm_destroy")
 
 
 class SlbmError(RuntimeError):
@@ -67,6 +67,7 @@ def _load():
     lib.solid_lbm_run_adjoint_steps.argtypes = [P, ctypes.c_int64]
     lib.solid_lbm_get_field.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32]
     lib.solid_lbm_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    lib.solid_lbm_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.solid_lbm_last_error.argtypes = [P]
     lib.solid_lbm_last_error.restype = ctypes.c_char_p
     lib.solid_lbm_destroy.argtypes = [P]
@@ -232,6 +233,10 @@ def solid_lbm_time_sweeps(ctx, adjoint, n):
     ms = ctypes.c_double()
     _check(ctx, LIB.solid_lbm_time_sweeps(ctx.handle, int(adjoint), int(n), ctypes.byref(ms)))
     return ms.value
+
+
+def solid_lbm_set_tuning(ctx, steps_per_launch=-1, rows_per_wave=0):
+    return _check(ctx, LIB.solid_lbm_set_tuning(ctx.handle, int(steps_per_launch), int(rows_per_wave)))
 
 
 def solid_lbm_destroy(ctx):

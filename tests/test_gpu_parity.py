@@ -268,3 +268,54 @@ def test_full_size_converged_matches_closed_form(S):
     assert abs(J - Jx) / Jx < 1e-8
     assert rel(S.solid_lbm_get_field(ctx, S.FIELD_DISP), d) < 1e-8
     assert rel(grad, gx) < 1e-7
+
+
+# ---------------------------------------------------------------- fused (multi-step) sweeps
+
+@pytest.mark.parametrize("T", [2, 4, 6, 8])
+@pytest.mark.parametrize("nx,ny,H", [(100, 37, 0), (100, 37, 5), (20, 9, 0), (64, 64, 17), (130, 3, 0)])
+def test_fused_sweeps_match_oracle(S, orc, T, nx, ny, H):
+    """T time steps fused per launch (column strips with register pipelines)
+    give the oracle's populations after a fixed step count, for the primal and
+    the adjoint, including grids narrower than a wave and shorter than 2T rows."""
+    dx = 1.0 / 48
+    F = I.grf(nx, ny, dx, 0.05, 0.1, 21, comps=2) if min(nx, ny) > 4 else np.random.default_rng(1).standard_normal((2, ny, nx))
+    F = F - F.mean((1, 2), keepdims=True)
+    tgt = I.grf(nx, ny, dx, 1e-6, 0.15, 22, comps=2) if min(nx, ny) > 4 else 1e-3 * np.random.default_rng(2).standard_normal((2, ny, nx))
+    steps = 4 * T + 3
+    p = periodic_problem(nx, ny, dx, 1.0, 0.3, tgt, S.CTRL_FORCE_NODAL, tol=0.0, max_steps=steps,
+                         zero_mean_projection=0)
+    ctx = S.solid_lbm_init(p)
+    S.solid_lbm_set_tuning(ctx, T, H)
+    S.solid_lbm_set_control(ctx, F)
+    S.solid_lbm_run_steps(ctx, steps)
+    q = oracle_problem(orc, p, dx * dx * F)
+    f = orc.run(q, q.zeros(8), steps)
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_POPS), f) < TOL_D
+    S.primal_solve(ctx, F)
+    r = S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL)
+    S.solid_lbm_run_adjoint_steps(ctx, steps)
+    cb = orc.cbar(q, tgt)
+    src = orc.source(q, r, dx * dx / cb)
+    ph = q.zeros(8)
+    for _ in range(steps):
+        ph = orc.adj_step(q, ph, src)[0]
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS), ph) < TOL_D
+
+
+def test_fused_and_single_step_solves_agree(S):
+    """The converged gradient does not depend on the launch shape beyond rounding."""
+    n = 96
+    modes = I.two_mode_basis(n)
+    tgt = I.two_mode_target(n)
+    p = periodic_problem(n, n, 1 / n, 1.0, 0.3, tgt, S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes,
+                         tol=1e-10)
+    out = []
+    for T in (1, 8):
+        ctx = S.solid_lbm_init(p)
+        S.solid_lbm_set_tuning(ctx, T, 0)
+        rc, J, grad, pi, ai = S.objective_and_grad(ctx, np.array([0.1, 0.1]))
+        out.append((J, grad, pi.steps, ai.steps))
+    assert out[0][2:] == out[1][2:]
+    assert abs(out[0][0] - out[1][0]) <= 1e-13 * out[0][0]
+    assert rel(out[1][1], out[0][1]) < 1e-12

@@ -76,7 +76,10 @@ enum {
     SLBM_FIELD_POPS = 3,      /* 8N: current primal post-streaming populations f^S */
     SLBM_FIELD_ADJ_POPS = 4,  /* 8N: current adjoint post-collision populations phi^C */
     SLBM_FIELD_RESIDUAL = 5,  /* 2N: r = d - d* on the observation set (0 elsewhere) */
-    SLBM_FIELD_CUR_DISP = 6   /* 2N: bared displacement of the current state f^S   */
+    SLBM_FIELD_CUR_DISP = 6,  /* 2N: bared displacement of the current state f^S   */
+    SLBM_FIELD_AVG_POPS = 7   /* 8N: two-step-averaged populations of the last completed
+                                 primal solve (the converged state; a checkpoint for
+                                 solid_lbm_restore_solve) */
 };
 
 typedef struct slbm_ctx slbm_ctx; /* opaque; owns all device buffers */
@@ -164,7 +167,31 @@ int objective_and_grad(slbm_ctx *ctx, const double *control, double *J, double *
                        int32_t ptr_kind, slbm_solve_info *primal_info,
                        slbm_solve_info *adjoint_info);
 
+/*
+ * Vector-Jacobian product of the solution map at the last completed primal
+ * solve: grad = (d dbar / d control)^T d_cot for a displacement cotangent d_cot
+ * (2N; entries outside the domain are ignored; on periodic domains its mean
+ * is removed, which does not change the product because dbar has zero mean).
+ * This is Algorithm "ALBM" with the objective's source (dJ/df)^T replaced by
+ * the cotangent and eq. optimality applied to it.  d_cot and grad (length as
+ * for objective_and_grad) are read/written according to ptr_kind.  The
+ * objective's residual held in the context is replaced by d_cot.
+ */
+int adjoint_solve_vjp(slbm_ctx *ctx, const double *d_cot, double *grad, int32_t ptr_kind,
+                      slbm_solve_info *info);
+
 /* ---- helpers ---- */
+
+/* Reinstates a converged primal state from a checkpoint: sets the control
+ * (as primal_solve) and takes avg_pops (8N, the SLBM_FIELD_AVG_POPS of a
+ * solve with that control) as the two-step-averaged fixed point; recomputes
+ * d, r and J from it.  Afterwards adjoint_solve / adjoint_solve_vjp run as
+ * after primal_solve. */
+int solid_lbm_restore_solve(slbm_ctx *ctx, const double *control, const double *avg_pops,
+                            int32_t ptr_kind);
+
+/* Objective J of the last completed primal solve (host). */
+int solid_lbm_objective(slbm_ctx *ctx, double *J);
 
 /* Sets the forcing/moduli from a control (as primal_solve) and resets the
  * primal state to f^S(0) (cold, or warm from init_disp); no stepping. */

@@ -274,6 +274,11 @@ def objective_and_grad(p, target, kind, control, modes=None, fixed_force=None, o
     c = cbar(q, target, obs) if normalize else 1.0
     r = (prim.dbar - target) * m
     J = 0.5 * float((r ** 2).sum()) * dx2 / c
+    if q.active is None:
+        # periodic: d has zero mean, so the mean of the adjoint source is outside
+        # the range of the solution map; removing it keeps the adjoint's
+        # translation mode at rest and leaves the gradient unchanged
+        r = zero_mean(r)
     src = source(q, r, dx2 / c)
     adj = adj_solve(q, src, tol=tol, K=K, max_steps=max_steps)
     dg_adj, dE = grad_local(q, prim.fbar, adj.ext, want_E=kind in ("E_nodal", "E_sq"))

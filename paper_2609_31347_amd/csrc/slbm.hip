@@ -520,21 +520,46 @@ int adjoint_prepare(slbm_ctx* c)
     return SLBM_OK;
 }
 
-int do_adjoint(slbm_ctx* c, slbm_solve_info* info)
+// Periodic domains: the displacement has zero mean by construction, so the
+// mean of the adjoint source lies outside the range of the solution map; it is
+// removed (per component) so that the adjoint's translation mode stays at rest.
+int project_source(slbm_ctx* c)
+{
+    if (c->masked) return SLBM_OK;
+    double m[2];
+    int rc;
+    for (int k = 0; k < 2; ++k) {
+        if ((rc = dot(c, c->r + k * c->N, nullptr, c->N, &m[k]))) return rc;
+        m[k] /= (double)c->N;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->work, m, 2 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->r, (const double*)c->work,
+                       (const int32_t*)nullptr, c->N, 1.0, c->r);
+    HIPCHK(c, hipGetLastError());
+    return SLBM_OK;
+}
+
+int do_adjoint(slbm_ctx* c, slbm_solve_info* info, double scale_override = -1.0)
 {
     if (!c->prim_done) return fail(c, SLBM_ESTATE, "adjoint_solve needs a completed primal_solve");
     auto w0 = std::chrono::steady_clock::now();
     int rc = adjoint_prepare(c);
     if (rc) return rc;
+    if ((rc = project_source(c))) return rc;
+    const double saved_cbar = c->cbar;
+    if (scale_override > 0.0) c->cbar = c->dx2 / scale_override;  // run_loop uses dx^2 / cbar
     int64_t t;
     double res;
     bool conv;
     bool use_tol = c->tol > 0.0;
     double dms = 0.0;
     int X = 0;  // buffer holding phi^C(t)
-    if ((rc = run_loop(c, true, 0, c->max_steps, use_tol, &t, &res, &conv, &dms, &X))) return rc;
+    rc = run_loop(c, true, 0, c->max_steps, use_tol, &t, &res, &conv, &dms, &X);
+    c->cbar = saved_cbar;
+    if (rc) return rc;
     bool wantE = c->kind == SLBM_CTRL_E_NODAL || c->kind == SLBM_CTRL_E_SCALAR_SQ;
-    double scale = c->dx2 / c->cbar;
+    double scale = scale_override > 0.0 ? scale_override : c->dx2 / c->cbar;
     if (c->masked)
         hipLaunchKernelGGL(k_adjoint_finalize<true>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->abuf[X],
                            c->abuf[X ^ 1], c->code, c->bnodes, c->fbar, c->r, c->g,
@@ -884,6 +909,7 @@ int solid_lbm_run_adjoint_steps(slbm_ctx* c, int64_t n)
     if (n < 0) return fail(c, SLBM_EINVAL, "n must be >= 0");
     int rc = adjoint_prepare(c);
     if (rc) return rc;
+    if ((rc = project_source(c))) return rc;
     if (n == 0) return SLBM_OK;
     int64_t t;
     double res;
@@ -931,6 +957,9 @@ int solid_lbm_get_field(slbm_ctx* c, int32_t which, double* out, int32_t ptr_kin
         }
         case SLBM_FIELD_ADJ_POPS:
             return copy_out(c, out, c->abuf[c->adj_cur], 8 * N * sizeof(double), ptr_kind);
+        case SLBM_FIELD_AVG_POPS:
+            if (!c->prim_done) return fail(c, SLBM_ESTATE, "no completed primal_solve");
+            return copy_out(c, out, c->fbar, 8 * N * sizeof(double), ptr_kind);
         default:
             return fail(c, SLBM_EINVAL, "unknown field");
     }
@@ -976,6 +1005,55 @@ int solid_lbm_time_sweeps(slbm_ctx* c, int32_t adjoint, int64_t n, double* ms)
     // solve (d, r, averaged populations) untouched
     if (adjoint) c->adj_cur = cur;
     else c->prim_cur = cur;
+    return SLBM_OK;
+}
+
+int adjoint_solve_vjp(slbm_ctx* c, const double* d_cot, double* grad, int32_t ptr_kind, slbm_solve_info* info)
+{
+    if (!c) return SLBM_EINVAL;
+    if (!d_cot || !grad) return fail(c, SLBM_EINVAL, "d_cot and grad are required");
+    if (!c->prim_done) return fail(c, SLBM_ESTATE, "adjoint_solve_vjp needs a completed primal_solve");
+    int rc = copy_in(c, c->r, d_cot, 2 * c->N * sizeof(double), ptr_kind);
+    if (rc) return rc;
+    // outside the domain the displacement is not defined: its cotangent is ignored
+    hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->r, (const double*)nullptr,
+                       c->masked ? c->code : (const int32_t*)nullptr, c->N, 1.0, c->r);
+    HIPCHK(c, hipGetLastError());
+    rc = do_adjoint(c, info, 1.0);
+    if (rc < 0) return rc;
+    int warn = rc;
+    rc = assemble_grad(c, grad, ptr_kind);
+    if (rc < 0) return rc;
+    return warn;
+}
+
+int solid_lbm_restore_solve(slbm_ctx* c, const double* control, const double* avg_pops, int32_t ptr_kind)
+{
+    if (!c) return SLBM_EINVAL;
+    if (!avg_pops) return fail(c, SLBM_EINVAL, "avg_pops is NULL");
+    int rc = apply_control(c, control, ptr_kind);
+    if (rc) return rc;
+    if ((rc = copy_in(c, c->fbar, avg_pops, 8 * c->N * sizeof(double), ptr_kind))) return rc;
+    if (c->masked)
+        hipLaunchKernelGGL(k_restore<true>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->fbar, c->g, c->code,
+                           c->target, c->obs, c->N, c->dbar, c->r, c->partial);
+    else
+        hipLaunchKernelGGL(k_restore<false>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->fbar, c->g, c->code,
+                           c->target, c->obs, c->N, c->dbar, c->r, c->partial);
+    HIPCHK(c, hipGetLastError());
+    double s;
+    if ((rc = sum_partials(c, &s))) return rc;
+    c->J = 0.5 * s * c->dx2 / c->cbar;
+    c->prim_done = true;
+    c->adj_done = false;
+    return SLBM_OK;
+}
+
+int solid_lbm_objective(slbm_ctx* c, double* J)
+{
+    if (!c || !J) return SLBM_EINVAL;
+    if (!c->prim_done) return fail(c, SLBM_ESTATE, "no completed primal_solve");
+    *J = c->J;
     return SLBM_OK;
 }
 

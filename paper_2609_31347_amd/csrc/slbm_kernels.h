@@ -505,6 +505,36 @@ __global__ __launch_bounds__(kBlock) void k_gather_state(const double* __restric
     }
 }
 
+// A converged state given as averaged populations fbar: its displacement
+// (eq. disp_from_moments), r = d - d* on the observation set, per-block |r|^2.
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_restore(const double* __restrict__ fbar, const double* __restrict__ g,
+                                                   const int32_t* __restrict__ code,
+                                                   const double* __restrict__ target,
+                                                   const uint8_t* __restrict__ obs, int64_t N,
+                                                   double* __restrict__ dbar, double* __restrict__ r,
+                                                   double* __restrict__ partial)
+{
+    int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double s = 0.0;
+    if (n < N) {
+        bool in = MASKED ? code[n] >= 0 : true;
+        double f[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) f[q] = fbar[q * N + n];
+        double d0 = in ? (f[0] - f[2]) + (f[4] - f[5]) + (f[7] - f[6]) + 0.5 * g[n] : 0.0;
+        double d1 = in ? (f[1] - f[3]) + (f[4] + f[5]) - (f[6] + f[7]) + 0.5 * g[N + n] : 0.0;
+        dbar[n] = d0;
+        dbar[N + n] = d1;
+        bool o = in && (obs ? obs[n] != 0 : true);
+        double r0 = o ? d0 - target[n] : 0.0, r1 = o ? d1 - target[N + n] : 0.0;
+        r[n] = r0;
+        r[N + n] = r1;
+        s = r0 * r0 + r1 * r1;
+    }
+    block_sum2(s, 0.0, partial + 2 * (int64_t)blockIdx.x);
+}
+
 // Bared stress (lattice units) of the averaged state fbar (eq. stress_from_moments).
 __global__ __launch_bounds__(kBlock) void k_stress(const double* __restrict__ fbar, const double* __restrict__ g,
                                                   const int32_t* __restrict__ code,

@@ -17,10 +17,12 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ESTATE, ENONFINITE = 0, 1, -1, -2, -3, 
 PERIODIC, MASKED = 0, 1
 CTRL_FORCE_MODES, CTRL_FORCE_NODAL, CTRL_E_NODAL, CTRL_E_SCALAR_SQ = 0, 1, 2, 3
 PTR_HOST, PTR_DEVICE = 0, 1
-FIELD_DISP, FIELD_STRESS, FIELD_ADJ_DISP, FIELD_POPS, FIELD_ADJ_POPS, FIELD_RESIDUAL, FIELD_CUR_DISP = range(7)
+(FIELD_DISP, FIELD_STRESS, FIELD_ADJ_DISP, FIELD_POPS, FIELD_ADJ_POPS, FIELD_RESIDUAL, FIELD_CUR_DISP,
+ FIELD_AVG_POPS) = range(8)
 FIELD_COMPS = {FIELD_DISP: 2, FIELD_STRESS: 3, FIELD_ADJ_DISP: 2, FIELD_POPS: 8, FIELD_ADJ_POPS: 8,
-               FIELD_RESIDUAL: 2, FIELD_CUR_DISP: 2}
-EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_grad", "solid_lbm_set_control",
+               FIELD_RESIDUAL: 2, FIELD_CUR_DISP: 2, FIELD_AVG_POPS: 8}
+EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_grad", "adjoint_solve_vjp",
+           "solid_lbm_restore_solve", "solid_lbm_objective", "solid_lbm_set_control",
            "solid_lbm_run_steps", "solid_lbm_run_adjoint_steps", "solid_lbm_get_field",
            "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_last_error", "solid_lbm_destroy")
 
@@ -68,6 +70,9 @@ def _load():
     lib.solid_lbm_get_field.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32]
     lib.solid_lbm_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.adjoint_solve_vjp.argtypes = [P, P, P, ctypes.c_int32, info]
+    lib.solid_lbm_restore_solve.argtypes = [P, P, P, ctypes.c_int32]
+    lib.solid_lbm_objective.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_last_error.argtypes = [P]
     lib.solid_lbm_last_error.restype = ctypes.c_char_p
     lib.solid_lbm_destroy.argtypes = [P]
@@ -233,6 +238,35 @@ def solid_lbm_time_sweeps(ctx, adjoint, n):
     ms = ctypes.c_double()
     _check(ctx, LIB.solid_lbm_time_sweeps(ctx.handle, int(adjoint), int(n), ctypes.byref(ms)))
     return ms.value
+
+
+def adjoint_solve_vjp(ctx, d_cot, grad=None):
+    """(rc, grad, info): grad = (d dbar / d control)^T d_cot at the last primal solve."""
+    keep = []
+    dp, kind = _arg(d_cot, keep)
+    if grad is None:
+        if kind == PTR_DEVICE:
+            raise ValueError("pass a device grad tensor with a device cotangent")
+        grad = np.zeros(ctx.grad_len())
+    gp = grad.data_ptr() if _is_torch(grad) else grad.ctypes.data
+    info = SolveInfo()
+    rc = _check(ctx, LIB.adjoint_solve_vjp(ctx.handle, dp, gp, kind, ctypes.byref(info)))
+    return rc, grad, info
+
+
+def solid_lbm_restore_solve(ctx, control, avg_pops):
+    keep = []
+    cp, kind = _arg(control, keep)
+    ap, kind2 = _arg(avg_pops, keep)
+    if kind != kind2:
+        raise ValueError("control and avg_pops must live in the same memory kind")
+    return _check(ctx, LIB.solid_lbm_restore_solve(ctx.handle, cp, ap, kind))
+
+
+def solid_lbm_objective(ctx):
+    J = ctypes.c_double()
+    _check(ctx, LIB.solid_lbm_objective(ctx.handle, ctypes.byref(J)))
+    return J.value
 
 
 def solid_lbm_set_tuning(ctx, steps_per_launch=-1, rows_per_wave=0):

@@ -105,7 +105,7 @@ def test_adjoint_fixed_steps_periodic(S, orc):
     phi = S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS)
     q = oracle_problem(orc, p, dx * dx * orc.zero_mean(F))
     cb = orc.cbar(q, tgt)
-    src = orc.source(q, r, dx * dx / cb)
+    src = orc.source(q, orc.zero_mean(r), dx * dx / cb)   # periodic: source mean removed
     ph = q.zeros(8)
     for _ in range(150):
         ph = orc.adj_step(q, ph, src)[0]
@@ -296,7 +296,7 @@ def test_fused_sweeps_match_oracle(S, orc, T, nx, ny, H):
     r = S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL)
     S.solid_lbm_run_adjoint_steps(ctx, steps)
     cb = orc.cbar(q, tgt)
-    src = orc.source(q, r, dx * dx / cb)
+    src = orc.source(q, orc.zero_mean(r), dx * dx / cb)   # periodic: source mean removed
     ph = q.zeros(8)
     for _ in range(steps):
         ph = orc.adj_step(q, ph, src)[0]

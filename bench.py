@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=40)
-    ap.add_argument("--mode", choices=("gradient", "sweeps"), default="gradient",
+    ap.add_argument("--mode", choices=("gradient", "sweeps", "lbfgs"), default="gradient",
                     help="sweeps: time fixed counts of primal/adjoint sweeps and a reference copy "
                          "(for rocprofv3 kernel traces and counters)")
     ap.add_argument("--sweeps", type=int, default=200)
@@ -92,6 +92,41 @@ def sweeps_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def lbfgs_mode(args):
+    """Two-amplitude identification by L-BFGS (Algorithm GBO, paper parameters of
+    benchmark 1) from A = (0.1, 0.1) on N in {128, 256, 512, 1024}: recovered
+    control, its error against A* = (0.7, 0.3), the EOC of that error, and the
+    throughput of all primal + adjoint sweeps of the run."""
+    import torch
+    from paper_2609_31347_amd import inputs as I
+    from paper_2609_31347_amd import slbm as S
+    from paper_2609_31347_amd.autotune import autotune
+    from paper_2609_31347_amd.optimize import PAPER_BENCH1, gpu_objective, lbfgs
+    torch.cuda.set_device(0)
+    props = torch.cuda.get_device_properties(0)
+    rows = []
+    for n in (128, 256, 512, 1024):
+        modes = I.two_mode_basis(n)
+        tgt = I.two_mode_target(n)
+        prob = dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC, target=tgt,
+                    control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes, tol=args.tol,
+                    max_steps=50_000_000)
+        ctx = S.solid_lbm_init(prob)
+        autotune(ctx, prob, np.array([0.1, 0.1]), device=f"{getattr(props, 'gcnArchName', '')}:{props.name}")
+        fun = gpu_objective(ctx)
+        r = lbfgs(fun, np.array([0.1, 0.1]), **PAPER_BENCH1)
+        err = float(np.linalg.norm(r.x - np.array([0.7, 0.3])) / np.linalg.norm([0.7, 0.3]))
+        row = {"n": n, "A": [float(v) for v in r.x], "J": r.J, "rel_error": err, "steps": r.steps,
+               "evaluations": r.evals, "reason": r.reason, "wall_s": round(r.wall_s, 3),
+               "sweeps": fun.sweeps, "mlups": round(fun.sweeps * n * n / r.wall_s / 1e6, 1),
+               "device_mlups": round(fun.sweeps * n * n / (fun.device_ms * 1e-3) / 1e6, 1)}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    ns = [r["n"] for r in rows]
+    eoc = -np.polyfit(np.log(ns), np.log([r["rel_error"] for r in rows]), 1)[0]
+    print(json.dumps({"mode": "lbfgs", "eoc_control_error": round(float(eoc), 4)}), flush=True)
+
+
 def cpu_baseline(n, steps, a):
     """Oracle sweeps on a bounded sample: `steps` primal and `steps` adjoint
     sweeps of the same N x N workload on one core."""
@@ -124,6 +159,8 @@ def main():
     args = parse()
     if args.mode == "sweeps":
         return sweeps_mode(args)
+    if args.mode == "lbfgs":
+        return lbfgs_mode(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
               f"decomposition is a design note, not built)", file=sys.stderr)

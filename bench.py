@@ -42,11 +42,14 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=40)
-    ap.add_argument("--mode", choices=("gradient", "sweeps", "lbfgs"), default="gradient",
+    ap.add_argument("--mode", choices=("gradient", "sweeps", "lbfgs", "batch"), default="gradient",
                     help="sweeps: time fixed counts of primal/adjoint sweeps and a reference copy "
                          "(for rocprofv3 kernel traces and counters)")
     ap.add_argument("--sweeps", type=int, default=200)
     ap.add_argument("--fuse", type=int, default=-1, help="time steps fused per launch (-1 automatic)")
+    ap.add_argument("--instances", type=int, default=96, help="batch mode: number of instances")
+    ap.add_argument("--plates", type=int, default=24, help="batch mode: how many of them are plates")
+    ap.add_argument("--sequential", action="store_true", help="batch mode: also solve them one by one")
     ap.add_argument("--rows", type=int, default=0, help="rows per wave of fused launches (0 automatic)")
     return ap.parse_args()
 
@@ -127,6 +130,76 @@ def lbfgs_mode(args):
     print(json.dumps({"mode": "lbfgs", "eoc_control_error": round(float(eoc), 4)}), flush=True)
 
 
+def batch_instances(count, plates, tol, max_steps=50_000_000):
+    """Seeded mixed batch: instance seeds 0..count-1 draw N from {64, ..., 512};
+    the first count - plates are periodic (two-amplitude control A ~ U[-1,1]^2 or a
+    GRF nodal force, by seed), the rest elliptic plates (semi-axes 1 x 0.6,
+    clamped on the left arc, traction (0, -1e-3) elsewhere, GRF body force)."""
+    from paper_2609_31347_amd import inputs as I
+    from paper_2609_31347_amd import slbm as S
+    sizes = (64, 96, 128, 192, 256, 384, 512)
+    probs, ctrls = [], []
+    for seed in range(count):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        n = int(rng.choice(sizes))
+        if seed < count - plates:
+            if rng.random() < 0.5:
+                probs.append(dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC,
+                                  target=I.two_mode_target(n), control_kind=S.CTRL_FORCE_MODES, n_modes=2,
+                                  force_modes=I.two_mode_basis(n)))
+                ctrls.append(rng.uniform(-1.0, 1.0, 2))
+            else:
+                probs.append(dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC,
+                                  target=I.two_mode_target(n), control_kind=S.CTRL_FORCE_NODAL))
+                ctrls.append(I.grf_force_control(n, seed))
+        else:
+            ny = int(np.ceil(0.6 * n))
+            cp = I.clamped_plate(n, ny)
+            probs.append(dict(nx=n, ny=ny, dx=cp["dx"], E=1.0, nu=0.3, domain=S.MASKED,
+                              node_mask=cp["active"].astype(np.uint8), link_bc=cp["bc"], link_wall=cp["wall"],
+                              link_normal=cp["normal"], target=np.zeros((2, ny, n)), normalize_objective=0,
+                              control_kind=S.CTRL_FORCE_NODAL))
+            ctrls.append(I.grf(n, ny, cp["dx"], 0.05, 0.1, seed, comps=2) * cp["active"])
+        probs[-1].update(tol=tol, max_steps=max_steps)
+    return probs, ctrls
+
+
+def batch_mode(args):
+    """Batched gradient evaluation of a seeded mix of uneven instances: one batch
+    (shared launches, per-instance convergence) against the same instances
+    solved one after another."""
+    import torch
+    from paper_2609_31347_amd import slbm as S
+    from paper_2609_31347_amd.autotune import autotune_batch
+    torch.cuda.set_device(0)
+    probs, ctrls = batch_instances(args.instances, args.plates, args.tol)
+    cells = [p["nx"] * p["ny"] for p in probs]
+    batch = S.solid_lbm_batch_init(probs)
+    tune = autotune_batch(batch, ctrls)
+    t0 = time.perf_counter()
+    rc, J, grads, pi, ai = S.batch_objective_and_grad(batch, ctrls)
+    wall = time.perf_counter() - t0
+    lups = sum(c * (p.sweeps + a.sweeps) for c, p, a in zip(cells, pi, ai))
+    out = {"mode": "batch", "instances": len(probs), "plates": args.plates, "tol": args.tol,
+           "total_cells": int(sum(cells)), "rc": rc, "tuning": tune,
+           "all_converged": bool(all(p.converged and a.converged for p, a in zip(pi, ai))),
+           "batch_wall_s": round(wall, 3), "batch_mlups": round(lups / wall / 1e6, 1),
+           "max_steps": int(max(p.steps for p in pi)), "primal_device_ms": round(pi[0].device_ms, 1),
+           "adjoint_device_ms": round(ai[0].device_ms, 1)}
+    if args.sequential:
+        t0 = time.perf_counter()
+        seq_lups = 0
+        for p, c, cl in zip(probs, ctrls, cells):
+            ctx = S.solid_lbm_init(p)
+            r = S.objective_and_grad(ctx, c)
+            seq_lups += cl * (r[3].sweeps + r[4].sweeps)
+            del ctx
+        seq = time.perf_counter() - t0
+        out.update({"sequential_wall_s": round(seq, 3), "sequential_mlups": round(seq_lups / seq / 1e6, 1),
+                    "speedup": round(seq / wall, 2)})
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(n, steps, a):
     """Oracle sweeps on a bounded sample: `steps` primal and `steps` adjoint
     sweeps of the same N x N workload on one core."""
@@ -161,6 +234,8 @@ def main():
         return sweeps_mode(args)
     if args.mode == "lbfgs":
         return lbfgs_mode(args)
+    if args.mode == "batch":
+        return batch_mode(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
               f"decomposition is a design note, not built)", file=sys.stderr)

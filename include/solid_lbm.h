@@ -228,6 +228,44 @@ const char *solid_lbm_last_error(const slbm_ctx *ctx);
 /* Frees every device buffer of ctx (NULL is a no-op). */
 void solid_lbm_destroy(slbm_ctx *ctx);
 
+/* ---- batches: many independent problems solved together ----
+ *
+ * A batch holds up to 128 problems of any sizes (periodic or plate; force
+ * controls or E = alpha^2) that share tol, max_steps and stream.  All of them
+ * advance in the same launches: one launch per time step (or per T fused
+ * steps for the periodic ones) covers every instance still running, each with
+ * its own residual test every K_i steps and its own stop.  Results equal those
+ * of the same problems solved one by one (the per-instance arithmetic is the
+ * same). */
+typedef struct slbm_batch slbm_batch;
+
+/* Creates a batch from count problems (validated and copied as by
+ * solid_lbm_init).  Returns SLBM_OK and *out or a negative code. */
+int solid_lbm_batch_init(const slbm_problem *problems, int32_t count, slbm_batch **out);
+
+/* Objective and gradient of every instance: controls[i] (length per the
+ * instance's control kind), J[i] (host), grads[i] (NULL array = J only);
+ * controls and grads per ptr_kind; primal_info / adjoint_info: NULL or arrays
+ * of count entries (device_ms and wall_s are those of the whole batch). */
+int batch_objective_and_grad(slbm_batch *batch, const double *const *controls, double *J,
+                             double *const *grads, int32_t ptr_kind, slbm_solve_info *primal_info,
+                             slbm_solve_info *adjoint_info);
+
+/* Fused launch shape of the batch's periodic instances (as solid_lbm_set_tuning). */
+int solid_lbm_batch_set_tuning(slbm_batch *batch, int32_t steps_per_launch, int32_t rows_per_wave);
+
+/* Times n batched primal (adjoint = 0) or adjoint sweeps of every instance on
+ * whatever the buffers hold (zeros after init); the instance states are
+ * invalidated (the next solve starts from its control as always). */
+int solid_lbm_batch_time_sweeps(slbm_batch *batch, int32_t adjoint, int64_t n, double *ms);
+
+/* The context of instance i (owned by the batch) for solid_lbm_get_field and
+ * the other per-context calls; NULL if i is out of range. */
+slbm_ctx *solid_lbm_batch_instance(slbm_batch *batch, int32_t i);
+
+const char *solid_lbm_batch_last_error(const slbm_batch *batch);
+void solid_lbm_batch_destroy(slbm_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

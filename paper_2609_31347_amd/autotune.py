@@ -68,3 +68,23 @@ def autotune(ctx, problem, control, sweeps=96, device="gpu0", use_cache=True, ca
         cache[key] = out
         _save(cache)
     return dict(out, cached=False)
+
+
+def autotune_batch(batch, controls=None, sweeps=48,
+                   candidates=((8, 24), (8, 48), (8, 96), (6, 24), (6, 48), (4, 24), (1, 0))):
+    """Chooses the fused shape (T, H) of a batch's periodic instances by timing
+    batched primal sweeps of all instances (plates run their single steps in
+    the same timing); near-ties go to the earlier candidate.  Returns
+    {"T", "H", "us"} with the time per batched step."""
+    from . import slbm as S
+    times = {}
+    for T, H in candidates:
+        S.solid_lbm_batch_set_tuning(batch, T, H)
+        t = max(T, 1)
+        S.solid_lbm_batch_time_sweeps(batch, 0, 2 * t)
+        n = max(sweeps // t, 1) * t
+        times[(T, H)] = S.solid_lbm_batch_time_sweeps(batch, 0, n) / n * 1e3
+    fastest = min(times.values())
+    best = next(c for c in candidates if times[c] <= fastest * (1.0 + TIE))
+    S.solid_lbm_batch_set_tuning(batch, best[0], best[1])
+    return {"T": best[0], "H": best[1], "us": {f"{k[0]},{k[1]}": round(v, 3) for k, v in times.items()}}

@@ -540,6 +540,8 @@ int project_source(slbm_ctx* c)
     return SLBM_OK;
 }
 
+int adjoint_finalize(slbm_ctx* c, int X, double scale);
+
 int do_adjoint(slbm_ctx* c, slbm_solve_info* info, double scale_override = -1.0)
 {
     if (!c->prim_done) return fail(c, SLBM_ESTATE, "adjoint_solve needs a completed primal_solve");
@@ -558,8 +560,25 @@ int do_adjoint(slbm_ctx* c, slbm_solve_info* info, double scale_override = -1.0)
     rc = run_loop(c, true, 0, c->max_steps, use_tol, &t, &res, &conv, &dms, &X);
     c->cbar = saved_cbar;
     if (rc) return rc;
+    if ((rc = adjoint_finalize(c, X, scale_override > 0.0 ? scale_override : c->dx2 / c->cbar))) return rc;
+    auto w1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->steps = t;
+        info->sweeps = t + 1;
+        info->residual = use_tol ? res : 0.0;
+        info->wall_s = std::chrono::duration<double>(w1 - w0).count();
+        info->device_ms = dms;
+        info->converged = conv ? 1 : 0;
+    }
+    return (use_tol && !conv) ? SLBM_NOT_CONVERGED : SLBM_OK;
+}
+
+// Two-step-averaged adjoint from X = phi^C(t), X^1 = phi^C(t+1) and the local
+// gradient pieces (eq. optimality); source scale s = dx^2 / Cbar (objective)
+// or 1 (cotangent).
+int adjoint_finalize(slbm_ctx* c, int X, double scale)
+{
     bool wantE = c->kind == SLBM_CTRL_E_NODAL || c->kind == SLBM_CTRL_E_SCALAR_SQ;
-    double scale = scale_override > 0.0 ? scale_override : c->dx2 / c->cbar;
     if (c->masked)
         hipLaunchKernelGGL(k_adjoint_finalize<true>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->abuf[X],
                            c->abuf[X ^ 1], c->code, c->bnodes, c->fbar, c->r, c->g,
@@ -574,16 +593,7 @@ int do_adjoint(slbm_ctx* c, slbm_solve_info* info, double scale_override = -1.0)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->adj_cur = X ^ 1;
     c->adj_done = true;
-    auto w1 = std::chrono::steady_clock::now();
-    if (info) {
-        info->steps = t;
-        info->sweeps = t + 1;
-        info->residual = use_tol ? res : 0.0;
-        info->wall_s = std::chrono::duration<double>(w1 - w0).count();
-        info->device_ms = dms;
-        info->converged = conv ? 1 : 0;
-    }
-    return (use_tol && !conv) ? SLBM_NOT_CONVERGED : SLBM_OK;
+    return SLBM_OK;
 }
 
 // Gradient per control kind from the local pieces dJdF / dJdE.
@@ -1081,6 +1091,513 @@ void solid_lbm_destroy(slbm_ctx* c)
     for (hipEvent_t e : {c->ev[0], c->ev[1], c->t0, c->t1})
         if (e) (void)hipEventDestroy(e);
     delete c;
+}
+
+}  // extern "C"
+
+// ======================================================================= batches
+struct slbm_batch {
+    std::vector<slbm_ctx*> ctx;
+    hipStream_t stream = nullptr;
+    Status* status = nullptr;      // one Status per instance, contiguous
+    Status* h_status = nullptr;    // pinned, 2 slots of B
+    BatchInst* d_inst = nullptr;
+    std::vector<BatchInst> h_inst;
+    int2* d_all = nullptr;         // every instance: (instance, block) of a single-step sweep
+    int2* d_plate = nullptr;       // plate instances only
+    int2* d_tb = nullptr;          // periodic instances: (instance, strip) of a fused launch
+    int64_t n_all = 0, n_plate = 0, n_tb = 0, tb_cap = 0;
+    int tb_T = -1, tb_H = 0;       // tuning (-1 / 0: automatic)
+    int T = 1, H = 0;              // effective fused shape of the current tables
+    bool any_periodic = false, any_plate = false;
+    double tol = 0.0;
+    int64_t max_steps = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
+    std::string err;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+thread_local std::string g_batch_init_error;
+
+int bfail(slbm_batch* b, int code, const std::string& msg)
+{
+    if (b) b->err = msg;
+    else g_batch_init_error = msg;
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                      \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return bfail(b, SLBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+int balloc(slbm_batch* b, void** p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+    if (e != hipSuccess) return bfail(b, SLBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    b->allocs.push_back(*p);
+    return SLBM_OK;
+}
+
+// Fused shape for the batch: periodic instances share one (T, H).
+void batch_shape(slbm_batch* b, int* T, int* H)
+{
+    int t = b->tb_T < 0 ? 8 : b->tb_T;
+    if (t != 2 && t != 4 && t != 6 && t != 8) t = 1;
+    if (!b->any_periodic) t = 1;
+    int h = b->tb_H;
+    if (h <= 0) {
+        int maxny = 0;
+        for (auto* c : b->ctx)
+            if (!c->masked) maxny = std::max(maxny, c->ny);
+        h = maxny <= 1536 ? 24 : 48;
+    }
+    if (t > 1 && h < 2 * t) h = 2 * t;
+    *T = t;
+    *H = h;
+}
+
+// (Re)builds the per-instance table for the current controls and the fused
+// strip table for shape (T, H); uploads both.
+int batch_tables(slbm_batch* b, bool adjoint)
+{
+    int T, H;
+    batch_shape(b, &T, &H);
+    const int B = (int)b->ctx.size();
+    std::vector<int2> tb;
+    for (int i = 0; i < B; ++i) {
+        slbm_ctx* c = b->ctx[i];
+        BatchInst I;
+        std::memset(&I, 0, sizeof(I));
+        SweepArgs a = base_args(c);
+        a.status = b->status + i;
+        for (int par = 0; par < 2; ++par) {
+            SweepArgs pa = a, aa = a;
+            pa.src = c->fbuf[par];
+            pa.dst = c->fbuf[par ^ 1];
+            pa.g = c->g;
+            aa.src = c->abuf[par];
+            aa.dst = c->abuf[par ^ 1];
+            aa.g = c->r;
+            aa.scale = c->dx2 / c->cbar;
+            I.prim[par] = pa;
+            I.adj[par] = aa;
+            for (int k = 0; k < 2; ++k) {
+                const SweepArgs& s = k ? aa : pa;
+                TBArgs t;
+                t.src = s.src;
+                t.dst = s.dst;
+                t.g = s.g;
+                t.status = b->status + i;
+                t.nx = c->nx;
+                t.ny = c->ny;
+                t.H = std::min(H, c->ny);
+                t.N = c->N;
+                t.k11 = s.k11;
+                t.ks = s.ks;
+                t.kd = s.kd;
+                t.scale = s.scale;
+                (k ? I.tadj : I.tprim)[par] = t;
+            }
+        }
+        I.status = b->status + i;
+        I.inv_nx = c->inv_nx;
+        I.masked = c->masked ? 1 : 0;
+        I.nblk = c->nblk;
+        if (!c->masked && T > 1) {
+            int V = 64 - 2 * T;
+            int sx = (c->nx + V - 1) / V, sy = (c->ny + std::min(H, c->ny) - 1) / std::min(H, c->ny);
+            I.sx = sx;
+            for (int k = 0; k < sx * sy; ++k) tb.push_back(make_int2(i, k));
+        }
+        b->h_inst[i] = I;
+    }
+    (void)adjoint;
+    BHIPCHK(b, hipMemcpyAsync(b->d_inst, b->h_inst.data(), B * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream));
+    if ((int64_t)tb.size() > b->tb_cap) {
+        void* q = nullptr;
+        int rc = balloc(b, &q, tb.size() * sizeof(int2));
+        if (rc) return rc;
+        b->d_tb = (int2*)q;
+        b->tb_cap = (int64_t)tb.size();
+    }
+    if (!tb.empty())
+        BHIPCHK(b, hipMemcpyAsync(b->d_tb, tb.data(), tb.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->n_tb = (int64_t)tb.size();
+    b->T = T;
+    b->H = H;
+    return SLBM_OK;
+}
+
+void launch_batch_step(slbm_batch* b, bool adjoint, const int2* table, int64_t nblocks, int pp, int pl,
+                       uint64_t lo, uint64_t hi)
+{
+    if (nblocks <= 0) return;
+    if (adjoint)
+        hipLaunchKernelGGL(k_sweep_batch<true>, dim3((unsigned)nblocks), dim3(kBlock), 0, b->stream, b->d_inst,
+                           table, pp, pl, lo, hi);
+    else
+        hipLaunchKernelGGL(k_sweep_batch<false>, dim3((unsigned)nblocks), dim3(kBlock), 0, b->stream, b->d_inst,
+                           table, pp, pl, lo, hi);
+}
+
+void launch_batch_fused(slbm_batch* b, bool adjoint, int pp)
+{
+    dim3 grid((unsigned)b->n_tb), block(64);
+#define BTB_CASE(TT)                                                                                       \
+    case TT:                                                                                               \
+        if (adjoint) hipLaunchKernelGGL((k_sweep_tb_batch<TT, true>), grid, block, 0, b->stream, b->d_inst, \
+                                        b->d_tb, pp);                                                      \
+        else hipLaunchKernelGGL((k_sweep_tb_batch<TT, false>), grid, block, 0, b->stream, b->d_inst,       \
+                                b->d_tb, pp);                                                              \
+        break;
+    switch (b->T) {
+        BTB_CASE(2)
+        BTB_CASE(4)
+        BTB_CASE(6)
+        BTB_CASE(8)
+    }
+#undef BTB_CASE
+}
+
+// Advances every instance from buffer 0 in lock-step (step index s), each
+// with its own residual checks every K_i steps and its own stop flag; plain
+// runs between checks are fused for periodic instances.  Afterwards, for each
+// instance: t (its final step), X (buffer holding its input of step t) and
+// whether it converged.
+int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::vector<int>& x_out,
+               std::vector<char>& conv, std::vector<double>& res, double* dev_ms)
+{
+    const int B = (int)b->ctx.size();
+    hipLaunchKernelGGL(k_status_reset_all, dim3((B + 127) / 128), dim3(128), 0, b->stream, b->status, B);
+    BHIPCHK(b, hipGetLastError());
+    int rc = batch_tables(b, adjoint);
+    if (rc) return rc;
+    const int64_t last = b->max_steps;
+    const bool use_tol = b->tol > 0.0;
+    std::vector<int64_t> K(B);
+    for (int i = 0; i < B; ++i) K[i] = b->ctx[i]->K;
+    std::vector<char> active(B, 1);
+    std::vector<std::vector<std::pair<int64_t, int>>> checks(B);
+    std::vector<int> last_in(B, 0);
+    int pp = 0, pl = 0, slot = 0, polls = 0;
+    int64_t s = 0;
+    BHIPCHK(b, hipEventRecord(b->t0, b->stream));
+    auto any_active = [&]() {
+        for (char a : active)
+            if (a) return true;
+        return false;
+    };
+    while (s <= last && any_active()) {
+        uint64_t lo = 0, hi = 0;
+        if (use_tol && s > 0)
+            for (int i = 0; i < B; ++i)
+                if (active[i] && s % K[i] == 0) (i < 64 ? lo : hi) |= 1ull << (i & 63);
+        if (lo || hi || s == last) {
+            launch_batch_step(b, adjoint, b->d_all, b->n_all, pp, pl, lo, hi);
+            for (int i = 0; i < B; ++i) {
+                int par = b->ctx[i]->masked ? pl : pp;
+                if ((i < 64 ? (lo >> i) : (hi >> (i - 64))) & 1ull) checks[i].emplace_back(s, par);
+                if (s == last) last_in[i] = par;
+            }
+            if (lo || hi) {
+                hipLaunchKernelGGL(k_residual_batch, dim3(B), dim3(kBlock), 0, b->stream, b->d_inst,
+                                   adjoint ? 1 : 0, lo, hi, b->tol, s);
+                BHIPCHK(b, hipMemcpyAsync(b->h_status + slot * B, b->status, B * sizeof(Status),
+                                          hipMemcpyDeviceToHost, b->stream));
+                BHIPCHK(b, hipEventRecord(b->ev[slot], b->stream));
+                if (polls >= 1) {
+                    BHIPCHK(b, hipEventSynchronize(b->ev[slot ^ 1]));
+                    for (int i = 0; i < B; ++i)
+                        if (b->h_status[(slot ^ 1) * B + i].stop) active[i] = 0;
+                }
+                ++polls;
+                slot ^= 1;
+            }
+            pp ^= 1;
+            pl ^= 1;
+            ++s;
+            continue;
+        }
+        // plain steps until the next check of an active instance (or the final step)
+        int64_t next = last;
+        if (use_tol)
+            for (int i = 0; i < B; ++i)
+                if (active[i]) next = std::min(next, (s / K[i] + 1) * K[i]);
+        int64_t run = next - s;
+        const int T = b->T;
+        if (T > 1 && run >= T) {
+            int64_t nT = run / T;
+            for (int64_t j = 0; j < nT; ++j) {
+                launch_batch_fused(b, adjoint, pp);
+                pp ^= 1;
+                for (int k = 0; k < T; ++k) {
+                    launch_batch_step(b, adjoint, b->d_plate, b->n_plate, pp, pl, 0, 0);
+                    pl ^= 1;
+                }
+            }
+            s += nT * T;
+            run -= nT * T;
+        }
+        for (int64_t j = 0; j < run; ++j) {
+            launch_batch_step(b, adjoint, b->d_all, b->n_all, pp, pl, 0, 0);
+            pp ^= 1;
+            pl ^= 1;
+            ++s;
+        }
+        BHIPCHK(b, hipGetLastError());
+    }
+    BHIPCHK(b, hipEventRecord(b->t1, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    float f = 0.f;
+    BHIPCHK(b, hipEventElapsedTime(&f, b->t0, b->t1));
+    if (dev_ms) *dev_ms = f;
+    std::vector<Status> st(B);
+    BHIPCHK(b, hipMemcpy(st.data(), b->status, B * sizeof(Status), hipMemcpyDeviceToHost));
+    t_out.assign(B, last);
+    x_out.assign(B, 0);
+    conv.assign(B, 0);
+    res.assign(B, 0.0);
+    for (int i = 0; i < B; ++i) {
+        res[i] = st[i].res;
+        if (use_tol && st[i].stop) {
+            int xin = -1;
+            for (auto& ck : checks[i])
+                if (ck.first == st[i].t_conv) xin = ck.second;
+            if (xin < 0) return bfail(b, SLBM_EHIP, "internal: converged step without a check sweep");
+            t_out[i] = st[i].t_conv;
+            x_out[i] = xin;
+            conv[i] = 1;
+        } else {
+            x_out[i] = last_in[i];
+        }
+    }
+    return SLBM_OK;
+}
+
+int batch_solve(slbm_batch* b, const double* const* controls, int ptr_kind, double* J, double* const* grads,
+                slbm_solve_info* pinfo, slbm_solve_info* ainfo)
+{
+    const int B = (int)b->ctx.size();
+    int rc;
+    auto w0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < B; ++i) {
+        slbm_ctx* c = b->ctx[i];
+        if ((rc = apply_control(c, controls[i], ptr_kind)) || (rc = reset_primal(c, nullptr, ptr_kind)))
+            return bfail(b, rc, "instance " + std::to_string(i) + ": " + c->err);
+    }
+    std::vector<int64_t> t;
+    std::vector<int> X;
+    std::vector<char> conv;
+    std::vector<double> res;
+    double dms = 0.0;
+    if ((rc = batch_loop(b, false, t, X, conv, res, &dms))) return rc;
+    bool all_conv = true;
+    for (int i = 0; i < B; ++i) {
+        slbm_ctx* c = b->ctx[i];
+        if ((rc = finalize_primal(c, X[i]))) return bfail(b, rc, "instance " + std::to_string(i) + ": " + c->err);
+        c->prim_cur = X[i] ^ 1;
+        c->prim_done = true;
+        c->adj_done = false;
+        if (J) J[i] = c->J;
+        all_conv = all_conv && conv[i];
+    }
+    auto w1 = std::chrono::steady_clock::now();
+    if (pinfo)
+        for (int i = 0; i < B; ++i) {
+            pinfo[i].steps = t[i];
+            pinfo[i].sweeps = t[i] + 1;
+            pinfo[i].residual = res[i];
+            pinfo[i].wall_s = std::chrono::duration<double>(w1 - w0).count();
+            pinfo[i].device_ms = dms;
+            pinfo[i].converged = conv[i];
+        }
+    if (!grads) return (b->tol > 0.0 && !all_conv) ? SLBM_NOT_CONVERGED : SLBM_OK;
+    // adjoints
+    for (int i = 0; i < B; ++i) {
+        slbm_ctx* c = b->ctx[i];
+        if ((rc = adjoint_prepare(c)) || (rc = project_source(c)))
+            return bfail(b, rc, "instance " + std::to_string(i) + ": " + c->err);
+    }
+    if ((rc = batch_loop(b, true, t, X, conv, res, &dms))) return rc;
+    for (int i = 0; i < B; ++i) {
+        slbm_ctx* c = b->ctx[i];
+        if ((rc = adjoint_finalize(c, X[i], c->dx2 / c->cbar)) || (rc = assemble_grad(c, grads[i], ptr_kind)))
+            return bfail(b, rc, "instance " + std::to_string(i) + ": " + c->err);
+        all_conv = all_conv && conv[i];
+    }
+    auto w2 = std::chrono::steady_clock::now();
+    if (ainfo)
+        for (int i = 0; i < B; ++i) {
+            ainfo[i].steps = t[i];
+            ainfo[i].sweeps = t[i] + 1;
+            ainfo[i].residual = res[i];
+            ainfo[i].wall_s = std::chrono::duration<double>(w2 - w1).count();
+            ainfo[i].device_ms = dms;
+            ainfo[i].converged = conv[i];
+        }
+    return (b->tol > 0.0 && !all_conv) ? SLBM_NOT_CONVERGED : SLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int solid_lbm_batch_init(const slbm_problem* problems, int32_t count, slbm_batch** out)
+{
+    if (!out) return bfail(nullptr, SLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!problems || count < 1 || count > 128) return bfail(nullptr, SLBM_EINVAL, "count must be 1..128");
+    for (int i = 0; i < count; ++i) {
+        const slbm_problem& p = problems[i];
+        if (p.control_kind == SLBM_CTRL_E_NODAL)
+            return bfail(nullptr, SLBM_EINVAL, "batches take force controls or E = alpha^2 (not E fields)");
+        if (p.tol != problems[0].tol || p.max_steps != problems[0].max_steps || p.stream != problems[0].stream)
+            return bfail(nullptr, SLBM_EINVAL, "all problems of a batch share tol, max_steps and stream");
+    }
+    slbm_batch* b = new slbm_batch();
+    b->stream = (hipStream_t)problems[0].stream;
+    b->tol = problems[0].tol;
+    b->max_steps = problems[0].max_steps;
+    for (int i = 0; i < count; ++i) {
+        slbm_ctx* c = nullptr;
+        int rc = solid_lbm_init(&problems[i], &c);
+        if (rc) {
+            std::string m = "instance " + std::to_string(i) + ": " + g_init_error;
+            solid_lbm_batch_destroy(b);
+            return bfail(nullptr, rc, m);
+        }
+        b->ctx.push_back(c);
+    }
+    int rc = SLBM_OK;
+    void* q = nullptr;
+    if (!rc && !(rc = balloc(b, &q, count * sizeof(Status)))) b->status = (Status*)q;
+    if (!rc && !(rc = balloc(b, &q, count * sizeof(BatchInst)))) b->d_inst = (BatchInst*)q;
+    std::vector<int2> all, plate;
+    for (int i = 0; i < count; ++i) {
+        slbm_ctx* c = b->ctx[i];
+        c->status = b->status + i;  // the instance's sweeps and the batch share its flag
+        for (int64_t k = 0; k < c->nblk; ++k) {
+            all.push_back(make_int2(i, (int)k));
+            if (c->masked) plate.push_back(make_int2(i, (int)k));
+        }
+        if (c->masked) b->any_plate = true;
+        else b->any_periodic = true;
+    }
+    if (!rc && !(rc = balloc(b, &q, all.size() * sizeof(int2)))) b->d_all = (int2*)q;
+    if (!rc && !(rc = balloc(b, &q, std::max<size_t>(1, plate.size()) * sizeof(int2)))) b->d_plate = (int2*)q;
+    if (!rc && hipMemcpy(b->d_all, all.data(), all.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        rc = SLBM_EHIP;
+    if (!rc && !plate.empty() &&
+        hipMemcpy(b->d_plate, plate.data(), plate.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        rc = SLBM_EHIP;
+    if (!rc && hipHostMalloc((void**)&b->h_status, 2 * count * sizeof(Status), hipHostMallocDefault) != hipSuccess)
+        rc = SLBM_EHIP;
+    if (!rc && (hipEventCreate(&b->ev[0]) != hipSuccess || hipEventCreate(&b->ev[1]) != hipSuccess ||
+                hipEventCreate(&b->t0) != hipSuccess || hipEventCreate(&b->t1) != hipSuccess))
+        rc = SLBM_EHIP;
+    if (rc) {
+        solid_lbm_batch_destroy(b);
+        return bfail(nullptr, rc, "batch allocation failed");
+    }
+    b->n_all = (int64_t)all.size();
+    b->n_plate = (int64_t)plate.size();
+    b->h_inst.resize(count);
+    // defined contents for timing sweeps before any solve
+    for (auto* c : b->ctx) {
+        for (double* a : {c->fbuf[0], c->fbuf[1], c->abuf[0], c->abuf[1]})
+            if (!rc) rc = fill(c, a, 8 * c->N, 0.0);
+        if (!rc) rc = fill(c, c->r, 2 * c->N, 0.0);
+    }
+    if (rc || hipStreamSynchronize(b->stream) != hipSuccess) {
+        solid_lbm_batch_destroy(b);
+        return bfail(nullptr, rc ? rc : SLBM_EHIP, "batch initialisation failed");
+    }
+    *out = b;
+    return SLBM_OK;
+}
+
+int batch_objective_and_grad(slbm_batch* b, const double* const* controls, double* J, double* const* grads,
+                             int32_t ptr_kind, slbm_solve_info* primal_info, slbm_solve_info* adjoint_info)
+{
+    if (!b) return SLBM_EINVAL;
+    if (!controls || !J) return bfail(b, SLBM_EINVAL, "controls and J are required");
+    return batch_solve(b, controls, ptr_kind, J, grads, primal_info, adjoint_info);
+}
+
+int solid_lbm_batch_set_tuning(slbm_batch* b, int32_t steps_per_launch, int32_t rows_per_wave)
+{
+    if (!b) return SLBM_EINVAL;
+    if (!(steps_per_launch == -1 || steps_per_launch == 0 || steps_per_launch == 1 || steps_per_launch == 2 ||
+          steps_per_launch == 4 || steps_per_launch == 6 || steps_per_launch == 8))
+        return bfail(b, SLBM_EINVAL, "steps_per_launch must be -1, 0, 1, 2, 4, 6 or 8");
+    if (rows_per_wave < 0) return bfail(b, SLBM_EINVAL, "rows_per_wave must be >= 0");
+    b->tb_T = steps_per_launch;
+    b->tb_H = rows_per_wave;
+    return SLBM_OK;
+}
+
+int solid_lbm_batch_time_sweeps(slbm_batch* b, int32_t adjoint, int64_t n, double* ms)
+{
+    if (!b || !ms) return SLBM_EINVAL;
+    if (n < 1) return bfail(b, SLBM_EINVAL, "n must be >= 1");
+    const int B = (int)b->ctx.size();
+    hipLaunchKernelGGL(k_status_reset_all, dim3((B + 127) / 128), dim3(128), 0, b->stream, b->status, B);
+    int rc = batch_tables(b, adjoint != 0);
+    if (rc) return rc;
+    int pp = 0, pl = 0;
+    BHIPCHK(b, hipEventRecord(b->t0, b->stream));
+    for (int64_t s = 0; s < n;) {
+        if (b->T > 1 && n - s >= b->T) {
+            launch_batch_fused(b, adjoint != 0, pp);
+            pp ^= 1;
+            for (int k = 0; k < b->T; ++k) {
+                launch_batch_step(b, adjoint != 0, b->d_plate, b->n_plate, pp, pl, 0, 0);
+                pl ^= 1;
+            }
+            s += b->T;
+        } else {
+            launch_batch_step(b, adjoint != 0, b->d_all, b->n_all, pp, pl, 0, 0);
+            pp ^= 1;
+            pl ^= 1;
+            ++s;
+        }
+    }
+    BHIPCHK(b, hipGetLastError());
+    BHIPCHK(b, hipEventRecord(b->t1, b->stream));
+    BHIPCHK(b, hipEventSynchronize(b->t1));
+    float f = 0.f;
+    BHIPCHK(b, hipEventElapsedTime(&f, b->t0, b->t1));
+    *ms = f;
+    // the states advanced by an unknown parity: later solves restart from their controls
+    for (auto* c : b->ctx) c->prim_valid = false;
+    return SLBM_OK;
+}
+
+slbm_ctx* solid_lbm_batch_instance(slbm_batch* b, int32_t i)
+{
+    if (!b || i < 0 || i >= (int32_t)b->ctx.size()) return nullptr;
+    return b->ctx[i];
+}
+
+const char* solid_lbm_batch_last_error(const slbm_batch* b) { return b ? b->err.c_str() : g_batch_init_error.c_str(); }
+
+void solid_lbm_batch_destroy(slbm_batch* b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto* c : b->ctx) solid_lbm_destroy(c);
+    for (void* p : b->allocs) (void)hipFree(p);
+    if (b->h_status) (void)hipHostFree(b->h_status);
+    for (hipEvent_t e : {b->ev[0], b->ev[1], b->t0, b->t1})
+        if (e) (void)hipEventDestroy(e);
+    delete b;
 }
 
 }  // extern "C"

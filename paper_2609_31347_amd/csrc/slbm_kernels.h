@@ -95,118 +95,125 @@ __device__ __forceinline__ void neighbours(int ix, int iy, int nx, int ny, int64
 }
 
 // ---------------------------------------------------------------- primal sweep
+// One node of a primal sweep; num/den receive its residual terms on check sweeps.
+template <bool MASKED, bool EFIELD, bool CHECK>
+__device__ __forceinline__ void primal_node(const SweepArgs& a, int64_t n, double inv_nx, double& num,
+                                            double& den)
+{
+    int code = MASKED ? a.code[n] : 0;
+    if (code < 0) return;
+    int iy = row_of(n, a.nx, inv_nx);
+    int ix = (int)(n - (int64_t)iy * a.nx);
+    int64_t idx[8];
+    neighbours(ix, iy, a.nx, a.ny, idx, +1);
+    const int64_t N = a.N;
+    double f[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) f[q] = a.src[q * N + idx[q]];
+    double gx = a.g[n], gy = a.g[N + n];
+    double d0, d1;
+    if (!MASKED || code == 0) {
+        double k11 = a.k11, ks = a.ks, kd = a.kd;
+        if (EFIELD) {
+            Relax<double> r = relax_from_E<double>(a.E[n], a.nu, false);
+            k11 = r.k11; ks = r.ks; kd = r.kd;
+        }
+        collide_bulk(f, gx, gy, k11, ks, kd, d0, d1);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a.dst[q * N + n] = f[q];
+    } else {
+        const BNode* bn = a.bnodes + (code - 1);
+        Relax<double> r = relax_from_E<double>(EFIELD ? a.E[n] : a.E0, a.nu, true);
+        double gg[2] = {gx, gy}, fC[8], h[8], mb[5];
+        node_map<double>(f, gg, r, bn, true, fC, h, mb);
+        d0 = mb[0];
+        d1 = mb[1];
+        uint32_t cut = bn->cut;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            a.dst[q * N + n] = fC[q];
+            if ((cut >> q) & 1u) a.dst[q * N + idx[q]] = h[q];   // ghost slot of the cut link
+        }
+    }
+    if (CHECK) {
+        double s0 = a.snap[n], s1 = a.snap[N + n];
+        num = (d0 - s0) * (d0 - s0) + (d1 - s1) * (d1 - s1);
+        den = d0 * d0 + d1 * d1;
+        a.snap[n] = d0;
+        a.snap[N + n] = d1;
+    }
+}
+
 template <bool MASKED, bool EFIELD, bool CHECK>
 __global__ __launch_bounds__(kBlock) void k_primal(SweepArgs a, double inv_nx)
 {
     if (a.status->stop) return;
     int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double num = 0.0, den = 0.0;
-    if (n < a.N) {
-        int code = MASKED ? a.code[n] : 0;
-        if (code >= 0) {
-            int iy = row_of(n, a.nx, inv_nx);
-            int ix = (int)(n - (int64_t)iy * a.nx);
-            int64_t idx[8];
-            neighbours(ix, iy, a.nx, a.ny, idx, +1);
-            const int64_t N = a.N;
-            double f[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) f[q] = a.src[q * N + idx[q]];
-            double gx = a.g[n], gy = a.g[N + n];
-            double d0, d1;
-            if (!MASKED || code == 0) {
-                double k11 = a.k11, ks = a.ks, kd = a.kd;
-                if (EFIELD) {
-                    Relax<double> r = relax_from_E<double>(a.E[n], a.nu, false);
-                    k11 = r.k11; ks = r.ks; kd = r.kd;
-                }
-                collide_bulk(f, gx, gy, k11, ks, kd, d0, d1);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) a.dst[q * N + n] = f[q];
-            } else {
-                const BNode* bn = a.bnodes + (code - 1);
-                Relax<double> r = relax_from_E<double>(EFIELD ? a.E[n] : a.E0, a.nu, true);
-                double gg[2] = {gx, gy}, fC[8], h[8], mb[5];
-                node_map<double>(f, gg, r, bn, true, fC, h, mb);
-                d0 = mb[0];
-                d1 = mb[1];
-                int64_t back[8];
-                neighbours(ix, iy, a.nx, a.ny, back, +1);
-                uint32_t cut = bn->cut;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    a.dst[q * N + n] = fC[q];
-                    if ((cut >> q) & 1u) a.dst[q * N + back[q]] = h[q];
-                }
-            }
-            if (CHECK) {
-                double s0 = a.snap[n], s1 = a.snap[N + n];
-                num = (d0 - s0) * (d0 - s0) + (d1 - s1) * (d1 - s1);
-                den = d0 * d0 + d1 * d1;
-                a.snap[n] = d0;
-                a.snap[N + n] = d1;
-            }
-        }
-    }
+    if (n < a.N) primal_node<MASKED, EFIELD, CHECK>(a, n, inv_nx, num, den);
     if (CHECK) block_sum2(num, den, a.partial + 2 * (int64_t)blockIdx.x);
 }
 
 // ---------------------------------------------------------------- adjoint sweep
+template <bool MASKED, bool EFIELD, bool CHECK>
+__device__ __forceinline__ void adjoint_node(const SweepArgs& a, int64_t n, double inv_nx, double& num,
+                                             double& den)
+{
+    int code = MASKED ? a.code[n] : 0;
+    if (code < 0) return;
+    int iy = row_of(n, a.nx, inv_nx);
+    int ix = (int)(n - (int64_t)iy * a.nx);
+    int64_t idx[8];
+    neighbours(ix, iy, a.nx, a.ny, idx, -1);
+    const int64_t N = a.N;
+    double p[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) p[q] = a.src[q * N + idx[q]];
+    double srx = a.scale * a.g[n], sry = a.scale * a.g[N + n];
+    if (CHECK) {
+        double d0 = (p[0] - p[2]) + (p[4] - p[5]) + (p[7] - p[6]);
+        double d1 = (p[1] - p[3]) + (p[4] + p[5]) - (p[6] + p[7]);
+        double s0 = a.snap[n], s1 = a.snap[N + n];
+        num = (d0 - s0) * (d0 - s0) + (d1 - s1) * (d1 - s1);
+        den = d0 * d0 + d1 * d1;
+        a.snap[n] = d0;
+        a.snap[N + n] = d1;
+    }
+    if (!MASKED || code == 0) {
+        double k11 = a.k11, ks = a.ks, kd = a.kd;
+        if (EFIELD) {
+            Relax<double> r = relax_from_E<double>(a.E[n], a.nu, false);
+            k11 = r.k11; ks = r.ks; kd = r.kd;
+        }
+        adj_collide_bulk(p, srx, sry, k11, ks, kd);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a.dst[q * N + n] = p[q];
+    } else {
+        // transposed extended map: out_p = sum_r jac[r][p] ext_r - src_p,
+        // ext = (routed regular slots, own slots of the cut links)
+        const BNode* bn = a.bnodes + (code - 1);
+        const double* J = a.bjac + (int64_t)(code - 1) * 128;
+        double ext[16];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            ext[q] = p[q];
+            ext[8 + q] = ((bn->cut >> q) & 1u) ? a.src[q * N + n] : 0.0;
+        }
+        for (int pp = 0; pp < 8; ++pp) {
+            double s = 0.0;
+            for (int r = 0; r < 16; ++r) s += J[r * 8 + pp] * ext[r];
+            a.dst[pp * N + n] = s - (srx * cx(pp) + sry * cy(pp));
+        }
+    }
+}
+
 template <bool MASKED, bool EFIELD, bool CHECK>
 __global__ __launch_bounds__(kBlock) void k_adjoint(SweepArgs a, double inv_nx)
 {
     if (a.status->stop) return;
     int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double num = 0.0, den = 0.0;
-    if (n < a.N) {
-        int code = MASKED ? a.code[n] : 0;
-        if (code >= 0) {
-            int iy = row_of(n, a.nx, inv_nx);
-            int ix = (int)(n - (int64_t)iy * a.nx);
-            int64_t idx[8];
-            neighbours(ix, iy, a.nx, a.ny, idx, -1);
-            const int64_t N = a.N;
-            double p[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) p[q] = a.src[q * N + idx[q]];
-            double srx = a.scale * a.g[n], sry = a.scale * a.g[N + n];
-            if (CHECK) {
-                double d0 = (p[0] - p[2]) + (p[4] - p[5]) + (p[7] - p[6]);
-                double d1 = (p[1] - p[3]) + (p[4] + p[5]) - (p[6] + p[7]);
-                double s0 = a.snap[n], s1 = a.snap[N + n];
-                num = (d0 - s0) * (d0 - s0) + (d1 - s1) * (d1 - s1);
-                den = d0 * d0 + d1 * d1;
-                a.snap[n] = d0;
-                a.snap[N + n] = d1;
-            }
-            if (!MASKED || code == 0) {
-                double k11 = a.k11, ks = a.ks, kd = a.kd;
-                if (EFIELD) {
-                    Relax<double> r = relax_from_E<double>(a.E[n], a.nu, false);
-                    k11 = r.k11; ks = r.ks; kd = r.kd;
-                }
-                adj_collide_bulk(p, srx, sry, k11, ks, kd);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) a.dst[q * N + n] = p[q];
-            } else {
-                // transposed extended map: out_p = sum_r jac[r][p] ext_r - src_p,
-                // ext = (routed regular slots, own slots of the cut links)
-                const BNode* bn = a.bnodes + (code - 1);
-                const double* J = a.bjac + (int64_t)(code - 1) * 128;
-                double ext[16];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    ext[q] = p[q];
-                    ext[8 + q] = ((bn->cut >> q) & 1u) ? a.src[q * N + n] : 0.0;
-                }
-                for (int pp = 0; pp < 8; ++pp) {
-                    double s = 0.0;
-                    for (int r = 0; r < 16; ++r) s += J[r * 8 + pp] * ext[r];
-                    a.dst[pp * N + n] = s - (srx * cx(pp) + sry * cy(pp));
-                }
-            }
-        }
-    }
+    if (n < a.N) adjoint_node<MASKED, EFIELD, CHECK>(a, n, inv_nx, num, den);
     if (CHECK) block_sum2(num, den, a.partial + 2 * (int64_t)blockIdx.x);
 }
 
@@ -676,18 +683,18 @@ __device__ __forceinline__ void tb_row(double (&p2)[T][3], double (&p1a)[T][3], 
     }
 }
 
+// One strip (sx, sy) of a fused launch, run by one 64-lane wave.
 template <int T, bool ADJ>
-__global__ __launch_bounds__(64) void k_sweep_tb(TBArgs a)
+__device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
 {
-    if (a.status->stop) return;
     constexpr int V = 64 - 2 * T;
     const int lane = threadIdx.x;
     const int nx = a.nx, ny = a.ny;
     const int64_t N = a.N;
-    const int xs = blockIdx.x * V - T + lane;           // unwrapped column of this lane
+    const int xs = sx * V - T + lane;                   // unwrapped column of this lane
     const int x = wrapi(xs, nx);
     const bool out_lane = lane >= T && lane < 64 - T && xs < nx;
-    const int y0 = blockIdx.y * a.H;
+    const int y0 = sy * a.H;
     const int y1 = min(y0 + a.H, ny);
     // histories of level k's outputs (k = 0..T-1): p2 = row two back, p1 = row one back.
     // primal: rows y-1 feed planes {1,4,5}, rows y+1 feed {3,6,7};
@@ -744,6 +751,134 @@ __global__ __launch_bounds__(64) void k_sweep_tb(TBArgs a)
         store(r, o);
     }
 #endif
+}
+
+template <int T, bool ADJ>
+__global__ __launch_bounds__(64) void k_sweep_tb(TBArgs a)
+{
+    if (a.status->stop) return;
+    tb_strip<T, ADJ>(a, blockIdx.x, blockIdx.y);
+}
+
+}  // namespace slbm
+
+namespace slbm {
+
+// ---------------------------------------------------------------- batched sweeps
+// Many independent problems advance in one launch.  A block table maps every
+// block of the launch to (instance, local block / strip); each instance keeps
+// its own buffers, parameters, residual checks and stop flag.  Periodic and
+// plate instances keep separate buffer parities (fused launches flip a buffer
+// once per T steps, single-step launches once per step).
+struct BatchInst {
+    SweepArgs prim[2];    // primal args by buffer parity (src = buffer p, dst = buffer p^1)
+    SweepArgs adj[2];     // adjoint args by buffer parity
+    TBArgs tprim[2], tadj[2];
+    Status* status;
+    double inv_nx;
+    int32_t masked;
+    int32_t sx;           // strips per row of fused launches (periodic instances)
+    int64_t nblk;         // blocks of one single-step sweep
+};
+
+__device__ __forceinline__ bool mask_bit(uint64_t lo, uint64_t hi, int i)
+{
+    return i < 64 ? ((lo >> i) & 1ull) : ((hi >> (i - 64)) & 1ull);
+}
+
+template <bool ADJ>
+__global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchInst* __restrict__ inst,
+                                                       const int2* __restrict__ table, int par_periodic,
+                                                       int par_plate, uint64_t check_lo, uint64_t check_hi)
+{
+    const int2 e = table[blockIdx.x];
+    const BatchInst& I = inst[e.x];
+    if (I.status->stop) return;
+    const int par = I.masked ? par_plate : par_periodic;
+    const SweepArgs& a = ADJ ? I.adj[par] : I.prim[par];
+    const bool check = mask_bit(check_lo, check_hi, e.x);
+    const int64_t n = (int64_t)e.y * kBlock + threadIdx.x;
+    double num = 0.0, den = 0.0;
+    if (n < a.N) {
+        if (ADJ) {
+            if (I.masked) {
+                if (check) adjoint_node<true, false, true>(a, n, I.inv_nx, num, den);
+                else adjoint_node<true, false, false>(a, n, I.inv_nx, num, den);
+            } else {
+                if (check) adjoint_node<false, false, true>(a, n, I.inv_nx, num, den);
+                else adjoint_node<false, false, false>(a, n, I.inv_nx, num, den);
+            }
+        } else {
+            if (I.masked) {
+                if (check) primal_node<true, false, true>(a, n, I.inv_nx, num, den);
+                else primal_node<true, false, false>(a, n, I.inv_nx, num, den);
+            } else {
+                if (check) primal_node<false, false, true>(a, n, I.inv_nx, num, den);
+                else primal_node<false, false, false>(a, n, I.inv_nx, num, den);
+            }
+        }
+    }
+    if (check) block_sum2(num, den, a.partial + 2 * (int64_t)e.y);
+}
+
+template <int T, bool ADJ>
+__global__ __launch_bounds__(64) void k_sweep_tb_batch(const BatchInst* __restrict__ inst,
+                                                      const int2* __restrict__ table, int par_periodic)
+{
+    const int2 e = table[blockIdx.x];
+    const BatchInst& I = inst[e.x];
+    if (I.status->stop) return;
+    const TBArgs a = ADJ ? I.tadj[par_periodic] : I.tprim[par_periodic];
+    tb_strip<T, ADJ>(a, e.y % I.sx, e.y / I.sx);
+}
+
+// One block per instance: instances flagged in the mask test their residual.
+__global__ __launch_bounds__(kBlock) void k_residual_batch(const BatchInst* __restrict__ inst, int adjoint,
+                                                          uint64_t check_lo, uint64_t check_hi, double tol,
+                                                          int64_t t)
+{
+    const int i = blockIdx.x;
+    if (!mask_bit(check_lo, check_hi, i)) return;
+    const BatchInst& I = inst[i];
+    Status* st = I.status;
+    if (st->stop) return;
+    const double* partial = adjoint ? I.adj[0].partial : I.prim[0].partial;
+    double a = 0.0, b = 0.0;
+    for (int64_t k = threadIdx.x; k < I.nblk; k += kBlock) {
+        a += partial[2 * k];
+        b += partial[2 * k + 1];
+    }
+    __shared__ double out[2];
+    block_sum2(a, b, out);
+    if (threadIdx.x == 0) {
+        double num = out[0], den = out[1];
+        double r = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+        st->res = r;
+        st->t_last = t;
+        if (r < tol) {
+            st->stop = 1;
+            st->t_conv = t;
+        }
+    }
+}
+
+__global__ void k_status_reset_all(Status* st, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        st[i].stop = 0;
+        st[i].pad = 0;
+        st[i].t_conv = -1;
+        st[i].t_last = -1;
+        st[i].res = INFINITY;
+    }
+}
+
+// Marks every instance stopped (end of a batch loop at the step limit).
+__global__ void k_status_stop_all(Status* st, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) st[i].stop = 1;
 }
 
 }  // namespace slbm

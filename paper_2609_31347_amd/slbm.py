@@ -24,7 +24,10 @@ FIELD_COMPS = {FIELD_DISP: 2, FIELD_STRESS: 3, FIELD_ADJ_DISP: 2, FIELD_POPS: 8,
 EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_grad", "adjoint_solve_vjp",
            "solid_lbm_restore_solve", "solid_lbm_objective", "solid_lbm_set_control",
            "solid_lbm_run_steps", "solid_lbm_run_adjoint_steps", "solid_lbm_get_field",
-           "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_last_error", "solid_lbm_destroy")
+           "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_last_error", "solid_lbm_destroy",
+           "solid_lbm_batch_init", "batch_objective_and_grad", "solid_lbm_batch_set_tuning",
+           "solid_lbm_batch_time_sweeps", "solid_lbm_batch_instance", "solid_lbm_batch_last_error",
+           "solid_lbm_batch_destroy")
 
 
 class SlbmError(RuntimeError):
@@ -77,8 +80,21 @@ def _load():
     lib.solid_lbm_last_error.restype = ctypes.c_char_p
     lib.solid_lbm_destroy.argtypes = [P]
     lib.solid_lbm_destroy.restype = None
-    for f in EXPORTS[:-2]:
-        getattr(lib, f).restype = ctypes.c_int
+    lib.solid_lbm_batch_init.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32, pp]
+    lib.batch_objective_and_grad.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, info, info]
+    lib.solid_lbm_batch_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.solid_lbm_batch_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    lib.solid_lbm_batch_instance.argtypes = [P, ctypes.c_int32]
+    lib.solid_lbm_batch_instance.restype = ctypes.c_void_p
+    lib.solid_lbm_batch_last_error.argtypes = [P]
+    lib.solid_lbm_batch_last_error.restype = ctypes.c_char_p
+    lib.solid_lbm_batch_destroy.argtypes = [P]
+    lib.solid_lbm_batch_destroy.restype = None
+    for f in EXPORTS:
+        if f not in ("solid_lbm_last_error", "solid_lbm_destroy", "solid_lbm_batch_instance",
+                     "solid_lbm_batch_last_error", "solid_lbm_batch_destroy"):
+            getattr(lib, f).restype = ctypes.c_int
     return lib
 
 
@@ -105,10 +121,12 @@ def _arg(a, keep, dtype=np.float64):
 
 
 class Context:
-    """Owns one slbm_ctx (freed by solid_lbm_destroy or on garbage collection)."""
+    """Owns one slbm_ctx (freed by solid_lbm_destroy or on garbage collection),
+    or borrows one of a batch (owned=False)."""
 
-    def __init__(self, handle, problem):
+    def __init__(self, handle, problem, owned=True):
         self.handle = handle
+        self.owned = owned
         self.nx, self.ny = problem["nx"], problem["ny"]
         self.N = self.nx * self.ny
         self.control_kind = problem.get("control_kind", CTRL_FORCE_MODES)
@@ -119,7 +137,7 @@ class Context:
                 CTRL_E_SCALAR_SQ: 1}[self.control_kind]
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and getattr(self, "owned", True):
             LIB.solid_lbm_destroy(self.handle)
             self.handle = None
 
@@ -131,9 +149,7 @@ def _check(ctx, rc):
     return rc
 
 
-def solid_lbm_init(problem):
-    """problem: dict with the fields of slbm_problem (arrays as numpy)."""
-    keep = []
+def _problem_struct(problem, keep):
     p = _Problem()
     p.nx, p.ny = int(problem["nx"]), int(problem["ny"])
     p.dx = float(problem["dx"])
@@ -156,6 +172,13 @@ def solid_lbm_init(problem):
     p.max_steps = int(problem.get("max_steps", 10_000_000))
     p.check_interval = int(problem.get("check_interval", 0))
     p.stream = problem.get("stream")
+    return p
+
+
+def solid_lbm_init(problem):
+    """problem: dict with the fields of slbm_problem (arrays as numpy)."""
+    keep = []
+    p = _problem_struct(problem, keep)
     h = ctypes.c_void_p()
     rc = LIB.solid_lbm_init(ctypes.byref(p), ctypes.byref(h))
     if rc < 0:
@@ -277,3 +300,90 @@ def solid_lbm_destroy(ctx):
     if ctx.handle:
         LIB.solid_lbm_destroy(ctx.handle)
         ctx.handle = None
+
+
+# ------------------------------------------------------------------ batches
+
+class Batch:
+    """Owns one slbm_batch; `contexts[i]` are its instances (borrowed)."""
+
+    def __init__(self, handle, problems):
+        self.handle = handle
+        self.problems = [dict(p) for p in problems]
+        self.contexts = [Context(LIB.solid_lbm_batch_instance(handle, i), p, owned=False)
+                         for i, p in enumerate(problems)]
+
+    def __len__(self):
+        return len(self.contexts)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            for c in self.contexts:
+                c.handle = None
+            LIB.solid_lbm_batch_destroy(self.handle)
+            self.handle = None
+
+
+def _bcheck(batch, rc):
+    if rc < 0:
+        msg = LIB.solid_lbm_batch_last_error(batch.handle if batch is not None else None)
+        raise SlbmError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def solid_lbm_batch_init(problems):
+    keep = []
+    arr = (_Problem * len(problems))()
+    for i, pr in enumerate(problems):
+        arr[i] = _problem_struct(pr, keep)
+    h = ctypes.c_void_p()
+    rc = LIB.solid_lbm_batch_init(arr, len(problems), ctypes.byref(h))
+    if rc < 0:
+        raise SlbmError(rc, LIB.solid_lbm_batch_last_error(None).decode())
+    return Batch(h, problems)
+
+
+def batch_objective_and_grad(batch, controls, grads=None, want_grad=True):
+    """Returns (rc, J (array), grads (list), primal infos, adjoint infos)."""
+    B = len(batch)
+    keep = []
+    cptr = (ctypes.c_void_p * B)()
+    kinds = set()
+    for i, c in enumerate(controls):
+        ptr, kind = _arg(c, keep)
+        cptr[i] = ptr
+        kinds.add(kind)
+    if len(kinds) != 1:
+        raise ValueError("controls must all be host or all device")
+    kind = kinds.pop()
+    gptr = None
+    if want_grad:
+        if grads is None:
+            if kind == PTR_DEVICE:
+                raise ValueError("pass device grads with device controls")
+            grads = [np.zeros(ctx.grad_len()) for ctx in batch.contexts]
+        gptr = (ctypes.c_void_p * B)()
+        for i, g in enumerate(grads):
+            gptr[i] = g.data_ptr() if _is_torch(g) else g.ctypes.data
+    J = (ctypes.c_double * B)()
+    pi, ai = (SolveInfo * B)(), (SolveInfo * B)()
+    rc = _bcheck(batch, LIB.batch_objective_and_grad(batch.handle, cptr, J, gptr, kind, pi, ai))
+    return rc, np.array(J[:]), grads, list(pi), list(ai)
+
+
+def solid_lbm_batch_set_tuning(batch, steps_per_launch=-1, rows_per_wave=0):
+    return _bcheck(batch, LIB.solid_lbm_batch_set_tuning(batch.handle, int(steps_per_launch), int(rows_per_wave)))
+
+
+def solid_lbm_batch_time_sweeps(batch, adjoint, n):
+    ms = ctypes.c_double()
+    _bcheck(batch, LIB.solid_lbm_batch_time_sweeps(batch.handle, int(adjoint), int(n), ctypes.byref(ms)))
+    return ms.value
+
+
+def solid_lbm_batch_destroy(batch):
+    if batch.handle:
+        for c in batch.contexts:
+            c.handle = None
+        LIB.solid_lbm_batch_destroy(batch.handle)
+        batch.handle = None

@@ -23,7 +23,8 @@ def S():
 def declared():
     src = open(os.path.join(ROOT, "include", "solid_lbm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*|slbm_ctx\s*\*)\s*\**\s*(\w+)\s*\(", src,
+                                 flags=re.M)))
 
 
 def test_every_declared_symbol_is_exported(S):

@@ -1,0 +1,98 @@
+"""Batched solves (many uneven instances advancing in shared launches) give the
+same steps, objectives and gradients as the instances solved one by one, and
+the oracle's (needs a GPU)."""
+import numpy as np
+import pytest
+
+from paper_2609_31347_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def mixed_problems(S, tol=1e-10):
+    probs, ctrls = [], []
+    n = 32
+    probs.append(dict(nx=n, ny=n, dx=1 / n, E=1.0, nu=0.3, domain=0, target=I.two_mode_target(n),
+                      control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=I.two_mode_basis(n)))
+    ctrls.append(np.array([0.1, 0.1]))
+    nx, ny = 48, 40
+    probs.append(dict(nx=nx, ny=ny, dx=1 / 48, E=0.8, nu=0.25, domain=0,
+                      target=I.grf(nx, ny, 1 / 48, 1e-6, 0.15, 4, comps=2), control_kind=S.CTRL_FORCE_NODAL))
+    ctrls.append(I.grf(nx, ny, 1 / 48, 0.05, 0.1, 5, comps=2))
+    n = 64
+    probs.append(dict(nx=n, ny=n, dx=1 / n, E=1.0, nu=0.3, domain=0, target=I.two_mode_target(n),
+                      control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=I.two_mode_basis(n)))
+    ctrls.append(np.array([-0.4, 0.9]))
+    pd = I.paper_plate(16)
+    probs.append(dict(nx=pd["nx"], ny=pd["ny"], dx=pd["dx"], E=0.1, nu=0.7, domain=S.MASKED,
+                      node_mask=pd["active"].astype(np.uint8), link_bc=pd["bc"], link_wall=pd["wall"],
+                      link_normal=pd["normal"], target=pd["target"], control_kind=S.CTRL_FORCE_NODAL))
+    ctrls.append(pd["F"] * 1.05)
+    cp = I.clamped_plate(40, 25)
+    tgt = I.grf(40, 25, cp["dx"], 1e-8, 0.3, 8, comps=2) * cp["active"]
+    probs.append(dict(nx=40, ny=25, dx=cp["dx"], E=1.0, nu=0.3, domain=S.MASKED,
+                      node_mask=cp["active"].astype(np.uint8), link_bc=cp["bc"], link_wall=cp["wall"],
+                      link_normal=cp["normal"], target=tgt, control_kind=S.CTRL_FORCE_NODAL))
+    ctrls.append(I.grf(40, 25, cp["dx"], 0.05, 0.2, 9, comps=2) * cp["active"])
+    n = 24
+    sol = I.paper_periodic(n)
+    probs.append(dict(nx=n, ny=n, dx=1 / n, E=0.11, nu=0.8, domain=0, target=sol["d"],
+                      control_kind=S.CTRL_E_SCALAR_SQ, fixed_force=sol["F"]))
+    ctrls.append(np.array([np.sqrt(0.13)]))
+    for p in probs:
+        p.update(tol=tol, max_steps=2_000_000)
+    return probs, ctrls
+
+
+def test_batch_equals_individual_solves_and_oracle(orc):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_31347_amd import slbm as S
+    probs, ctrls = mixed_problems(S)
+    batch = S.solid_lbm_batch_init(probs)
+    rc, J, grads, pi, ai = S.batch_objective_and_grad(batch, ctrls)
+    assert rc == 0 and all(x.converged for x in pi) and all(x.converged for x in ai)
+    for i, (p, c) in enumerate(zip(probs, ctrls)):
+        ctx = S.solid_lbm_init(p)
+        rci, Ji, gi, pii, aii = S.objective_and_grad(ctx, c)
+        assert pii.steps == pi[i].steps and aii.steps == ai[i].steps, i
+        assert abs(J[i] - Ji) <= 1e-13 * abs(Ji), i
+        assert rel(grads[i], gi) < 1e-12, i
+    # two instances against the oracle
+    n = 32
+    q = orc.Problem(n, n, 1 / n, 1.0, 0.3, np.zeros((2, n, n)))
+    G = orc.objective_and_grad(q, probs[0]["target"], "modes", ctrls[0], modes=probs[0]["force_modes"], tol=1e-10)
+    assert abs(J[0] - G.J) / G.J < 1e-12 and rel(grads[0], G.grad) < 1e-10
+    p = probs[3]
+    q = orc.Problem(p["nx"], p["ny"], p["dx"], 0.1, 0.7, np.zeros((2, p["ny"], p["nx"])), active=p["node_mask"],
+                    bc=p["link_bc"], wall=p["link_wall"], normal=p["link_normal"])
+    G = orc.objective_and_grad(q, p["target"], "nodal", ctrls[3], tol=1e-10, project=False)
+    assert abs(J[3] - G.J) / G.J < 1e-12 and rel(np.asarray(grads[3]).reshape(G.grad.shape), G.grad) < 1e-10
+
+
+def test_batch_fixed_steps_and_tuning():
+    """tol <= 0: every instance runs exactly max_steps; shapes from the tuner do not change results."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_31347_amd import slbm as S
+    probs, ctrls = mixed_problems(S, tol=0.0)
+    for p in probs:
+        p["max_steps"] = 333
+    out = []
+    for T, H in ((1, 0), (8, 24), (4, 5)):
+        batch = S.solid_lbm_batch_init(probs)
+        S.solid_lbm_batch_set_tuning(batch, T, H)
+        rc, J, grads, pi, ai = S.batch_objective_and_grad(batch, ctrls)
+        assert all(x.steps == 333 for x in pi)
+        out.append((J, grads))
+    for J, grads in out[1:]:
+        assert rel(J, out[0][0]) < 1e-13
+        for g, g0 in zip(grads, out[0][1]):
+            assert rel(g, g0) < 1e-12

@@ -180,6 +180,13 @@ int objective_and_grad(slbm_ctx *ctx, const double *control, double *J, double *
 int adjoint_solve_vjp(slbm_ctx *ctx, const double *d_cot, double *grad, int32_t ptr_kind,
                       slbm_solve_info *info);
 
+/* As objective_and_grad, with the primal solve started from init_disp (2N,
+ * NULL = cold start) instead of d_0 = 0: a warm start changes the number of
+ * steps, not the fixed point. */
+int objective_and_grad_from(slbm_ctx *ctx, const double *control, const double *init_disp, double *J,
+                            double *grad, int32_t ptr_kind, slbm_solve_info *primal_info,
+                            slbm_solve_info *adjoint_info);
+
 /* ---- helpers ---- */
 
 /* Reinstates a converged primal state from a checkpoint: sets the control
@@ -230,8 +237,8 @@ void solid_lbm_destroy(slbm_ctx *ctx);
 
 /* ---- batches: many independent problems solved together ----
  *
- * A batch holds up to 128 problems of any sizes (periodic or plate; force
- * controls or E = alpha^2) that share tol, max_steps and stream.  All of them
+ * A batch holds up to 128 problems of any sizes and kinds (periodic or plate,
+ * any control) that share tol, max_steps and stream.  All of them
  * advance in the same launches: one launch per time step (or per T fused
  * steps for the periodic ones) covers every instance still running, each with
  * its own residual test every K_i steps and its own stop.  Results equal those

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libslbm.so")
-SRC = [os.path.join(HERE, "csrc", "slbm.hip")]
+SRC = [os.path.join(HERE, "csrc", "slbm.hip"), os.path.join(HERE, "csrc", "slbm_net.hip")]
 ARCH = os.environ.get("SLBM_OFFLOAD_ARCH", "gfx950")
 
 

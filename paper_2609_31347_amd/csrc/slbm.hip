@@ -877,6 +877,24 @@ int adjoint_solve(slbm_ctx* c, slbm_solve_info* info)
     return do_adjoint(c, info);
 }
 
+int objective_and_grad_from(slbm_ctx* c, const double* control, const double* init_disp, double* J, double* grad,
+                            int32_t ptr_kind, slbm_solve_info* pinfo, slbm_solve_info* ainfo)
+{
+    if (!c) return SLBM_EINVAL;
+    if (!J) return fail(c, SLBM_EINVAL, "J is NULL");
+    int rc = primal_solve(c, control, init_disp, ptr_kind, pinfo);
+    if (rc < 0) return rc;
+    int warn = rc;
+    *J = c->J;
+    if (!grad) return warn;
+    rc = do_adjoint(c, ainfo);
+    if (rc < 0) return rc;
+    if (rc > 0) warn = rc;
+    rc = assemble_grad(c, grad, ptr_kind);
+    if (rc < 0) return rc;
+    return warn;
+}
+
 int objective_and_grad(slbm_ctx* c, const double* control, double* J, double* grad, int32_t ptr_kind,
                        slbm_solve_info* pinfo, slbm_solve_info* ainfo)
 {
@@ -1207,8 +1225,9 @@ int batch_tables(slbm_batch* b, bool adjoint)
         I.status = b->status + i;
         I.inv_nx = c->inv_nx;
         I.masked = c->masked ? 1 : 0;
+        I.efield = c->efield_on ? 1 : 0;
         I.nblk = c->nblk;
-        if (!c->masked && T > 1) {
+        if (!c->masked && !c->efield_on && T > 1) {
             int V = 64 - 2 * T;
             int sx = (c->nx + V - 1) / V, sy = (c->ny + std::min(H, c->ny) - 1) / std::min(H, c->ny);
             I.sx = sx;
@@ -1301,7 +1320,7 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
         if (lo || hi || s == last) {
             launch_batch_step(b, adjoint, b->d_all, b->n_all, pp, pl, lo, hi);
             for (int i = 0; i < B; ++i) {
-                int par = b->ctx[i]->masked ? pl : pp;
+                int par = (b->ctx[i]->masked || b->ctx[i]->kind == SLBM_CTRL_E_NODAL) ? pl : pp;
                 if ((i < 64 ? (lo >> i) : (hi >> (i - 64))) & 1ull) checks[i].emplace_back(s, par);
                 if (s == last) last_in[i] = par;
             }
@@ -1455,8 +1474,6 @@ int solid_lbm_batch_init(const slbm_problem* problems, int32_t count, slbm_batch
     if (!problems || count < 1 || count > 128) return bfail(nullptr, SLBM_EINVAL, "count must be 1..128");
     for (int i = 0; i < count; ++i) {
         const slbm_problem& p = problems[i];
-        if (p.control_kind == SLBM_CTRL_E_NODAL)
-            return bfail(nullptr, SLBM_EINVAL, "batches take force controls or E = alpha^2 (not E fields)");
         if (p.tol != problems[0].tol || p.max_steps != problems[0].max_steps || p.stream != problems[0].stream)
             return bfail(nullptr, SLBM_EINVAL, "all problems of a batch share tol, max_steps and stream");
     }
@@ -1482,11 +1499,13 @@ int solid_lbm_batch_init(const slbm_problem* problems, int32_t count, slbm_batch
     for (int i = 0; i < count; ++i) {
         slbm_ctx* c = b->ctx[i];
         c->status = b->status + i;  // the instance's sweeps and the batch share its flag
+        // instances that cannot use fused launches (plates, E fields) step one by one
+        bool single = c->masked || c->kind == SLBM_CTRL_E_NODAL;
         for (int64_t k = 0; k < c->nblk; ++k) {
             all.push_back(make_int2(i, (int)k));
-            if (c->masked) plate.push_back(make_int2(i, (int)k));
+            if (single) plate.push_back(make_int2(i, (int)k));
         }
-        if (c->masked) b->any_plate = true;
+        if (single) b->any_plate = true;
         else b->any_periodic = true;
     }
     if (!rc && !(rc = balloc(b, &q, all.size() * sizeof(int2)))) b->d_all = (int2*)q;

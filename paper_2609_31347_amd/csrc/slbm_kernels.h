@@ -777,6 +777,7 @@ struct BatchInst {
     Status* status;
     double inv_nx;
     int32_t masked;
+    int32_t efield;       // E plane per node (E control): single-step kernels only
     int32_t sx;           // strips per row of fused launches (periodic instances)
     int64_t nblk;         // blocks of one single-step sweep
 };
@@ -794,29 +795,29 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchInst* __restr
     const int2 e = table[blockIdx.x];
     const BatchInst& I = inst[e.x];
     if (I.status->stop) return;
-    const int par = I.masked ? par_plate : par_periodic;
+    const int par = (I.masked || I.efield) ? par_plate : par_periodic;   // single-step instances
     const SweepArgs& a = ADJ ? I.adj[par] : I.prim[par];
     const bool check = mask_bit(check_lo, check_hi, e.x);
     const int64_t n = (int64_t)e.y * kBlock + threadIdx.x;
     double num = 0.0, den = 0.0;
     if (n < a.N) {
-        if (ADJ) {
-            if (I.masked) {
-                if (check) adjoint_node<true, false, true>(a, n, I.inv_nx, num, den);
-                else adjoint_node<true, false, false>(a, n, I.inv_nx, num, den);
-            } else {
-                if (check) adjoint_node<false, false, true>(a, n, I.inv_nx, num, den);
-                else adjoint_node<false, false, false>(a, n, I.inv_nx, num, den);
-            }
-        } else {
-            if (I.masked) {
-                if (check) primal_node<true, false, true>(a, n, I.inv_nx, num, den);
-                else primal_node<true, false, false>(a, n, I.inv_nx, num, den);
-            } else {
-                if (check) primal_node<false, false, true>(a, n, I.inv_nx, num, den);
-                else primal_node<false, false, false>(a, n, I.inv_nx, num, den);
-            }
+        const int sel = (I.masked ? 4 : 0) | (I.efield ? 2 : 0) | (check ? 1 : 0);
+#define BN_CASE(i, M, EF, CH)                                                       \
+    case i:                                                                         \
+        if (ADJ) adjoint_node<M, EF, CH>(a, n, I.inv_nx, num, den);                 \
+        else primal_node<M, EF, CH>(a, n, I.inv_nx, num, den);                      \
+        break;
+        switch (sel) {
+            BN_CASE(0, false, false, false)
+            BN_CASE(1, false, false, true)
+            BN_CASE(2, false, true, false)
+            BN_CASE(3, false, true, true)
+            BN_CASE(4, true, false, false)
+            BN_CASE(5, true, false, true)
+            BN_CASE(6, true, true, false)
+            BN_CASE(7, true, true, true)
         }
+#undef BN_CASE
     }
     if (check) block_sum2(num, den, a.partial + 2 * (int64_t)e.y);
 }

@@ -21,7 +21,8 @@ PTR_HOST, PTR_DEVICE = 0, 1
  FIELD_AVG_POPS) = range(8)
 FIELD_COMPS = {FIELD_DISP: 2, FIELD_STRESS: 3, FIELD_ADJ_DISP: 2, FIELD_POPS: 8, FIELD_ADJ_POPS: 8,
                FIELD_RESIDUAL: 2, FIELD_CUR_DISP: 2, FIELD_AVG_POPS: 8}
-EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_grad", "adjoint_solve_vjp",
+EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_grad", "objective_and_grad_from",
+           "adjoint_solve_vjp",
            "solid_lbm_restore_solve", "solid_lbm_objective", "solid_lbm_set_control",
            "solid_lbm_run_steps", "solid_lbm_run_adjoint_steps", "solid_lbm_get_field",
            "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_last_error", "solid_lbm_destroy",
@@ -74,6 +75,7 @@ def _load():
     lib.solid_lbm_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.adjoint_solve_vjp.argtypes = [P, P, P, ctypes.c_int32, info]
+    lib.objective_and_grad_from.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double), P, ctypes.c_int32, info, info]
     lib.solid_lbm_restore_solve.argtypes = [P, P, P, ctypes.c_int32]
     lib.solid_lbm_objective.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_last_error.argtypes = [P]
@@ -203,12 +205,15 @@ def adjoint_solve(ctx):
     return rc, info
 
 
-def objective_and_grad(ctx, control, grad=None, want_grad=True):
+def objective_and_grad(ctx, control, grad=None, want_grad=True, init_disp=None):
     """Returns (rc, J, grad, primal_info, adjoint_info).  grad: optional output
     array/tensor (device tensors are written in place); allocated on the host
-    when not given."""
+    when not given.  init_disp: warm start of the primal (objective_and_grad_from)."""
     keep = []
     cp, kind = _arg(control, keep)
+    ip, kind2 = _arg(init_disp, keep)
+    if init_disp is not None and kind2 != kind:
+        raise ValueError("control and init_disp must live in the same memory kind")
     out = None
     gp = None
     if want_grad:
@@ -226,8 +231,12 @@ def objective_and_grad(ctx, control, grad=None, want_grad=True):
             raise ValueError("control and grad must live in the same memory kind")
     J = ctypes.c_double()
     pi, ai = SolveInfo(), SolveInfo()
-    rc = _check(ctx, LIB.objective_and_grad(ctx.handle, cp, ctypes.byref(J), gp, kind, ctypes.byref(pi),
-                                            ctypes.byref(ai)))
+    if init_disp is None:
+        rc = _check(ctx, LIB.objective_and_grad(ctx.handle, cp, ctypes.byref(J), gp, kind, ctypes.byref(pi),
+                                                ctypes.byref(ai)))
+    else:
+        rc = _check(ctx, LIB.objective_and_grad_from(ctx.handle, cp, ip, ctypes.byref(J), gp, kind,
+                                                     ctypes.byref(pi), ctypes.byref(ai)))
     return rc, J.value, out, pi, ai
 
 

@@ -1,0 +1,52 @@
+"""Pins of the CPU reference of the warm-start network: the convolution is a
+library correlation, the gradients are finite differences of the forward."""
+import numpy as np
+from scipy import signal
+
+from oracle import convnet as C
+
+
+def test_conv3x3_is_a_zero_padded_correlation():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, 3, 7, 9))
+    w = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    y = C.conv3x3(x, w, b)
+    for bb in range(2):
+        for co in range(4):
+            ref = b[co] + sum(signal.correlate2d(x[bb, ci], w[co, ci], mode="same", boundary="fill")
+                              for ci in range(3))
+            assert np.abs(y[bb, co] - ref).max() < 1e-12
+
+
+def test_conv_gradients_match_finite_differences():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, 3, 5, 6))
+    w = rng.standard_normal((2, 3, 3, 3))
+    dz = rng.standard_normal((2, 2, 5, 6))
+    f = lambda x_, w_: float((C.conv3x3(x_, w_) * dz).sum())
+    dw, db = C.conv3x3_grad_w(dz, x)
+    dx = C.conv3x3_grad_x(dz, w)
+    h = 1e-6
+    for idx in [(0, 0, 0, 0), (1, 2, 2, 1), (0, 1, 1, 2)]:
+        e = np.zeros_like(w)
+        e[idx] = h
+        assert abs((f(x, w + e) - f(x, w - e)) / (2 * h) - dw[idx]) < 1e-7
+    for idx in [(0, 0, 0, 0), (1, 2, 4, 5), (0, 1, 2, 3)]:
+        e = np.zeros_like(x)
+        e[idx] = h
+        assert abs((f(x + e, w) - f(x - e, w)) / (2 * h) - dx[idx]) < 1e-7
+    assert np.allclose(db, dz.sum((0, 2, 3)))
+
+
+def test_bf16_rounding_is_nearest_even():
+    """bfloat16 keeps 8 significant bits: spacing 2^-7 just above 1."""
+    u = 2.0 ** -7
+    x = np.array([1.0, 1.0 + u / 2, 1.0 + 3 * u / 2, 1.0 + 0.75 * u, 1.0 + 0.25 * u, -2.5], dtype=np.float32)
+    r = C.bf16(x)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                  # tie between 1 and 1 + u: even mantissa (1.0)
+    assert r[2] == np.float32(1.0 + 2 * u)   # tie between 1 + u and 1 + 2u: even (1 + 2u)
+    assert r[3] == np.float32(1.0 + u)
+    assert r[4] == 1.0
+    assert r[5] == -2.5

@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=40)
-    ap.add_argument("--mode", choices=("gradient", "sweeps", "lbfgs", "batch"), default="gradient",
+    ap.add_argument("--mode", choices=("gradient", "sweeps", "lbfgs", "batch", "warmstart"), default="gradient",
                     help="sweeps: time fixed counts of primal/adjoint sweeps and a reference copy "
                          "(for rocprofv3 kernel traces and counters)")
     ap.add_argument("--sweeps", type=int, default=200)
@@ -50,6 +50,11 @@ def parse():
     ap.add_argument("--instances", type=int, default=96, help="batch mode: number of instances")
     ap.add_argument("--plates", type=int, default=24, help="batch mode: how many of them are plates")
     ap.add_argument("--sequential", action="store_true", help="batch mode: also solve them one by one")
+    ap.add_argument("--train-samples", type=int, default=4000, help="warmstart mode: training solves")
+    ap.add_argument("--train-iters", type=int, default=3000, help="warmstart mode: Adam iterations")
+    ap.add_argument("--train-lr", type=float, default=5e-4, help="warmstart mode: peak Adam learning rate")
+    ap.add_argument("--eval-sizes", default="64,128,256", help="warmstart mode: plate widths to evaluate")
+    ap.add_argument("--eval-fields", type=int, default=4, help="warmstart mode: held-out E fields per size")
     ap.add_argument("--rows", type=int, default=0, help="rows per wave of fused launches (0 automatic)")
     return ap.parse_args()
 
@@ -200,6 +205,77 @@ def batch_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def warmstart_mode(args):
+    """Learned warm start of the E-field identification on the clamped plate:
+    training data from batched FP64 solves at 64 x 39, training by the
+    project's MFMA kernels, then cold vs warm time-to-gradient (primal +
+    adjoint to the residual tol) on held-out E fields at each evaluation size.
+    Every stage prints one JSON line."""
+    import torch
+    from paper_2609_31347_amd import slbm as S
+    from paper_2609_31347_amd import warmstart as WS
+    torch.cuda.set_device(0)
+    ws = WS.WarmStart(nx_coarse=64, seed=0)
+    t0 = time.perf_counter()
+    ref_steps = ws.reference(tol=1e-10)
+    print(json.dumps({"stage": "reference", "steps": int(ref_steps), "wall_s": round(time.perf_counter() - t0, 2)}),
+          flush=True)
+    X, Y, info = [], [], None
+    chunk = 480
+    for k in range(0, args.train_samples, chunk):
+        Xk, Yk, info = ws.make_data(min(chunk, args.train_samples - k), seed0=k, tol=1e-8)
+        X.append(Xk)
+        Y.append(Yk)
+        print(json.dumps({"stage": "data", "samples": k + len(Xk), **{kk: round(v, 3) for kk, v in info.items()}}),
+              flush=True)
+    X, Y = np.concatenate(X), np.concatenate(Y)
+    nv = max(1, len(X) // 10)                 # held-out tenth for the validation loss
+    t0 = time.perf_counter()
+    ws.train(X[nv:], Y[nv:], iters=args.train_iters, batch=32, lr=args.train_lr, log_every=500,
+             log=lambda r: print(json.dumps({"stage": "train", **r}), flush=True), Xv=X[:nv], Yv=Y[:nv])
+    print(json.dumps({"stage": "trained", "wall_s": round(time.perf_counter() - t0, 2)}), flush=True)
+    rows = []
+    for nx in [int(v) for v in args.eval_sizes.split(",")]:
+        cp = WS.plate(nx)
+        # identification target: displacement of a reference modulus field
+        E_star = WS.e_field(cp, 99999)
+        ctx = S.solid_lbm_init(WS.plate_problem(cp, args.tol))
+        S.primal_solve(ctx, E_star)
+        target = S.solid_lbm_get_field(ctx, S.FIELD_DISP)
+        ctx = S.solid_lbm_init(WS.plate_problem(cp, args.tol, target=target))
+        for seed in range(10000, 10000 + args.eval_fields):
+            E = WS.e_field(cp, seed)
+            t0 = time.perf_counter()
+            rc, Jc, gc, pc, ac = S.objective_and_grad(ctx, E)
+            tc = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            d0 = ws.predict(cp, E)
+            tp = time.perf_counter() - t0
+            rc, Jw, gw, pw, aw = S.objective_and_grad(ctx, E, init_disp=d0)
+            tw = time.perf_counter() - t0
+            # ablation: the E = 1 displacement alone as the initial state
+            rc, _, _, pr, _ = S.objective_and_grad(ctx, E, init_disp=ws.predict(cp, E, use_net=False),
+                                                   want_grad=False)
+            row = {"stage": "eval", "grid": [cp["active"].shape[1], cp["active"].shape[0]], "seed": seed,
+                   "cold_primal_steps": pc.steps, "warm_primal_steps": pw.steps,
+                   "ref_only_primal_steps": pr.steps, "adjoint_steps": ac.steps,
+                   "cold_time_to_gradient_s": round(tc, 3), "warm_time_to_gradient_s": round(tw, 3),
+                   "predict_s": round(tp, 4), "J_rel_diff": abs(Jw - Jc) / abs(Jc),
+                   "grad_rel_diff": float(np.linalg.norm(np.asarray(gw) - np.asarray(gc)) / np.linalg.norm(gc))}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+    for nx in sorted(set(r["grid"][0] for r in rows)):
+        rr = [r for r in rows if r["grid"][0] == nx]
+        print(json.dumps({"stage": "summary", "width": nx,
+                          "primal_step_ratio": round(np.mean([r["warm_primal_steps"] / r["cold_primal_steps"]
+                                                              for r in rr]), 4),
+                          "ref_only_primal_step_ratio": round(np.mean([r["ref_only_primal_steps"] /
+                                                                       r["cold_primal_steps"] for r in rr]), 4),
+                          "time_to_gradient_ratio": round(np.mean([r["warm_time_to_gradient_s"] /
+                                                                   r["cold_time_to_gradient_s"] for r in rr]), 4)}),
+              flush=True)
+
+
 def cpu_baseline(n, steps, a):
     """Oracle sweeps on a bounded sample: `steps` primal and `steps` adjoint
     sweeps of the same N x N workload on one core."""
@@ -236,6 +312,8 @@ def main():
         return lbfgs_mode(args)
     if args.mode == "batch":
         return batch_mode(args)
+    if args.mode == "warmstart":
+        return warmstart_mode(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
               f"decomposition is a design note, not built)", file=sys.stderr)

@@ -28,19 +28,20 @@
 extern "C" {
 #endif
 
-/* y[b][co][p] = act(bias[co] + sum_{ci,ky,kx} W[co][ci][ky][kx] x[b][ci][p + (ky-1, kx-1)])
- * with zero padding at the image border; act = ReLU if relu != 0.
+/* y[b][co][p] = act(bias[co] + sum_{ci,ky,kx} W[co][ci][ky][kx] x[b][ci][p + dil (ky-1, kx-1)])
+ * with zero padding at the image border; act = ReLU if relu != 0; dilation dil >= 1.
  * x: bf16 [B][Cin][H][W]; w: packed bf16 (see above); bias: FP32 [Cout] or NULL;
  * y: FP32 [B][Cout][H][W]; y_bf16: bf16 copy of y or NULL. */
 int slbm_conv3x3_forward(const uint16_t *x, const uint16_t *w, const float *bias, float *y,
                          uint16_t *y_bf16, int32_t B, int32_t Cin, int32_t Cout, int32_t H, int32_t W,
-                         int32_t relu, void *stream);
+                         int32_t relu, int32_t dilation, void *stream);
 
-/* Weight gradient: dw[co][ci*9 + tap] = sum_b sum_p dz[b][co][p] x[b][ci][p + off(tap)],
+/* Weight gradient: dw[co][ci*9 + tap] = sum_b sum_p dz[b][co][p] x[b][ci][p + dil off(tap)],
  * db[co] = sum_b sum_p dz[b][co][p] (db may be NULL); dz FP32 [B][Cout][H][W],
  * x bf16 [B][Cin][H][W]; dw FP32 [Cout][Cin*9] (unpacked). Deterministic. */
 int slbm_conv3x3_backward_weight(const float *dz, const uint16_t *x, float *dw, float *db, int32_t B,
-                                 int32_t Cin, int32_t Cout, int32_t H, int32_t W, void *stream);
+                                 int32_t Cin, int32_t Cout, int32_t H, int32_t W, int32_t dilation,
+                                 void *stream);
 
 /* dz = dy * (y > 0) (ReLU backward; relu == 0: dz = dy), also as bf16. n elements. */
 int slbm_act_backward(const float *dy, const float *y, float *dz, uint16_t *dz_bf16, int64_t n,
@@ -48,7 +49,8 @@ int slbm_act_backward(const float *dy, const float *y, float *dz, uint16_t *dz_b
 
 /* Packs FP32 weights w32 [Cout][Cin*9] into the bf16 MFMA layout (wp) and the
  * flipped, transposed layout of the data gradient (wt: the weights of the
- * convolution dx = conv(dz) with Cout inputs and Cin outputs). wt may be NULL. */
+ * convolution dx = conv(dz) with Cout inputs, Cin outputs and the same
+ * dilation). wt may be NULL. */
 int slbm_pack_weights(const float *w32, uint16_t *wp, uint16_t *wt, int32_t Cin, int32_t Cout, void *stream);
 
 /* FP32 -> bf16 (round to nearest even), n elements. */

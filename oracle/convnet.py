@@ -26,39 +26,39 @@ def _shift(x, dy, dx):
     return out
 
 
-def conv3x3(x, w, b=None):
-    """y[b, co] = b[co] + sum_{ci, ky, kx} w[co, ci, ky, kx] x[b, ci, y + ky - 1, x + kx - 1]."""
+def conv3x3(x, w, b=None, dil=1):
+    """y[b, co] = b[co] + sum_{ci, ky, kx} w[co, ci, ky, kx] x[b, ci, y + dil (ky - 1), x + dil (kx - 1)]."""
     x = np.asarray(x, np.float64)
     w = np.asarray(w, np.float64)
     y = np.zeros((x.shape[0], w.shape[0]) + x.shape[2:])
     for ky in range(3):
         for kx in range(3):
-            xs = _shift(x, ky - 1, kx - 1)
+            xs = _shift(x, dil * (ky - 1), dil * (kx - 1))
             y += np.einsum("oc,bchw->bohw", w[:, :, ky, kx], xs)
     if b is not None:
         y += np.asarray(b, np.float64)[None, :, None, None]
     return y
 
 
-def conv3x3_grad_w(dz, x):
-    """dw[co, ci, ky, kx] = sum_{b, y, x} dz[b, co, y, x] x[b, ci, y + ky - 1, x + kx - 1]."""
+def conv3x3_grad_w(dz, x, dil=1):
+    """dw[co, ci, ky, kx] = sum_{b, y, x} dz[b, co, y, x] x[b, ci, y + dil (ky - 1), x + dil (kx - 1)]."""
     dz = np.asarray(dz, np.float64)
     x = np.asarray(x, np.float64)
     dw = np.zeros((dz.shape[1], x.shape[1], 3, 3))
     for ky in range(3):
         for kx in range(3):
-            dw[:, :, ky, kx] = np.einsum("bohw,bchw->oc", dz, _shift(x, ky - 1, kx - 1))
+            dw[:, :, ky, kx] = np.einsum("bohw,bchw->oc", dz, _shift(x, dil * (ky - 1), dil * (kx - 1)))
     return dw, dz.sum((0, 2, 3))
 
 
-def conv3x3_grad_x(dz, w):
-    """dx[b, ci, y, x] = sum_{co, ky, kx} w[co, ci, ky, kx] dz[b, co, y - ky + 1, x - kx + 1]."""
+def conv3x3_grad_x(dz, w, dil=1):
+    """dx[b, ci, y, x] = sum_{co, ky, kx} w[co, ci, ky, kx] dz[b, co, y - dil (ky - 1), x - dil (kx - 1)]."""
     dz = np.asarray(dz, np.float64)
     w = np.asarray(w, np.float64)
     dx = np.zeros((dz.shape[0], w.shape[1]) + dz.shape[2:])
     for ky in range(3):
         for kx in range(3):
-            dx += np.einsum("oc,bohw->bchw", w[:, :, ky, kx], _shift(dz, 1 - ky, 1 - kx))
+            dx += np.einsum("oc,bohw->bchw", w[:, :, ky, kx], _shift(dz, dil * (1 - ky), dil * (1 - kx)))
     return dx
 
 
@@ -71,14 +71,14 @@ def mse(y, t, mask):
 
 
 def net_forward_backward(x, layers, t, mask):
-    """Forward + backward of a stack of (w, b, relu) layers with the GPU's
+    """Forward + backward of a stack of (w, b, relu, dilation) layers with the GPU's
     rounding points: inputs and activations fed to a convolution are rounded
     to bf16, weights are bf16, sums are exact (float64); the data gradient
     entering each convolution is rounded to bf16.  Returns (loss, grads, y)."""
     acts = [bf16(x)]
     outs = []
-    for w, b, relu in layers:
-        y = conv3x3(acts[-1], bf16(w), b)
+    for w, b, relu, dil in layers:
+        y = conv3x3(acts[-1], bf16(w), b, dil)
         if relu:
             y = np.maximum(y, 0.0)
         outs.append(y)
@@ -86,9 +86,9 @@ def net_forward_backward(x, layers, t, mask):
     loss, dy = mse(outs[-1], t, mask)
     grads = [None] * len(layers)
     for i in range(len(layers) - 1, -1, -1):
-        w, b, relu = layers[i]
+        w, b, relu, dil = layers[i]
         dz = dy * (outs[i] > 0) if relu else dy
-        grads[i] = conv3x3_grad_w(dz, acts[i])
+        grads[i] = conv3x3_grad_w(dz, acts[i], dil)
         if i > 0:
-            dy = conv3x3_grad_x(bf16(dz.astype(np.float32)), bf16(w))
+            dy = conv3x3_grad_x(bf16(dz.astype(np.float32)), bf16(w), dil)
     return loss, grads, outs[-1]

@@ -32,7 +32,7 @@ __host__ __device__ inline int kpad(int K) { return (K + 7) / 8 * 8; }
 __global__ __launch_bounds__(64) void k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
                                                 const float* __restrict__ bias, float* __restrict__ y,
                                                 uint16_t* __restrict__ yb, int Cin, int Cout, int H, int W,
-                                                int Kp, int relu)
+                                                int Kp, int relu, int dil)
 {
     const int HW = H * W;
     const int p0 = blockIdx.x * 32, b = blockIdx.y;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(64) void k_conv_fwd(const uint16_t* __restrict__ x,
             short v = 0;
             if (pv && k < K) {
                 const int ci = k / 9, tap = k - ci * 9;
-                const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+                const int yy = py + (tap / 3 - 1) * dil, xx = px + (tap % 3 - 1) * dil;
                 if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = (short)xb[(int64_t)ci * HW + yy * W + xx];
             }
             bv[j] = v;
@@ -76,11 +76,11 @@ __global__ __launch_bounds__(64) void k_conv_fwd(const uint16_t* __restrict__ x,
     }
 }
 
-// dw[co][ci][tap] and db[co]: one block per (co, ci); fixed striding and a
+// dw[co][ci][tap] and db[co] (taps at dilation dil): one block per (co, ci); fixed striding and a
 // fixed reduction tree (deterministic).
 __global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ dz, const uint16_t* __restrict__ x,
                                                    float* __restrict__ dw, float* __restrict__ db, int B, int Cin,
-                                                   int Cout, int H, int W)
+                                                   int Cout, int H, int W, int dil)
 {
     const int co = blockIdx.x, ci = blockIdx.y;
     const int HW = H * W;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ dz
         const uint16_t* xc = x + ((int64_t)b * Cin + ci) * HW;
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
-            const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+            const int yy = py + (tap / 3 - 1) * dil, xx = px + (tap % 3 - 1) * dil;
             if (yy >= 0 && yy < H && xx >= 0 && xx < W) acc[tap] += g * bf2f(xc[yy * W + xx]);
         }
         acc[9] += g;
@@ -219,21 +219,22 @@ int status(hipError_t e) { return e == hipSuccess ? 0 : -3; }
 extern "C" {
 
 int slbm_conv3x3_forward(const uint16_t* x, const uint16_t* w, const float* bias, float* y, uint16_t* y_bf16,
-                         int32_t B, int32_t Cin, int32_t Cout, int32_t H, int32_t W, int32_t relu, void* stream)
+                         int32_t B, int32_t Cin, int32_t Cout, int32_t H, int32_t W, int32_t relu, int32_t dilation,
+                         void* stream)
 {
-    if (!x || !w || !y || B < 1 || Cin < 1 || Cout < 1 || Cout > 32 || H < 1 || W < 1) return -1;
+    if (!x || !w || !y || B < 1 || Cin < 1 || Cout < 1 || Cout > 32 || H < 1 || W < 1 || dilation < 1) return -1;
     dim3 grid(blocks((int64_t)H * W, 32), (unsigned)B);
     hipLaunchKernelGGL(k_conv_fwd, grid, dim3(64), 0, (hipStream_t)stream, x, w, bias, y, y_bf16, Cin, Cout, H, W,
-                       kpad(Cin * 9), relu);
+                       kpad(Cin * 9), relu, dilation);
     return status(hipGetLastError());
 }
 
 int slbm_conv3x3_backward_weight(const float* dz, const uint16_t* x, float* dw, float* db, int32_t B, int32_t Cin,
-                                 int32_t Cout, int32_t H, int32_t W, void* stream)
+                                 int32_t Cout, int32_t H, int32_t W, int32_t dilation, void* stream)
 {
-    if (!dz || !x || !dw || B < 1 || Cin < 1 || Cout < 1 || H < 1 || W < 1) return -1;
+    if (!dz || !x || !dw || B < 1 || Cin < 1 || Cout < 1 || H < 1 || W < 1 || dilation < 1) return -1;
     hipLaunchKernelGGL(k_conv_bwd_w, dim3((unsigned)Cout, (unsigned)Cin), dim3(256), 0, (hipStream_t)stream, dz, x,
-                       dw, db, B, Cin, Cout, H, W);
+                       dw, db, B, Cin, Cout, H, W, dilation);
     return status(hipGetLastError());
 }
 

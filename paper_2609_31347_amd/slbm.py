@@ -138,9 +138,11 @@ class Context:
         return {CTRL_FORCE_MODES: self.n_modes, CTRL_FORCE_NODAL: 2 * self.N, CTRL_E_NODAL: self.N,
                 CTRL_E_SCALAR_SQ: 1}[self.control_kind]
 
-    def __del__(self):
+    def __del__(self, _destroy=LIB.solid_lbm_destroy):
+        # the destroy function is bound at definition time: at interpreter
+        # shutdown the module globals may already be gone
         if getattr(self, "handle", None) and getattr(self, "owned", True):
-            LIB.solid_lbm_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
 

@@ -9,7 +9,8 @@ convolutional network predicts d_0 from the modulus field E(x):
   input  (4 channels): 1/E - 1 on the plate, the plate mask, and the
          displacement of the same plate with E = 1 (d_ref, 2 channels, scaled),
   output (2 channels): (d - d_ref) / s, s = max |d_ref|,
-  6 layers of 3x3 convolutions, 32 channels, ReLU between them, bf16 weights
+  6 layers of 3x3 convolutions (dilations 1, 2, 4, 8, 4, 1), 32 channels, ReLU
+  between them, bf16 weights
   and activations with FP32 accumulation on MFMA (csrc/slbm_net.hip), trained
   with Adam by the same kernels.
 
@@ -29,7 +30,11 @@ import torch
 from . import inputs as I
 from . import slbm as S
 
-LAYERS = ((4, 32, True), (32, 32, True), (32, 32, True), (32, 32, True), (32, 32, True), (32, 2, False))
+# (inputs, outputs, ReLU, dilation): six 3x3 layers, 32 channels; the dilations
+# widen the receptive field to 41 nodes, since the displacement depends on E
+# over the whole plate
+LAYERS = ((4, 32, True, 1), (32, 32, True, 2), (32, 32, True, 4), (32, 32, True, 8), (32, 32, True, 4),
+          (32, 2, False, 1))
 NU = 0.3
 
 
@@ -53,8 +58,8 @@ def _chk(rc, what):
 _L = S.LIB
 _P = ctypes.c_void_p
 _i32, _i64, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
-_L.slbm_conv3x3_forward.argtypes = [_P, _P, _P, _P, _P, _i32, _i32, _i32, _i32, _i32, _i32, _P]
-_L.slbm_conv3x3_backward_weight.argtypes = [_P, _P, _P, _P, _i32, _i32, _i32, _i32, _i32, _P]
+_L.slbm_conv3x3_forward.argtypes = [_P, _P, _P, _P, _P, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _P]
+_L.slbm_conv3x3_backward_weight.argtypes = [_P, _P, _P, _P, _i32, _i32, _i32, _i32, _i32, _i32, _P]
 _L.slbm_act_backward.argtypes = [_P, _P, _P, _P, _i64, _i32, _P]
 _L.slbm_pack_weights.argtypes = [_P, _P, _P, _i32, _i32, _P]
 _L.slbm_to_bf16.argtypes = [_P, _P, _i64, _P]
@@ -77,7 +82,7 @@ class ConvNet:
         g = torch.Generator().manual_seed(seed)
         self.layers = layers
         self.w, self.b, self.wp, self.wt, self.m, self.v = [], [], [], [], [], []
-        for i, (ci, co, relu) in enumerate(layers):
+        for i, (ci, co, relu, dil) in enumerate(layers):
             std = (2.0 / (ci * 9)) ** 0.5 * (0.1 if i == len(layers) - 1 else 1.0)
             w = (torch.randn(co, ci * 9, generator=g) * std).float().cuda()
             b = torch.zeros(co, dtype=torch.float32, device="cuda")
@@ -91,18 +96,18 @@ class ConvNet:
         self.pack()
 
     def pack(self):
-        for (ci, co, _), w, wp, wt in zip(self.layers, self.w, self.wp, self.wt):
+        for (ci, co, _, _), w, wp, wt in zip(self.layers, self.w, self.wp, self.wt):
             _chk(_L.slbm_pack_weights(_p(w), _p(wp), _p(wt), ci, co, _stream()), "pack")
 
     def forward(self, xb):
         """xb: bf16 [B, 4, H, W].  Returns the FP32 output; keeps activations."""
         B, _, H, W = xb.shape
         self.acts, self.outs = [xb], []
-        for (ci, co, relu), wp, b in zip(self.layers, self.wp, self.b):
+        for (ci, co, relu, dil), wp, b in zip(self.layers, self.wp, self.b):
             y = torch.empty((B, co, H, W), dtype=torch.float32, device="cuda")
             yb = torch.empty((B, co, H, W), dtype=torch.bfloat16, device="cuda")
             _chk(_L.slbm_conv3x3_forward(_p(self.acts[-1]), _p(wp), _p(b), _p(y), _p(yb), B, ci, co, H, W,
-                                         int(relu), _stream()), "conv forward")
+                                         int(relu), dil, _stream()), "conv forward")
             self.outs.append(y)
             self.acts.append(yb)
         return self.outs[-1]
@@ -112,19 +117,19 @@ class ConvNet:
         B, _, H, W = dy.shape
         self.gw, self.gb = [None] * len(self.layers), [None] * len(self.layers)
         for i in range(len(self.layers) - 1, -1, -1):
-            ci, co, relu = self.layers[i]
+            ci, co, relu, dil = self.layers[i]
             dz = torch.empty_like(dy)
             dzb = torch.empty(dy.shape, dtype=torch.bfloat16, device="cuda")
             _chk(_L.slbm_act_backward(_p(dy), _p(self.outs[i]), _p(dz), _p(dzb), dy.numel(), int(relu),
                                       _stream()), "act backward")
             gw = torch.empty((co, ci * 9), dtype=torch.float32, device="cuda")
             gb = torch.empty(co, dtype=torch.float32, device="cuda")
-            _chk(_L.slbm_conv3x3_backward_weight(_p(dz), _p(self.acts[i]), _p(gw), _p(gb), B, ci, co, H, W,
+            _chk(_L.slbm_conv3x3_backward_weight(_p(dz), _p(self.acts[i]), _p(gw), _p(gb), B, ci, co, H, W, dil,
                                                  _stream()), "weight gradient")
             self.gw[i], self.gb[i] = gw, gb
             if i > 0:
                 dx = torch.empty((B, ci, H, W), dtype=torch.float32, device="cuda")
-                _chk(_L.slbm_conv3x3_forward(_p(dzb), _p(self.wt[i]), None, _p(dx), None, B, co, ci, H, W, 0,
+                _chk(_L.slbm_conv3x3_forward(_p(dzb), _p(self.wt[i]), None, _p(dx), None, B, co, ci, H, W, 0, dil,
                                              _stream()), "data gradient")
                 dy = dx
         return self.gw, self.gb
@@ -213,7 +218,7 @@ class WarmStart:
         Y = ((d - self.dref[None]) / self.s * m).astype(np.float32)
         return X, Y, dict(solves=n, wall_s=time.perf_counter() - t0, mean_steps=float(steps.mean()))
 
-    def train(self, X, Y, iters=2000, batch=32, lr=1e-3, seed=0, log_every=200, log=None):
+    def train(self, X, Y, iters=2000, batch=32, lr=5e-4, seed=0, log_every=200, log=None, Xv=None, Yv=None):
         rng = np.random.Generator(np.random.PCG64(seed))
         Xg = torch.from_numpy(X).cuda()
         Yg = torch.from_numpy(Y).cuda()
@@ -229,22 +234,38 @@ class WarmStart:
             self.net.step(lr_t)
             if it % log_every == 0 or it == iters - 1:
                 rec = dict(it=it, loss=float(loss.item()), wall_s=round(time.perf_counter() - t0, 2))
+                if Xv is not None:
+                    rec["val_loss"] = self.evaluate(Xv, Yv)
                 self.history.append(rec)
                 if log:
                     log(rec)
         return self.history
 
-    def predict_coarse(self, E_coarse):
+    def evaluate(self, X, Y, batch=64):
+        """Mean masked MSE of the network on (X, Y)."""
+        mask = torch.from_numpy(self.cp["active"].astype(np.float32)).cuda()
+        tot, n = 0.0, 0
+        for k in range(0, len(X), batch):
+            xb = to_bf16(torch.from_numpy(X[k:k + batch]).cuda())
+            y = self.net.forward(xb)
+            loss, _ = mse(y, torch.from_numpy(Y[k:k + batch]).cuda(), mask[None].expand(len(xb), -1, -1).contiguous())
+            tot += float(loss.item()) * len(xb)
+            n += len(xb)
+        return tot / n
+
+    def predict_coarse(self, E_coarse, use_net=True):
+        if not use_net:                       # ablation: the E = 1 displacement alone
+            return self.dref * self.cp["active"]
         x = torch.from_numpy(features(E_coarse, self.cp["active"], self.dref, self.s)[None]).cuda()
         y = self.net.forward(to_bf16(x))
         return self.dref + self.s * y[0].double().cpu().numpy() * self.cp["active"]
 
-    def predict(self, cp_fine, E_fine):
+    def predict(self, cp_fine, E_fine, use_net=True):
         """Initial displacement for a plate of any resolution (same geometry)."""
         if cp_fine["active"].shape == self.cp["active"].shape:
-            return self.predict_coarse(E_fine) * cp_fine["active"]
+            return self.predict_coarse(E_fine, use_net) * cp_fine["active"]
         Ec = _resample(E_fine, cp_fine, self.cp, fill_outside=False)
-        dc = self.predict_coarse(Ec)
+        dc = self.predict_coarse(Ec, use_net)
         return np.stack([_resample(dc[c], self.cp, cp_fine, fill_outside=True) for c in range(2)]) * cp_fine["active"]
 
 

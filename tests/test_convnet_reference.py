@@ -1,9 +1,24 @@
 """Pins of the CPU reference of the warm-start network: the convolution is a
 library correlation, the gradients are finite differences of the forward."""
 import numpy as np
+import pytest
 from scipy import signal
 
 from oracle import convnet as C
+
+
+def test_dilated_conv_is_a_correlation_with_a_spread_kernel():
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((1, 2, 9, 11))
+    w = rng.standard_normal((3, 2, 3, 3))
+    y = C.conv3x3(x, w, dil=2)
+    for co in range(3):
+        ref = 0
+        for ci in range(2):
+            k = np.zeros((5, 5))
+            k[::2, ::2] = w[co, ci]
+            ref = ref + signal.correlate2d(x[0, ci], k, mode="same", boundary="fill")
+        assert np.abs(y[0, co] - ref).max() < 1e-12
 
 
 def test_conv3x3_is_a_zero_padded_correlation():
@@ -19,14 +34,15 @@ def test_conv3x3_is_a_zero_padded_correlation():
             assert np.abs(y[bb, co] - ref).max() < 1e-12
 
 
-def test_conv_gradients_match_finite_differences():
+@pytest.mark.parametrize("dil", [1, 2])
+def test_conv_gradients_match_finite_differences(dil):
     rng = np.random.default_rng(1)
     x = rng.standard_normal((2, 3, 5, 6))
     w = rng.standard_normal((2, 3, 3, 3))
     dz = rng.standard_normal((2, 2, 5, 6))
-    f = lambda x_, w_: float((C.conv3x3(x_, w_) * dz).sum())
-    dw, db = C.conv3x3_grad_w(dz, x)
-    dx = C.conv3x3_grad_x(dz, w)
+    f = lambda x_, w_: float((C.conv3x3(x_, w_, dil=dil) * dz).sum())
+    dw, db = C.conv3x3_grad_w(dz, x, dil)
+    dx = C.conv3x3_grad_x(dz, w, dil)
     h = 1e-6
     for idx in [(0, 0, 0, 0), (1, 2, 2, 1), (0, 1, 1, 2)]:
         e = np.zeros_like(w)

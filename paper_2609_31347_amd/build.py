@@ -22,7 +22,11 @@ def build(force=True, verbose=False):
     if not force and os.path.exists(LIB):
         return LIB
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # -ffp-contract=on: a multiply-add is fused only within one source
+    # expression, so the node arithmetic shared by the single-step and the
+    # fused kernels rounds the same in every kernel (hipcc's default "fast"
+    # lets the backend decide per kernel)
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-function",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),

@@ -40,7 +40,7 @@ struct slbm_ctx {
     double *g = nullptr, *Efield = nullptr, *target = nullptr, *snap = nullptr, *dbar = nullptr,
            *r = nullptr, *fbar = nullptr, *dJdF = nullptr, *dJdE = nullptr, *adisp = nullptr,
            *modes = nullptr, *fixedF = nullptr, *work = nullptr, *partial = nullptr, *scal = nullptr,
-           *bjac = nullptr, *ctrl = nullptr;
+           *ctrl = nullptr;
     uint8_t* obs = nullptr;
     int32_t* code = nullptr;
     BNode* bnodes = nullptr;
@@ -50,6 +50,8 @@ struct slbm_ctx {
     hipEvent_t t0 = nullptr, t1 = nullptr;
     int tb_T = -1;     // steps fused per launch (0/1: single-step sweeps; -1: automatic)
     int tb_H = 0;      // rows per wave of the fused sweeps (0: automatic)
+    int tile_w = 0, tile_h = 0;  // tile of the LDS-tiled fused sweeps (0: automatic)
+    bool tile_attr = false;      // LDS limits of the plate tile kernels raised
     int64_t nblk = 0;  // blocks of one sweep
     int64_t pcap = 0;  // capacity of the partial-sum buffer in blocks
     // state
@@ -122,7 +124,6 @@ SweepArgs base_args(slbm_ctx* c)
     std::memset(&a, 0, sizeof(a));
     a.code = c->code;
     a.bnodes = c->bnodes;
-    a.bjac = c->bjac;
     a.snap = c->snap;
     a.partial = c->partial;
     a.status = c->status;
@@ -214,6 +215,93 @@ void launch_fused(slbm_ctx* c, bool adjoint, const SweepArgs& s, int T)
 #undef TB_CASE
 }
 
+// Sweeps fused per launch by the LDS-tiled kernel (plates and E fields; 1 =
+// single-step sweeps only).  Any count 1..halo works, so runs shorter than
+// the halo between residual checks are fused too.
+// Automatic: 8 steps per launch (32 x 32 regions, 16 x 16 tiles) up to ~128k
+// nodes, 6 (20 x 20 tiles) beyond -- measured on MI355X for plates of 64 to
+// 512 nodes across, primal and adjoint.
+int tile_halo(const slbm_ctx* c)
+{
+    if (c->tb_T < 0) return c->N <= 131072 ? 8 : 6;
+    return std::max(1, std::min(c->tb_T, 8));
+}
+
+int tile_steps(const slbm_ctx* c) { return (c->masked || c->efield_on) ? tile_halo(c) : 1; }
+
+// Interior tile of the LDS-tiled sweeps for a halo h: the region (tw + 2h) x
+// (th + 2h) must hold at most kTileMaxNodes nodes.  Automatic: a 32 x 32 region.
+void tile_shape(const slbm_ctx* c, int h, int* tw, int* th)
+{
+    if (c->tile_w > 0 && c->tile_h > 0 && (c->tile_w + 2 * h) * (c->tile_h + 2 * h) <= kTileMaxNodes) {
+        *tw = c->tile_w;
+        *th = c->tile_h;
+        return;
+    }
+    *tw = std::max(2, 32 - 2 * h);
+    *th = std::max(2, 32 - 2 * h);
+}
+
+// Plate tiles stage boundary data in LDS beyond the default 64 KiB of
+// dynamic LDS: raise the limit of those kernels (once per context).
+int tile_lds_limits(slbm_ctx* c)
+{
+    if (c->tile_attr) return SLBM_OK;
+    const int lmax = (int)tile_lds_bytes(kTileMaxNodes, true);
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<true, false, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<true, true, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<true, false, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<true, true, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+    c->tile_attr = true;
+    return SLBM_OK;
+}
+
+void launch_tile(slbm_ctx* c, bool adjoint, const SweepArgs& s, int steps, int halo)
+{
+    TileArgs a;
+    a.src = s.src;
+    a.dst = s.dst;
+    a.g = s.g;
+    a.E = s.E;
+    a.code = s.code;
+    a.bnodes = s.bnodes;
+    a.status = c->status;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.N = c->N;
+    a.k11 = s.k11;
+    a.ks = s.ks;
+    a.kd = s.kd;
+    a.E0 = s.E0;
+    a.nu = s.nu;
+    a.scale = s.scale;
+    a.halo = halo;
+    a.steps = steps;
+    tile_shape(c, halo, &a.tw, &a.th);
+    a.tiles_x = (c->nx + a.tw - 1) / a.tw;
+    const int tiles_y = (c->ny + a.th - 1) / a.th;
+    const size_t lds = tile_lds_bytes((a.tw + 2 * halo) * (a.th + 2 * halo), c->masked);
+    dim3 grid((unsigned)(a.tiles_x * tiles_y)), block(kTileBlock);
+    int sel = (c->masked ? 4 : 0) | (c->efield_on ? 2 : 0) | (adjoint ? 1 : 0);
+#define TL_CASE(i, M, EF, AD) \
+    case i: hipLaunchKernelGGL((k_sweep_tile<M, EF, AD>), grid, block, lds, c->stream, a); break;
+    switch (sel) {
+        TL_CASE(0, false, false, false)
+        TL_CASE(1, false, false, true)
+        TL_CASE(2, false, true, false)
+        TL_CASE(3, false, true, true)
+        TL_CASE(4, true, false, false)
+        TL_CASE(5, true, false, true)
+        TL_CASE(6, true, true, false)
+        TL_CASE(7, true, true, true)
+    }
+#undef TL_CASE
+}
+
 // Runs sweeps with indices 0 .. last (inclusive) from buffer parity `start`,
 // checking every K steps when tol > 0; stops at the first passing test.
 // Returns the step index t of the final state whose successor was also
@@ -240,6 +328,11 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
     // single-step launches, runs of plain sweeps between them are fused by T
     int cur = start;
     const int T = fused_steps(c);
+    const int TL = tile_steps(c);
+    if (TL > 1 && c->masked) {
+        int rc = tile_lds_limits(c);
+        if (rc) return rc;
+    }
     std::vector<std::pair<int64_t, int>> checks;  // (step, input buffer) of every check sweep
     int last_in = start;
     while (s <= last && !stopped) {
@@ -255,6 +348,15 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
                 launch_fused(c, adjoint, a, T);
                 cur ^= 1;
                 s += T;
+                continue;
+            }
+            if (!check && TL > 1 && plain >= 2) {
+                const int k = (int)std::min<int64_t>(plain, TL);
+                a.src = bufs[cur];
+                a.dst = bufs[cur ^ 1];
+                launch_tile(c, adjoint, a, k, TL);
+                cur ^= 1;
+                s += k;
                 continue;
             }
             a.src = bufs[cur];
@@ -511,11 +613,6 @@ int adjoint_prepare(slbm_ctx* c)
     if ((rc = fill(c, c->abuf[0], 8 * c->N, 0.0))) return rc;
     if ((rc = fill(c, c->abuf[1], 8 * c->N, 0.0))) return rc;
     if ((rc = fill(c, c->snap, 2 * c->N, 0.0))) return rc;
-    if (c->masked && c->nb > 0) {
-        hipLaunchKernelGGL(k_boundary_jacobian, dim3((c->nb + 63) / 64), dim3(64), 0, c->stream, c->bnodes, c->nb,
-                           c->efield_on ? c->Efield : (const double*)nullptr, c->E_cur, c->nu, c->bjac);
-        HIPCHK(c, hipGetLastError());
-    }
     c->adj_cur = 0;
     return SLBM_OK;
 }
@@ -714,12 +811,14 @@ int solid_lbm_init(const slbm_problem* p, slbm_ctx** out)
                     b.cut |= 1u << q;
                     if (kind == SLBM_LINK_DIRICHLET) b.dirichlet |= 1u << q;
                     else any_neumann = true;
+                    double w[2], nr[2];
                     for (int k = 0; k < 2; ++k) {
-                        b.wall[q][k] = p->link_wall[(int64_t)(k * 8 + q) * N + n];
-                        b.nrm[q][k] = p->link_normal ? p->link_normal[(int64_t)(k * 8 + q) * N + n] : 0.0;
-                        if (!std::isfinite(b.wall[q][k]) || !std::isfinite(b.nrm[q][k]))
+                        w[k] = p->link_wall[(int64_t)(k * 8 + q) * N + n];
+                        nr[k] = p->link_normal ? p->link_normal[(int64_t)(k * 8 + q) * N + n] : 0.0;
+                        if (!std::isfinite(w[k]) || !std::isfinite(nr[k]))
                             return fail(nullptr, SLBM_ENONFINITE, "non-finite wall data");
                     }
+                    closure_coefs(q, kind == SLBM_LINK_DIRICHLET, w[0], w[1], nr[0], nr[1], b.coef[q]);
                 }
                 if (b.cut) {
                     code[n] = (int32_t)bn.size() + 1;
@@ -809,7 +908,6 @@ int solid_lbm_init(const slbm_problem* p, slbm_ctx** out)
     if (masked) {
         A(&c->code, N * sizeof(int32_t));
         A(&c->bnodes, std::max<size_t>(1, bn.size()) * sizeof(BNode));
-        A(&c->bjac, std::max<size_t>(1, bn.size()) * 128 * sizeof(double));
     }
     if (p->obs_mask) A(&c->obs, N);
 #undef A
@@ -1010,6 +1108,11 @@ int solid_lbm_time_sweeps(slbm_ctx* c, int32_t adjoint, int64_t n, double* ms)
     double** bufs = adjoint ? c->abuf : c->fbuf;
     int cur = adjoint ? c->adj_cur : c->prim_cur;
     const int T = fused_steps(c);
+    const int TL = tile_steps(c);
+    if (TL > 1 && c->masked) {
+        int rc = tile_lds_limits(c);
+        if (rc) return rc;
+    }
     HIPCHK(c, hipEventRecord(c->t0, c->stream));
     for (int64_t s = 0; s < n;) {
         a.src = bufs[cur];
@@ -1017,6 +1120,10 @@ int solid_lbm_time_sweeps(slbm_ctx* c, int32_t adjoint, int64_t n, double* ms)
         if (T > 1 && n - s >= T) {
             launch_fused(c, adjoint != 0, a, T);
             s += T;
+        } else if (TL > 1 && n - s >= 2) {
+            const int k = (int)std::min<int64_t>(n - s, TL);
+            launch_tile(c, adjoint != 0, a, k, TL);
+            s += k;
         } else {
             launch_sweep(c, adjoint != 0, a, false);
             ++s;
@@ -1085,12 +1192,31 @@ int solid_lbm_objective(slbm_ctx* c, double* J)
     return SLBM_OK;
 }
 
+int solid_lbm_set_tiles(slbm_ctx* c, int32_t tile_w, int32_t tile_h)
+{
+    if (!c) return SLBM_EINVAL;
+    if ((tile_w == 0) != (tile_h == 0) || tile_w < 0 || tile_h < 0)
+        return fail(c, SLBM_EINVAL, "tile_w and tile_h must both be 0 (automatic) or both >= 1");
+    if (tile_w > 0) {
+        const int h = tile_halo(c);
+        if ((tile_w + 2 * h) * (tile_h + 2 * h) > kTileMaxNodes)
+            return fail(c, SLBM_EINVAL, "tile plus halo exceeds " + std::to_string(kTileMaxNodes) + " nodes");
+    }
+    c->tile_w = tile_w;
+    c->tile_h = tile_h;
+    return SLBM_OK;
+}
+
 int solid_lbm_set_tuning(slbm_ctx* c, int32_t steps_per_launch, int32_t rows_per_wave)
 {
     if (!c) return SLBM_EINVAL;
-    if (!(steps_per_launch == -1 || steps_per_launch == 0 || steps_per_launch == 1 || steps_per_launch == 2 ||
-          steps_per_launch == 4 || steps_per_launch == 6 || steps_per_launch == 8))
-        return fail(c, SLBM_EINVAL, "steps_per_launch must be -1 (automatic), 0, 1, 2, 4, 6 or 8");
+    if (steps_per_launch < -1 || steps_per_launch > 8)
+        return fail(c, SLBM_EINVAL, "steps_per_launch must be -1 (automatic) or 0 .. 8");
+    if (!(c->masked || c->kind == SLBM_CTRL_E_NODAL) && steps_per_launch > 1 && (steps_per_launch & 1))
+        return fail(c, SLBM_EINVAL, "periodic bulk problems fuse 2, 4, 6 or 8 steps per launch");
+    if (c->tile_w > 0 && steps_per_launch > 1 &&
+        (c->tile_w + 2 * steps_per_launch) * (c->tile_h + 2 * steps_per_launch) > kTileMaxNodes)
+        return fail(c, SLBM_EINVAL, "tile plus halo exceeds " + std::to_string(kTileMaxNodes) + " nodes");
     if (rows_per_wave < 0) return fail(c, SLBM_EINVAL, "rows_per_wave must be >= 0");
     c->tb_T = steps_per_launch;
     c->tb_H = rows_per_wave;

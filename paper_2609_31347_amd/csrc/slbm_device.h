@@ -79,9 +79,50 @@ struct BNode {
     uint32_t cut;        // bit q set: x - c_q is outside (f_q needs a closure)
     uint32_t dirichlet;  // bit q set: that closure is Dirichlet, else Neumann
     uint32_t pad;
-    double wall[8][2];   // d_D (Dirichlet) or T (Neumann), lattice units
-    double nrm[8][2];    // outward unit normal (Neumann)
+    // closure of cut link q as an affine form of the node's bared stress:
+    // h_q = +-fC_qbar + k[0] sxx + k[1] syy + k[2] sxy + k[3]
+    // (+ for Dirichlet, - for Neumann; k[3] carries the wall data d_D or T)
+    double coef[8][4];
 };
+
+// Closure coefficients of one cut link (host, at set-up).  The closures
+// (the paper defers their formulas; this is the build's own first-order
+// design, wall point at the link midpoint):
+//   Dirichlet  h_q = fC_qbar + 2 W_q c_q . d_D,   W = 1/3 (axis), 1/12 (diagonal)
+//              (W_q c_q . d are the populations whose moments are N d)
+//   Neumann    h_q = -fC_qbar + 2 fsig_q(sigma_w),  fsig the populations with
+//              second moments -sigma_w and no others; sigma_w = the node's bared
+//              stress sigma with its traction on the wall normal n replaced by T:
+//              sigma_w = sigma + n a^T + a n^T - (a.n) n n^T,  a = T - sigma n.
+// sigma_w is linear in (sigma, T), so 2 fsig_q(sigma_w) = u . sigma + v(T);
+// u and v are formed by evaluating that map on unit stresses and on T.
+inline double neumann_closure(int q, double sxx, double syy, double sxy, double tx, double ty, double nx,
+                              double ny)
+{
+    double ax = tx - (sxx * nx + sxy * ny);
+    double ay = ty - (sxy * nx + syy * ny);
+    double an = ax * nx + ay * ny;
+    double wxx = sxx + 2.0 * nx * ax - an * nx * nx;
+    double wyy = syy + 2.0 * ny * ay - an * ny * ny;
+    double wxy = sxy + ax * ny + ay * nx - an * nx * ny;
+    double fs = q == 0 || q == 2 ? -0.5 * wxx : q == 1 || q == 3 ? -0.5 * wyy : q == 4 || q == 6 ? -0.25 * wxy
+                                                                                                  : 0.25 * wxy;
+    return 2.0 * fs;
+}
+
+inline void closure_coefs(int q, bool dirichlet, double w0, double w1, double nx, double ny, double k[4])
+{
+    if (dirichlet) {
+        const double W = q < 4 ? 1.0 / 3.0 : 1.0 / 12.0;
+        k[0] = k[1] = k[2] = 0.0;
+        k[3] = 2.0 * W * (cx(q) * w0 + cy(q) * w1);
+        return;
+    }
+    k[0] = neumann_closure(q, 1.0, 0.0, 0.0, 0.0, 0.0, nx, ny);
+    k[1] = neumann_closure(q, 0.0, 1.0, 0.0, 0.0, 0.0, nx, ny);
+    k[2] = neumann_closure(q, 0.0, 0.0, 1.0, 0.0, 0.0, nx, ny);
+    k[3] = neumann_closure(q, 0.0, 0.0, 0.0, w0, w1, nx, ny);
+}
 
 // ---------------------------------------------------------------- node map
 // Extended node map: populations f^S of one node and its forcing g ->
@@ -89,13 +130,8 @@ struct BNode {
 // h_q of the cut links (taken as f^S_q(x) at the next step).  mb holds the
 // bared moments (m10, m01, m11, m_s, m_d).
 //
-// Closures (the paper defers their formulas; this is the build's own first-order
-// design): wall point at the link midpoint,
-//   Dirichlet  h_q = fC_qbar + 2 W_q c_q . d_D,   W = 1/3 (axis), 1/12 (diagonal)
-//              (W_q c_q . d are the populations whose moments are N d)
-//   Neumann    h_q = -fC_qbar + 2 fsig_q(sigma_w),  fsig the populations with
-//              second moments -sigma_w and no others; sigma_w = the node's bared
-//              stress with its traction on the wall normal n replaced by T.
+// Closures: the affine forms of BNode::coef (see closure_coefs); with_walls
+// = false drops the wall terms (the linear part, for the adjoint Jacobian).
 template <class T>
 __host__ __device__ inline void node_map(const T f[8], const T g[2], const Relax<T>& r,
                                          const BNode* bn, bool with_walls, T fC[8], T h[8],
@@ -138,29 +174,16 @@ __host__ __device__ inline void node_map(const T f[8], const T g[2], const Relax
     T sxx = -T(0.5) * (mb[3] + mb[4]);
     T syy = -T(0.5) * (mb[3] - mb[4]);
     T sxy = -mb[2];
+    // branch-free: all eight links are formed and the cut bits select, so the
+    // record's loads go out together
+    const uint32_t cut = bn->cut, dir = bn->dirichlet;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        h[q] = T(0.0);
-        if (!((bn->cut >> q) & 1u)) continue;
-        T w0 = with_walls ? T(bn->wall[q][0]) : T(0.0);
-        T w1 = with_walls ? T(bn->wall[q][1]) : T(0.0);
-        if ((bn->dirichlet >> q) & 1u) {
-            double W = q < 4 ? 1.0 / 3.0 : 1.0 / 12.0;
-            h[q] = fC[opp(q)] + T(2.0 * W) * (T((double)cx(q)) * w0 + T((double)cy(q)) * w1);
-        } else {
-            double nx = bn->nrm[q][0], ny = bn->nrm[q][1];
-            T ax = w0 - (sxx * T(nx) + sxy * T(ny));
-            T ay = w1 - (sxy * T(nx) + syy * T(ny));
-            T an = ax * T(nx) + ay * T(ny);
-            T wxx = sxx + T(2.0 * nx) * ax - an * T(nx * nx);
-            T wyy = syy + T(2.0 * ny) * ay - an * T(ny * ny);
-            T wxy = sxy + ax * T(ny) + ay * T(nx) - an * T(nx * ny);
-            T fs = q == 0 || q == 2 ? -T(0.5) * wxx
-                 : q == 1 || q == 3 ? -T(0.5) * wyy
-                 : q == 4 || q == 6 ? -T(0.25) * wxy
-                                    : T(0.25) * wxy;
-            h[q] = T(2.0) * fs - fC[opp(q)];
-        }
+        const double* k = bn->coef[q];
+        T lin = T(k[0]) * sxx + T(k[1]) * syy + T(k[2]) * sxy;
+        if (with_walls) lin = lin + T(k[3]);
+        T hq = (((dir >> q) & 1u) ? fC[opp(q)] : -fC[opp(q)]) + lin;
+        h[q] = ((cut >> q) & 1u) ? hq : T(0.0);
     }
 }
 
@@ -229,6 +252,58 @@ __device__ __forceinline__ void adj_collide_bulk(double p[8], double srx, double
     p[5] = t - x11 + (x01 - x10);
     p[6] = t + x11 - (x10 + x01);
     p[7] = t - x11 + (x10 - x01);
+}
+
+// Transposed map of a boundary node (eq. adjoint_collision at nodes with cut
+// links): the adjoint of the linear part of node_map (with_walls = false),
+//   fC = C_b f,  h_q = s_q fC_qbar + u_q . sigma(f)   (s_q = +1 Dirichlet, -1 Neumann),
+// applied to yf (adjoint of fC, pulled from x + c_q) and yh (adjoint of the
+// closure values, the node's own slots of its cut links, 0 elsewhere):
+//   out = C_b^T (yf + sum_q s_q yh_q e_qbar) + (d sigma / d f)^T (sum_q yh_q u_q) - s (r . c_q).
+// C_b = M^{-1} A_b M differs from the bulk collision by m_f = 0 after the
+// collision, m22 = -gamma k_s m_s; the transpose runs through the moments as
+// adj_collide_bulk does and equals it for gamma = 0 and no cut links.
+__host__ __device__ inline void adj_boundary(const double yf[8], const double yh[8], const BNode* bn,
+                                             const Relax<double>& r, double srx, double sry, double out[8])
+{
+    const uint32_t dir = bn->dirichlet;
+    double z[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) z[q] = yf[q];
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double y = yh[q];
+        z[opp(q)] += ((dir >> q) & 1u) ? y : -y;
+        w0 += y * bn->coef[q][0];
+        w1 += y * bn->coef[q][1];
+        w2 += y * bn->coef[q][2];
+    }
+    // gradients w.r.t. the post-collision moments (M^{-T} z)
+    const double pa = 0.5 * (z[0] - z[2]), pb = 0.5 * (z[1] - z[3]);
+    const double ps = 0.25 * ((z[0] + z[1]) + (z[2] + z[3]));
+    const double pd = 0.25 * ((z[0] - z[1]) + (z[2] - z[3]));
+    const double p11 = 0.25 * ((z[4] - z[5]) + (z[6] - z[7]));
+    const double p12 = 0.25 * ((z[4] - z[5]) - (z[6] - z[7]));
+    const double p21 = 0.25 * ((z[4] + z[5]) - (z[6] + z[7]));
+    const double p22 = 0.25 * ((z[4] + z[5]) + (z[6] + z[7]));
+    // gradients w.r.t. the pre-collision moments; stress term: sxx = -(mb_s + mb_d)/2,
+    // syy = -(mb_s - mb_d)/2, sxy = -mb_11 with mb = (1 + k) m / 2
+    const double g10 = (1.0 - kTheta) * pa + kTheta * p12 - srx;
+    const double g01 = (1.0 - kTheta) * pb + kTheta * p21 - sry;
+    const double g11 = r.k11 * p11 - 0.5 * (1.0 + r.k11) * w2;
+    const double gs = r.ks * ((1.0 + 2.0 * r.gam) * ps - r.gam * p22) - 0.25 * (1.0 + r.ks) * (w0 + w1);
+    const double gd = r.kd * pd - 0.25 * (1.0 + r.kd) * (w0 - w1);
+    // M^T g
+    out[0] = g10 + gs + gd;
+    out[1] = g01 + gs - gd;
+    out[2] = gs + gd - g10;
+    out[3] = gs - gd - g01;
+    const double t = 2.0 * gs;
+    out[4] = t + g11 + (g10 + g01);
+    out[5] = t - g11 + (g01 - g10);
+    out[6] = t + g11 - (g10 + g01);
+    out[7] = t - g11 + (g10 - g01);
 }
 
 }  // namespace slbm

@@ -37,7 +37,6 @@ struct SweepArgs {
     const double* __restrict__ E;     // 1 plane Young's modulus (E field) or null
     const int32_t* __restrict__ code; // masked: -1 outside, 0 bulk, k+1 boundary record k
     const BNode* __restrict__ bnodes;
-    const double* __restrict__ bjac;  // adjoint: 128 doubles per boundary node
     double* __restrict__ snap;        // check sweeps: 2 planes, d(t - K)
     double* __restrict__ partial;     // check sweeps: 2 doubles per block
     const Status* __restrict__ status;
@@ -189,21 +188,17 @@ __device__ __forceinline__ void adjoint_node(const SweepArgs& a, int64_t n, doub
 #pragma unroll
         for (int q = 0; q < 8; ++q) a.dst[q * N + n] = p[q];
     } else {
-        // transposed extended map: out_p = sum_r jac[r][p] ext_r - src_p,
-        // ext = (routed regular slots, own slots of the cut links)
+        // transposed extended map of the boundary node: inputs are the routed
+        // regular slots and the node's own slots of its cut links
         const BNode* bn = a.bnodes + (code - 1);
-        const double* J = a.bjac + (int64_t)(code - 1) * 128;
-        double ext[16];
+        const Relax<double> r = relax_from_E<double>(EFIELD ? a.E[n] : a.E0, a.nu, true);
+        double yh[8], out[8];
+        const uint32_t cut = bn->cut;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            ext[q] = p[q];
-            ext[8 + q] = ((bn->cut >> q) & 1u) ? a.src[q * N + n] : 0.0;
-        }
-        for (int pp = 0; pp < 8; ++pp) {
-            double s = 0.0;
-            for (int r = 0; r < 16; ++r) s += J[r * 8 + pp] * ext[r];
-            a.dst[pp * N + n] = s - (srx * cx(pp) + sry * cy(pp));
-        }
+        for (int q = 0; q < 8; ++q) yh[q] = ((cut >> q) & 1u) ? a.src[q * N + n] : 0.0;
+        adj_boundary(p, yh, bn, r, srx, sry, out);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a.dst[q * N + n] = out[q];
     }
 }
 
@@ -388,31 +383,6 @@ __global__ __launch_bounds__(kBlock) void k_primal_finalize(
         }
     }
     block_sum2(s, 0.0, partial + 2 * (int64_t)blockIdx.x);
-}
-
-// ---------------------------------------------------------------- boundary Jacobians
-// jac[r][p] = d out_r / d f_p of the extended node map (fC rows 0..7, closure
-// rows 8..15) of every boundary node: the map is affine in f, so its linear
-// part (zero forcing, zero walls) applied to unit vectors is the Jacobian.
-__global__ __launch_bounds__(64) void k_boundary_jacobian(const BNode* __restrict__ bnodes, int nb,
-                                                         const double* __restrict__ E, double E0, double nu,
-                                                         double* __restrict__ jac)
-{
-    int b = blockIdx.x * 64 + threadIdx.x;
-    if (b >= nb) return;
-    const BNode* bn = bnodes + b;
-    Relax<double> r = relax_from_E<double>(E ? E[bn->cell] : E0, nu, true);
-    double* J = jac + (int64_t)b * 128;
-    for (int p = 0; p < 8; ++p) {
-        double e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        e[p] = 1.0;
-        double g0[2] = {0.0, 0.0}, fC[8], h[8], mb[5];
-        node_map<double>(e, g0, r, bn, false, fC, h, mb);
-        for (int q = 0; q < 8; ++q) {
-            J[q * 8 + p] = fC[q];
-            J[(8 + q) * 8 + p] = h[q];
-        }
-    }
 }
 
 // ---------------------------------------------------------------- finalize adjoint + gradient
@@ -758,6 +728,189 @@ __global__ __launch_bounds__(64) void k_sweep_tb(TBArgs a)
 {
     if (a.status->stop) return;
     tb_strip<T, ADJ>(a, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------- fused sweeps, plates and E fields
+// Several sweeps of a plate (masked domain with boundary closures) or of a
+// per-node modulus field per launch.  A workgroup owns a tile of tw x th
+// nodes; it loads the tile plus a halo of `halo` nodes (all 8 planes) into
+// LDS, runs `steps` <= halo sweeps there in place, and writes only the
+// tile's own nodes (and the ghost slots of its boundary nodes) back to HBM.
+// Sweep s computes the tile grown by steps - s nodes, so every value it
+// pulls was produced by sweep s - 1 inside the region.  Each sweep reads all
+// pulls first and writes after a barrier; a ghost slot (x - c_q, q) of a cut
+// link is read and written only by its boundary node x (and an adjoint
+// boundary node's own slot of a cut link only by x), so those are written
+// at once.  The per-node arithmetic is the single-step kernels' own, so a
+// launch of k steps equals k single sweeps bit for bit.
+struct TileArgs {
+    const double* __restrict__ src;
+    double* __restrict__ dst;
+    const double* __restrict__ g;     // primal: forcing; adjoint: r
+    const double* __restrict__ E;     // E plane or null
+    const int32_t* __restrict__ code;
+    const BNode* __restrict__ bnodes;
+    const Status* __restrict__ status;
+    int32_t nx, ny;
+    int64_t N;
+    double k11, ks, kd, E0, nu, scale;
+    int32_t tw, th, halo, steps, tiles_x;
+};
+
+constexpr int kTileBlock = 1024;
+constexpr int kTileNPT = 1;                          // region nodes per thread
+constexpr int kTileMaxNodes = kTileBlock * kTileNPT; // region <= 1024 nodes (64 KiB of LDS)
+// Boundary records staged in LDS once per launch (plates); records beyond
+// the cap are read from HBM / L2 (same values, only slower).
+constexpr int kTileMaxB = 96;                        // 96 x 272 B
+
+__host__ __device__ constexpr size_t tile_lds_bytes(int region, bool masked)
+{
+    return (size_t)8 * region * sizeof(double) + (masked ? (size_t)kTileMaxB * sizeof(BNode) : 0);
+}
+
+template <bool MASKED, bool EFIELD, bool ADJ>
+__global__ __launch_bounds__(kTileBlock) void k_sweep_tile(TileArgs a)
+{
+    if (a.status->stop) return;
+    extern __shared__ __align__(16) double lds[];    // 8 planes of RX * RY doubles, then staged records
+    const int h = a.halo, RX = a.tw + 2 * h, RY = a.th + 2 * h, R = RX * RY;
+    const int bx = blockIdx.x % a.tiles_x, by = blockIdx.x / a.tiles_x;
+    const int x0 = bx * a.tw - h, y0 = by * a.th - h;   // unwrapped origin of the region
+    const int nx = a.nx, ny = a.ny;
+    const int64_t N = a.N;
+    // per-node constants of the launch, held in registers: position, code,
+    // source term (primal: g; adjoint: s r) and relaxation (the same
+    // relax_from_E values the single-step kernels form every step)
+    int rx[kTileNPT], ry[kTileNPT], cd[kTileNPT];
+    int64_t gn[kTileNPT];
+    double c0[kTileNPT], c1[kTileNPT];
+    Relax<double> rl[kTileNPT];
+    // staged boundary records
+    __shared__ int nstaged;
+    BNode* lbn = reinterpret_cast<BNode*>(lds + 8 * R);
+    const BNode* bnp[kTileNPT];
+    if (MASKED) {
+        if (threadIdx.x == 0) nstaged = 0;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < kTileNPT; ++j) {
+        const int i = threadIdx.x + j * kTileBlock;
+        rx[j] = i % RX;
+        ry[j] = i / RX;
+        cd[j] = -1;
+        gn[j] = 0;
+        c0[j] = c1[j] = 0.0;
+        rl[j].k11 = a.k11;
+        rl[j].ks = a.ks;
+        rl[j].kd = a.kd;
+        rl[j].gam = 0.0;
+        if (i < R) {
+            const int64_t n = (int64_t)wrapi(y0 + ry[j], ny) * nx + wrapi(x0 + rx[j], nx);
+            gn[j] = n;
+            cd[j] = MASKED ? a.code[n] : 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lds[q * R + i] = a.src[q * N + n];
+            if (cd[j] >= 0) {
+                if (ADJ) {
+                    c0[j] = a.scale * a.g[n];
+                    c1[j] = a.scale * a.g[N + n];
+                } else {
+                    c0[j] = a.g[n];
+                    c1[j] = a.g[N + n];
+                }
+                if (EFIELD || cd[j] > 0) rl[j] = relax_from_E<double>(EFIELD ? a.E[n] : a.E0, a.nu, cd[j] > 0);
+            }
+        }
+        bnp[j] = nullptr;
+        if (MASKED && i < R && cd[j] > 0) {
+            const int k = cd[j] - 1;
+            const int slot = atomicAdd(&nstaged, 1);
+            bnp[j] = a.bnodes + k;
+            if (slot < kTileMaxB) {
+                const double2* s2 = reinterpret_cast<const double2*>(a.bnodes + k);
+                double2* d2 = reinterpret_cast<double2*>(lbn + slot);
+#pragma unroll
+                for (int w = 0; w < (int)(sizeof(BNode) / 16); ++w) d2[w] = s2[w];
+                bnp[j] = lbn + slot;
+            }
+        }
+    }
+    __syncthreads();
+    for (int s = 1; s <= a.steps; ++s) {
+        const bool last = s == a.steps;
+        const int m = h - (a.steps - s);             // this sweep computes [m, RX - m) x [m, RY - m)
+        double out[kTileNPT][8];
+        bool act[kTileNPT];
+#pragma unroll
+        for (int j = 0; j < kTileNPT; ++j) {
+            const int i = threadIdx.x + j * kTileBlock;
+            act[j] = i < R && cd[j] >= 0 && rx[j] >= m && rx[j] < RX - m && ry[j] >= m && ry[j] < RY - m;
+            // the last sweep writes HBM: only nodes of the grid proper (no wrapped copies)
+            if (last) act[j] = act[j] && x0 + rx[j] < nx && y0 + ry[j] < ny;
+            if (!act[j]) continue;
+            const int64_t n = gn[j];
+            const int code = cd[j];
+            double f[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int off = cx(q) + cy(q) * RX;
+                f[q] = lds[q * R + (ADJ ? i + off : i - off)];
+            }
+            if (!ADJ) {
+                if (!MASKED || code == 0) {
+                    double d0, d1;
+                    collide_bulk(f, c0[j], c1[j], rl[j].k11, rl[j].ks, rl[j].kd, d0, d1);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) out[j][q] = f[q];
+                } else {
+                    const BNode* bn = bnp[j];
+                    double gg[2] = {c0[j], c1[j]}, fC[8], hv[8], mb[5];
+                    node_map<double>(f, gg, rl[j], bn, true, fC, hv, mb);
+                    const uint32_t cut = bn->cut;
+                    int64_t idx[8];
+                    if (last) neighbours((int)(n % nx), (int)(n / nx), nx, ny, idx, +1);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        out[j][q] = fC[q];
+                        if ((cut >> q) & 1u) {
+                            if (last) a.dst[q * N + idx[q]] = hv[q];
+                            else lds[q * R + i - (cx(q) + cy(q) * RX)] = hv[q];
+                        }
+                    }
+                }
+            } else {
+                const double srx = c0[j], sry = c1[j];
+                if (!MASKED || code == 0) {
+                    adj_collide_bulk(f, srx, sry, rl[j].k11, rl[j].ks, rl[j].kd);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) out[j][q] = f[q];
+                } else {
+                    const BNode* bn = bnp[j];
+                    const uint32_t cut = bn->cut;
+                    double yh[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) yh[q] = ((cut >> q) & 1u) ? lds[q * R + i] : 0.0;
+                    adj_boundary(f, yh, bn, rl[j], srx, sry, out[j]);
+                }
+            }
+            if (last) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) a.dst[q * N + n] = out[j][q];
+            }
+        }
+        if (last) break;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kTileNPT; ++j) {
+            if (!act[j]) continue;
+            const int i = threadIdx.x + j * kTileBlock;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lds[q * R + i] = out[j][q];
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace slbm

@@ -25,7 +25,8 @@ EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_gra
            "adjoint_solve_vjp",
            "solid_lbm_restore_solve", "solid_lbm_objective", "solid_lbm_set_control",
            "solid_lbm_run_steps", "solid_lbm_run_adjoint_steps", "solid_lbm_get_field",
-           "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_last_error", "solid_lbm_destroy",
+           "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_set_tiles", "solid_lbm_last_error",
+           "solid_lbm_destroy",
            "solid_lbm_batch_init", "batch_objective_and_grad", "solid_lbm_batch_set_tuning",
            "solid_lbm_batch_time_sweeps", "solid_lbm_batch_instance", "solid_lbm_batch_last_error",
            "solid_lbm_batch_destroy")
@@ -74,6 +75,7 @@ def _load():
     lib.solid_lbm_get_field.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32]
     lib.solid_lbm_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.solid_lbm_set_tiles.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.adjoint_solve_vjp.argtypes = [P, P, P, ctypes.c_int32, info]
     lib.objective_and_grad_from.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double), P, ctypes.c_int32, info, info]
     lib.solid_lbm_restore_solve.argtypes = [P, P, P, ctypes.c_int32]
@@ -307,6 +309,10 @@ def solid_lbm_set_tuning(ctx, steps_per_launch=-1, rows_per_wave=0):
     return _check(ctx, LIB.solid_lbm_set_tuning(ctx.handle, int(steps_per_launch), int(rows_per_wave)))
 
 
+def solid_lbm_set_tiles(ctx, tile_w=0, tile_h=0):
+    return _check(ctx, LIB.solid_lbm_set_tiles(ctx.handle, int(tile_w), int(tile_h)))
+
+
 def solid_lbm_destroy(ctx):
     if ctx.handle:
         LIB.solid_lbm_destroy(ctx.handle)
@@ -327,11 +333,11 @@ class Batch:
     def __len__(self):
         return len(self.contexts)
 
-    def __del__(self):
+    def __del__(self, _destroy=LIB.solid_lbm_batch_destroy):
         if getattr(self, "handle", None):
             for c in self.contexts:
                 c.handle = None
-            LIB.solid_lbm_batch_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
 

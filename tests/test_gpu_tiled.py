@@ -1,0 +1,188 @@
+"""LDS-tiled fused sweeps of plates and E-field controls (needs a GPU).
+
+A launch of k steps must perform exactly the arithmetic of k single sweeps:
+populations after a fixed step count equal the single-step path bit for bit
+and the oracle to 1e-12, for the primal and the adjoint, with ragged tiles,
+step counts that do not divide the run, grids narrower than a region (the
+periodic region wraps onto itself) and every halo up to 8.
+"""
+import numpy as np
+import pytest
+
+from paper_2609_31347_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL_D = 1e-12
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_31347_amd import slbm
+    return slbm
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def plate_problem(S, pd, kind, **kw):
+    d = dict(nx=pd["nx"], ny=pd["ny"], dx=pd["dx"], E=pd.get("E", 1.0), nu=pd.get("nu", 0.3), domain=S.MASKED,
+             node_mask=pd["active"].astype(np.uint8), link_bc=pd["bc"], link_wall=pd["wall"],
+             link_normal=pd["normal"], target=pd.get("target", np.zeros((2, pd["ny"], pd["nx"]))),
+             control_kind=kind)
+    d.update(kw)
+    return d
+
+
+def oracle_plate(orc, p, g, E):
+    return orc.Problem(p["nx"], p["ny"], p["dx"], E, p["nu"], g, active=p["node_mask"], bc=p["link_bc"],
+                       wall=p["link_wall"], normal=p["link_normal"])
+
+
+@pytest.fixture(scope="module")
+def plate16():
+    return I.paper_plate(16)
+
+
+def e_field(pd, seed):
+    ny, nx = pd["active"].shape
+    return pd.get("E", 1.0) * (1.0 + 0.4 * np.tanh(I.grf(nx, ny, pd["dx"], 1.0, 0.2, seed)[0]))
+
+
+@pytest.mark.parametrize("T,tiles", [(2, (0, 0)), (3, (5, 3)), (4, (0, 0)), (5, (7, 11)), (8, (16, 16)),
+                                     (8, (1, 1))])
+@pytest.mark.parametrize("kind", ["force", "E"])
+def test_tiled_plate_sweeps_match_oracle(S, orc, plate16, T, tiles, kind):
+    pd = plate16
+    steps = 3 * T + 2
+    if kind == "force":
+        p = plate_problem(S, pd, S.CTRL_FORCE_NODAL)
+        control, E = pd["F"], pd["E"]
+    else:
+        p = plate_problem(S, pd, S.CTRL_E_NODAL, fixed_force=pd["F"])
+        control = E = e_field(pd, 5)
+    ctx = S.solid_lbm_init(p)
+    S.solid_lbm_set_tuning(ctx, T, 0)
+    S.solid_lbm_set_tiles(ctx, *tiles)
+    S.solid_lbm_set_control(ctx, control)
+    S.solid_lbm_run_steps(ctx, steps)
+    q = oracle_plate(orc, p, pd["F"] * pd["dx"] ** 2 * pd["active"], E)
+    f = orc.run(q, q.zeros(8), steps)
+    _, d, _ = orc.step(q, f)
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_POPS), f) < TOL_D
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_CUR_DISP), d) < TOL_D
+
+
+@pytest.mark.parametrize("T", [1, 4, 8])
+@pytest.mark.parametrize("kind", ["force", "E"])
+def test_plate_adjoint_fixed_steps_match_oracle(S, orc, plate16, T, kind):
+    """Adjoint sweeps of a plate (boundary nodes apply the transposed node map
+    in closed form) against the oracle's transposed probed node Jacobians."""
+    pd = plate16
+    if kind == "force":
+        p = plate_problem(S, pd, S.CTRL_FORCE_NODAL, tol=1e-10)
+        control, E = pd["F"] * 1.1, pd["E"]
+        g = pd["F"] * 1.1 * pd["dx"] ** 2 * pd["active"]
+    else:
+        p = plate_problem(S, pd, S.CTRL_E_NODAL, fixed_force=pd["F"], tol=1e-10)
+        control = E = e_field(pd, 5)
+        g = pd["F"] * pd["dx"] ** 2 * pd["active"]
+    ctx = S.solid_lbm_init(p)
+    S.solid_lbm_set_tuning(ctx, T, 0)
+    S.primal_solve(ctx, control)
+    r = S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL)
+    steps = 3 * T + 5
+    S.solid_lbm_run_adjoint_steps(ctx, steps)
+    q = oracle_plate(orc, p, g, E)
+    src = orc.source(q, r, pd["dx"] ** 2 / orc.cbar(q, pd["target"]))
+    ph = q.zeros(8)
+    for _ in range(steps):
+        ph = orc.adj_step(q, ph, src)[0]
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS), ph) < TOL_D
+
+
+def _fixed_step_fields(S, p, control, T, tiles, steps, adjoint_steps):
+    ctx = S.solid_lbm_init(p)
+    S.solid_lbm_set_tuning(ctx, T, 0)
+    S.solid_lbm_set_tiles(ctx, *tiles)
+    S.solid_lbm_set_control(ctx, control)
+    S.solid_lbm_run_steps(ctx, steps)
+    pops = S.solid_lbm_get_field(ctx, S.FIELD_POPS)
+    rc, info = S.primal_solve(ctx, control)
+    S.solid_lbm_run_adjoint_steps(ctx, adjoint_steps)
+    return pops, S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS), info.steps
+
+
+def _cases(S):
+    cp = I.clamped_plate(64, 39)
+    pd = dict(cp, E=1.0, nu=0.3)
+    plate_e = (plate_problem(S, pd, S.CTRL_E_NODAL, tol=1e-9, max_steps=400000, normalize_objective=0),
+               e_field(pd, 3))
+    p16 = I.paper_plate(16)
+    plate_f = (plate_problem(S, p16, S.CTRL_FORCE_NODAL, tol=1e-9), p16["F"] * 1.3)
+    out = [("plate_E", plate_e), ("plate_force", plate_f)]
+    for nx, ny in ((20, 9), (100, 37)):
+        dx = 1.0 / 48
+        F = I.grf(nx, ny, dx, 0.05, 0.1, 21, comps=2)
+        F = F - F.mean((1, 2), keepdims=True)
+        tgt = I.grf(nx, ny, dx, 1e-6, 0.15, 22, comps=2)
+        E = 1.0 + 0.3 * np.tanh(I.grf(nx, ny, dx, 1.0, 0.2, 9)[0])
+        p = dict(nx=nx, ny=ny, dx=dx, E=1.0, nu=0.3, domain=0, target=tgt, control_kind=S.CTRL_E_NODAL,
+                 fixed_force=F, tol=1e-9)
+        out.append((f"periodic_E_{nx}x{ny}", (p, E)))
+    return out
+
+
+@pytest.mark.parametrize("T,tiles", [(3, (0, 0)), (8, (5, 7)), (4, (24, 24))])
+def test_tiled_sweeps_equal_single_step_bit_for_bit(S, T, tiles):
+    for name, (p, control) in _cases(S):
+        steps, asteps = 7 * T + 1, 5 * T + 3
+        ref = _fixed_step_fields(S, p, control, 1, (0, 0), steps, asteps)
+        got = _fixed_step_fields(S, p, control, T, tiles, steps, asteps)
+        assert ref[2] == got[2], name
+        assert np.array_equal(ref[0], got[0]), (name, rel(got[0], ref[0]))
+        assert np.array_equal(ref[1], got[1]), (name, rel(got[1], ref[1]))
+
+
+def test_tiled_and_single_step_gradients_identical(S):
+    cp = I.clamped_plate(48, 29)
+    pd = dict(cp, E=1.0, nu=0.3)
+    E = e_field(pd, 11)
+    ctx0 = S.solid_lbm_init(plate_problem(S, pd, S.CTRL_E_NODAL, tol=1e-9, normalize_objective=0))
+    S.primal_solve(ctx0, E * 1.1)
+    target = S.solid_lbm_get_field(ctx0, S.FIELD_DISP)
+    out = []
+    for T in (1, 4, 7):
+        ctx = S.solid_lbm_init(plate_problem(S, pd, S.CTRL_E_NODAL, tol=1e-9, target=target))
+        S.solid_lbm_set_tuning(ctx, T, 0)
+        rc, J, grad, pi, ai = S.objective_and_grad(ctx, E)
+        out.append((J, np.asarray(grad), pi.steps, ai.steps))
+    for o in out[1:]:
+        assert o[2:] == out[0][2:]
+        assert o[0] == out[0][0]
+        assert np.array_equal(o[1], out[0][1])
+
+
+def test_tuning_limits(S, plate16):
+    pd = plate16
+    ctx = S.solid_lbm_init(plate_problem(S, pd, S.CTRL_FORCE_NODAL))
+    S.solid_lbm_set_tuning(ctx, 7, 0)                       # any count 2..8 for plates
+    with pytest.raises(S.SlbmError):
+        S.solid_lbm_set_tiles(ctx, 30, 30)                  # (30 + 14)^2 > 1024 nodes
+    with pytest.raises(S.SlbmError):
+        S.solid_lbm_set_tiles(ctx, 4, 0)
+    with pytest.raises(S.SlbmError):
+        S.solid_lbm_set_tuning(ctx, 9, 0)
+    S.solid_lbm_set_tiles(ctx, 18, 18)                      # (18 + 14)^2 = 1024
+    with pytest.raises(S.SlbmError):
+        S.solid_lbm_set_tuning(ctx, 8, 0)                   # (18 + 16)^2 > 1024
+    n = 32
+    sol = I.paper_periodic(n)
+    pc = dict(nx=n, ny=n, dx=1 / n, E=1.0, nu=0.3, domain=0, target=sol["d"], control_kind=S.CTRL_FORCE_NODAL)
+    ctx = S.solid_lbm_init(pc)
+    with pytest.raises(S.SlbmError):
+        S.solid_lbm_set_tuning(ctx, 3, 0)                   # wave-strip kernel: 2, 4, 6, 8

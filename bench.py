@@ -29,8 +29,10 @@ PEAK_GBS = 8000.0           # MI355X HBM3E
 # Measured HBM bytes per launch of the dominant kernel, keyed by (N, T, H), from
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors of a plain device copy);
 # see profiles/.  Entries are dropped whenever the kernel changes.
-TRAFFIC_BYTES = {(1024, 8, 24): (2.0 * 121596.3 + 65536.0) * 1024,
-                 (2048, 8, 48): (2.0 * 381713.5 + 262144.0) * 1024}
+TRAFFIC_BYTES = {(1024, 8, 24): (2.0 * 121564.9 + 65536.0) * 1024,
+                 (1024, 6, 24): (2.0 * 98651.5 + 65536.0) * 1024,
+                 (1024, 4, 24): (2.0 * 82403.2 + 65536.0) * 1024,
+                 (2048, 8, 48): (2.0 * 381766.6 + 262144.0) * 1024}
 
 
 def parse():
@@ -45,6 +47,8 @@ def parse():
     ap.add_argument("--mode", choices=("gradient", "sweeps", "lbfgs", "batch", "warmstart"), default="gradient",
                     help="sweeps: time fixed counts of primal/adjoint sweeps and a reference copy "
                          "(for rocprofv3 kernel traces and counters)")
+    ap.add_argument("--plate", action="store_true", help="sweeps mode: the elliptic plate with an E field")
+    ap.add_argument("--tiles", default="", help="sweeps mode: tile w,h of the LDS-tiled plate sweeps")
     ap.add_argument("--sweeps", type=int, default=200)
     ap.add_argument("--fuse", type=int, default=-1, help="time steps fused per launch (-1 automatic)")
     ap.add_argument("--instances", type=int, default=96, help="batch mode: number of instances")
@@ -54,7 +58,8 @@ def parse():
     ap.add_argument("--train-iters", type=int, default=3000, help="warmstart mode: Adam iterations")
     ap.add_argument("--train-lr", type=float, default=5e-4, help="warmstart mode: peak Adam learning rate")
     ap.add_argument("--eval-sizes", default="64,128,256", help="warmstart mode: plate widths to evaluate")
-    ap.add_argument("--eval-fields", type=int, default=4, help="warmstart mode: held-out E fields per size")
+    ap.add_argument("--eval-fields", default="4", help="warmstart mode: held-out E fields per size "
+                                                         "(one number, or one per size)")
     ap.add_argument("--rows", type=int, default=0, help="rows per wave of fused launches (0 automatic)")
     return ap.parse_args()
 
@@ -68,19 +73,32 @@ def sweeps_mode(args):
     from paper_2609_31347_amd import slbm as S
     torch.cuda.set_device(0)
     n = args.n
-    modes = I.two_mode_basis(n)
-    tgt = I.two_mode_target(n)
-    ctx = S.solid_lbm_init(dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC, target=tgt,
-                                control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes, tol=0.0,
-                                max_steps=10, stream=torch.cuda.current_stream().cuda_stream))
+    if args.plate:
+        # elliptic plate of the E-field identification (box n x ceil(0.6 n)), E(x) from a GRF
+        from paper_2609_31347_amd import warmstart as WS
+        cp = WS.plate(n)
+        ny = cp["active"].shape[0]
+        tgt = 1e-3 * np.ones((2, ny, n)) * cp["active"]
+        ctx = S.solid_lbm_init(dict(WS.plate_problem(cp, 0.0, max_steps=10, target=tgt),
+                                    stream=torch.cuda.current_stream().cuda_stream))
+        a = WS.e_field(cp, 7)
+    else:
+        ny = n
+        modes = I.two_mode_basis(n)
+        tgt = I.two_mode_target(n)
+        ctx = S.solid_lbm_init(dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC, target=tgt,
+                                    control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes, tol=0.0,
+                                    max_steps=10, stream=torch.cuda.current_stream().cuda_stream))
+        a = np.array([0.1, 0.1])
     S.solid_lbm_set_tuning(ctx, args.fuse, args.rows)
-    a = np.array([0.1, 0.1])
+    if args.tiles:
+        S.solid_lbm_set_tiles(ctx, *[int(v) for v in args.tiles.split(",")])
     S.primal_solve(ctx, a)                       # 10 fixed steps: gives the adjoint its inputs
     S.solid_lbm_time_sweeps(ctx, 0, 20)          # warm-up
     S.solid_lbm_time_sweeps(ctx, 1, 20)
     ms_p = S.solid_lbm_time_sweeps(ctx, 0, args.sweeps)
     ms_a = S.solid_lbm_time_sweeps(ctx, 1, args.sweeps)
-    cells = n * n
+    cells = n * ny
     src = torch.empty(8 * cells, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -91,7 +109,8 @@ def sweeps_mode(args):
     ev1.record()
     torch.cuda.synchronize()
     ms_c = ev0.elapsed_time(ev1)
-    out = {"mode": "sweeps", "grid": [n, n], "sweeps": args.sweeps, "fuse": args.fuse, "rows": args.rows,
+    out = {"mode": "sweeps", "workload": "plate, E field" if args.plate else "periodic, two-mode force",
+           "grid": [n, ny], "sweeps": args.sweeps, "fuse": args.fuse, "rows": args.rows, "tiles": args.tiles,
            "primal_us": round(ms_p / args.sweeps * 1e3, 3), "adjoint_us": round(ms_a / args.sweeps * 1e3, 3),
            "primal_GBs": round(BYTES_PER_NODE * cells / (ms_p / args.sweeps * 1e-3) / 1e9, 1),
            "adjoint_GBs": round(BYTES_PER_NODE * cells / (ms_a / args.sweeps * 1e-3) / 1e9, 1),
@@ -235,33 +254,57 @@ def warmstart_mode(args):
              log=lambda r: print(json.dumps({"stage": "train", **r}), flush=True), Xv=X[:nv], Yv=Y[:nv])
     print(json.dumps({"stage": "trained", "wall_s": round(time.perf_counter() - t0, 2)}), flush=True)
     rows = []
-    for nx in [int(v) for v in args.eval_sizes.split(",")]:
+
+    def gradient(ctx, E, d0, cbar, dx, tag):
+        """Primal solve (cold or warm) then the adjoint: the objective's gradient
+        as the VJP of the residual r dx^2 / Cbar (the objective's own adjoint
+        source), in two calls so that each one reports when it ends."""
+        t0 = time.perf_counter()
+        rc, pi = S.primal_solve(ctx, E, d0)
+        tp = time.perf_counter() - t0
+        J = S.solid_lbm_objective(ctx)
+        print(json.dumps({"stage": "primal", "run": tag, "steps": pi.steps, "wall_s": round(tp, 3),
+                          "converged": pi.converged}), flush=True)
+        r = S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL)
+        t1 = time.perf_counter()
+        rc, g, ai = S.adjoint_solve_vjp(ctx, r * (dx * dx / cbar))
+        ta = time.perf_counter() - t1
+        print(json.dumps({"stage": "adjoint", "run": tag, "steps": ai.steps, "wall_s": round(ta, 3),
+                          "converged": ai.converged}), flush=True)
+        return J, np.asarray(g).copy(), pi, ai, tp + ta
+
+    sizes = [int(v) for v in args.eval_sizes.split(",")]
+    nf = [int(v) for v in str(args.eval_fields).split(",")]
+    n_fields = {nx: nf[min(i, len(nf) - 1)] for i, nx in enumerate(sizes)}
+    for nx in sizes:
         cp = WS.plate(nx)
         # identification target: displacement of a reference modulus field
         E_star = WS.e_field(cp, 99999)
         ctx = S.solid_lbm_init(WS.plate_problem(cp, args.tol))
-        S.primal_solve(ctx, E_star)
+        t0 = time.perf_counter()
+        rc, ti = S.primal_solve(ctx, E_star)
+        print(json.dumps({"stage": "target", "width": nx, "steps": ti.steps,
+                          "wall_s": round(time.perf_counter() - t0, 3)}), flush=True)
         target = S.solid_lbm_get_field(ctx, S.FIELD_DISP)
+        cbar = float(((target ** 2).sum(0) * cp["active"]).sum()) * cp["dx"] ** 2
         ctx = S.solid_lbm_init(WS.plate_problem(cp, args.tol, target=target))
-        for seed in range(10000, 10000 + args.eval_fields):
+        for seed in range(10000, 10000 + n_fields[nx]):
             E = WS.e_field(cp, seed)
-            t0 = time.perf_counter()
-            rc, Jc, gc, pc, ac = S.objective_and_grad(ctx, E)
-            tc = time.perf_counter() - t0
+            tag = f"{nx}:{seed}"
+            Jc, gc, pc, ac, tc = gradient(ctx, E, None, cbar, cp["dx"], tag + ":cold")
             t0 = time.perf_counter()
             d0 = ws.predict(cp, E)
             tp = time.perf_counter() - t0
-            rc, Jw, gw, pw, aw = S.objective_and_grad(ctx, E, init_disp=d0)
-            tw = time.perf_counter() - t0
-            # ablation: the E = 1 displacement alone as the initial state
-            rc, _, _, pr, _ = S.objective_and_grad(ctx, E, init_disp=ws.predict(cp, E, use_net=False),
-                                                   want_grad=False)
+            Jw, gw, pw, aw, tw = gradient(ctx, E, d0, cbar, cp["dx"], tag + ":warm")
+            tw += tp
+            # ablation: the E = 1 displacement alone as the initial state (primal only)
+            rc, pr = S.primal_solve(ctx, E, ws.predict(cp, E, use_net=False))
             row = {"stage": "eval", "grid": [cp["active"].shape[1], cp["active"].shape[0]], "seed": seed,
                    "cold_primal_steps": pc.steps, "warm_primal_steps": pw.steps,
                    "ref_only_primal_steps": pr.steps, "adjoint_steps": ac.steps,
                    "cold_time_to_gradient_s": round(tc, 3), "warm_time_to_gradient_s": round(tw, 3),
                    "predict_s": round(tp, 4), "J_rel_diff": abs(Jw - Jc) / abs(Jc),
-                   "grad_rel_diff": float(np.linalg.norm(np.asarray(gw) - np.asarray(gc)) / np.linalg.norm(gc))}
+                   "grad_rel_diff": float(np.linalg.norm(gw - gc) / np.linalg.norm(gc))}
             rows.append(row)
             print(json.dumps(row), flush=True)
     for nx in sorted(set(r["grid"][0] for r in rows)):

@@ -401,6 +401,17 @@ def main():
     t_primal = p_ms / p_sweeps * 1e-3          # s per primal time step (device, events)
     t_adj = a_ms / a_sweeps * 1e-3
     T, H = tune["T"], tune["H"]
+    tw, th = tune.get("tiles", [0, 0])
+    if tw > 0:
+        kname = (f"k_sweep_tile<false,false,false> (primal sweep, {T} time steps per launch, "
+                 f"{tw}x{th} tiles in LDS)")
+        traffic = None
+    elif T > 1:
+        kname = f"k_sweep_tb<{T},false> (primal sweep, {T} time steps per launch, {H} rows per wave)"
+        traffic = TRAFFIC_BYTES.get((n, T, H))
+    else:
+        kname = "k_primal<false,false,false> (primal sweep)"
+        traffic = None
     ach = BYTES_PER_NODE * cells / t_primal / 1e9
     ach_adj = BYTES_PER_NODE * cells / t_adj / 1e9
     out = {
@@ -428,16 +439,14 @@ def main():
         "J": rec[-1][1],
         "grad": [float(x) for x in grad.cpu().numpy()],
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get((n, T, H)),
-                     "kernel": (f"k_sweep_tb<{T},false> (primal sweep, {T} time steps per launch, "
-                                f"{H} rows per wave)" if T > 1 else "k_primal<false,false,false> (primal sweep)"),
+                     "frac": round(ach / PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                      "bytes_per_node_step": BYTES_PER_NODE, "node_steps_per_launch": cells * max(T, 1),
                      "avg_step_us": round(t_primal * 1e6, 3),
                      "note": "achieved = algorithmic bytes of the single-step scheme (144 B per node and "
                              "time step) over the measured time; fused launches reuse data across their T "
                              "steps in registers, so frac can exceed 1 while the HBM traffic (traffic, "
                              "bytes per launch) stays below the peak"},
-        "tuning": {"T": T, "H": H, "cached": tune["cached"], "candidates_us": tune.get("us")},
+        "tuning": {"T": T, "H": H, "tiles": [tw, th], "cached": tune["cached"], "candidates_us": tune.get("us")},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, np.array([0.1, 0.1]))

@@ -224,8 +224,11 @@ int solid_lbm_time_sweeps(slbm_ctx *ctx, int32_t adjoint, int64_t n, double *ms)
 /* Launch shape of the sweeps.  steps_per_launch: -1 automatic (default), 0 or
  * 1 = one time step per launch, else that many time steps fused in one
  * launch: 2, 4, 6 or 8 for periodic, uniform-material problems (wave-strip
- * kernel; automatic 8), 2 .. 8 for plates and E-field controls (LDS-tiled
- * kernel; automatic 8 up to 131072 nodes, 6 above).  rows_per_wave: rows each wave of a wave-strip launch
+ * kernel), 2 .. 8 for plates, E-field controls and problems given a tile by
+ * solid_lbm_set_tiles (LDS-tiled kernel).  Automatic: the LDS-tiled kernel
+ * for plates, E fields and periodic grids up to 262144 nodes (8 steps up to
+ * 131072 nodes, 6 above), the wave-strip kernel with 8 steps for larger
+ * periodic grids.  rows_per_wave: rows each wave of a wave-strip launch
  * covers (0 = automatic).  Every setting gives the same result bit for bit:
  * a fused launch performs exactly the arithmetic of its single sweeps.
  * SLBM_EINVAL if the value is out of range, or if a tile set by
@@ -233,7 +236,8 @@ int solid_lbm_time_sweeps(slbm_ctx *ctx, int32_t adjoint, int64_t n, double *ms)
 int solid_lbm_set_tuning(slbm_ctx *ctx, int32_t steps_per_launch, int32_t rows_per_wave);
 
 /* Interior tile (tile_w x tile_h nodes) of each workgroup of the LDS-tiled
- * fused sweeps of plates and E-field controls; the tile plus a halo of
+ * fused sweeps (selects that kernel also for periodic uniform problems); the
+ * tile plus a halo of
  * steps_per_launch nodes on every side must hold at most 1024 nodes (8 FP64
  * planes in 64 KiB of LDS).  0, 0 = automatic (a 32 x 32 region).  Does not
  * change results.  SLBM_EINVAL for one zero and one nonzero value, negative

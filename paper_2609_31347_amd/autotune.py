@@ -1,11 +1,15 @@
 """Launch-shape autotuner for the fused (multi-step) sweeps.
 
-For one problem context it times a small set of candidate shapes -- time steps
-fused per launch T and rows per wave H -- with the library's own HIP-event
-timer (`solid_lbm_time_sweeps`, primal and adjoint sweeps), keeps the fastest
-and caches the choice per (GPU, grid, domain, control kind) in a JSON file, so
-later contexts of the same shape skip the timing.  The timed sweeps advance the
-context's current state; call it before a solve (primal_solve resets the state).
+For one problem context it times a small set of candidate launch shapes with
+the library's own HIP-event timer (`solid_lbm_time_sweeps`, primal sweeps),
+keeps the fastest and caches the choice per (GPU, grid, domain, control kind)
+in a JSON file, so later contexts of the same shape skip the timing.  A
+candidate is (T, H, tw, th): T time steps per launch; H rows per wave of the
+wave-strip kernel (periodic, uniform material) or, with tw, th > 0, a tw x th
+tile of the LDS-tiled kernel (any problem); T = 1 is one step per launch.
+Plates and E-field controls only take tiled or single-step shapes.  The timed
+sweeps advance the context's current state; call it before a solve
+(primal_solve resets the state).
 """
 import json
 import os
@@ -13,9 +17,29 @@ import os
 from . import slbm as S
 
 # in order of preference on near-ties (larger T moves fewer HBM bytes per step)
-CANDIDATES = ((8, 24), (8, 48), (8, 64), (8, 96), (6, 24), (6, 48), (4, 24), (1, 0))
+STRIP = ((8, 24, 0, 0), (8, 48, 0, 0), (8, 12, 0, 0), (6, 24, 0, 0), (6, 48, 0, 0), (6, 12, 0, 0),
+         (4, 24, 0, 0))
+TILES = ((8, 0, 16, 16), (6, 0, 20, 20), (4, 0, 24, 24), (6, 0, 52, 4))
+SINGLE = ((1, 0, 0, 0),)
+CANDIDATES = STRIP + TILES + SINGLE
 TIE = 0.02
 CACHE = os.environ.get("SLBM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "slbm_autotune.json"))
+
+
+def _tiled_only(problem):
+    return int(problem.get("domain", 0)) == S.MASKED or int(problem.get("control_kind", 0)) == S.CTRL_E_NODAL
+
+
+def _apply(ctx, c):
+    T, H, tw, th = c
+    S.solid_lbm_set_tiles(ctx, 0, 0)
+    S.solid_lbm_set_tuning(ctx, T, H)
+    if tw > 0:
+        S.solid_lbm_set_tiles(ctx, tw, th)
+
+
+def _name(c):
+    return f"{c[0]},{c[1]}" if c[2] == 0 else f"{c[0]},tile{c[2]}x{c[3]}"
 
 
 def _key(ctx, problem, device):
@@ -41,28 +65,31 @@ def _save(d):
         pass
 
 
-def autotune(ctx, problem, control, sweeps=96, device="gpu0", use_cache=True, candidates=CANDIDATES):
-    """Chooses and sets (T, H) for ctx.  `control` is any valid control for the
-    problem (it sets the forcing the sweeps run with).  Returns
-    {"T": T, "H": H, "us": {"T,H": (primal_us, adjoint_us)}, "cached": bool}."""
+def autotune(ctx, problem, control, sweeps=96, device="gpu0", use_cache=True, candidates=None):
+    """Chooses and sets the launch shape of ctx.  `control` is any valid
+    control for the problem (it sets the forcing the sweeps run with).  Returns
+    {"T", "H", "tiles": [tw, th], "us": {shape: primal us per step}, "cached"}."""
     key = _key(ctx, problem, device)
+    if candidates is None:
+        candidates = (TILES + SINGLE) if _tiled_only(problem) else CANDIDATES
     cache = _load() if use_cache else {}
-    if key in cache:
-        T, H = cache[key]["T"], cache[key]["H"]
-        S.solid_lbm_set_tuning(ctx, T, H)
-        return dict(cache[key], cached=True)
+    if key in cache and "tiles" in cache[key]:
+        e = cache[key]
+        _apply(ctx, (e["T"], e["H"], e["tiles"][0], e["tiles"][1]))
+        return dict(e, cached=True)
     S.solid_lbm_set_control(ctx, control)
     times = {}
-    for T, H in candidates:
-        S.solid_lbm_set_tuning(ctx, T, H)
-        n = max(sweeps // max(T, 1), 1) * max(T, 1)
-        S.solid_lbm_time_sweeps(ctx, 0, max(T, 1) * 2)               # warm-up of this shape
-        tp = S.solid_lbm_time_sweeps(ctx, 0, n) / n * 1e3
-        times[(T, H)] = tp
+    for c in candidates:
+        _apply(ctx, c)
+        T = max(c[0], 1)
+        n = max(sweeps // T, 1) * T
+        S.solid_lbm_time_sweeps(ctx, 0, T * 2)               # warm-up of this shape
+        times[c] = S.solid_lbm_time_sweeps(ctx, 0, n) / n * 1e3
     fastest = min(times.values())
     best = next(c for c in candidates if times[c] <= fastest * (1.0 + TIE))
-    S.solid_lbm_set_tuning(ctx, best[0], best[1])
-    out = {"T": best[0], "H": best[1], "us": {f"{k[0]},{k[1]}": round(v, 3) for k, v in times.items()}}
+    _apply(ctx, best)
+    out = {"T": best[0], "H": best[1], "tiles": [best[2], best[3]],
+           "us": {_name(k): round(v, 3) for k, v in times.items()}}
     if use_cache:
         cache = _load()
         cache[key] = out

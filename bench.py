@@ -200,9 +200,15 @@ def batch_mode(args):
     cells = [p["nx"] * p["ny"] for p in probs]
     batch = S.solid_lbm_batch_init(probs)
     tune = autotune_batch(batch, ctrls)
+    print(json.dumps({"stage": "tuned", **tune}), flush=True)
     t0 = time.perf_counter()
-    rc, J, grads, pi, ai = S.batch_objective_and_grad(batch, ctrls)
+    rc, J, _, pi, _ = S.batch_objective_and_grad(batch, ctrls, want_grad=False)
+    tp = time.perf_counter() - t0
+    print(json.dumps({"stage": "primal", "wall_s": round(tp, 3), "max_steps": int(max(p.steps for p in pi))}),
+          flush=True)
+    rc2, grads, ai = S.batch_gradient(batch)
     wall = time.perf_counter() - t0
+    print(json.dumps({"stage": "adjoint", "wall_s": round(wall - tp, 3)}), flush=True)
     lups = sum(c * (p.sweeps + a.sweeps) for c, p, a in zip(cells, pi, ai))
     out = {"mode": "batch", "instances": len(probs), "plates": args.plates, "tol": args.tol,
            "total_cells": int(sum(cells)), "rc": rc, "tuning": tune,
@@ -213,10 +219,12 @@ def batch_mode(args):
     if args.sequential:
         t0 = time.perf_counter()
         seq_lups = 0
-        for p, c, cl in zip(probs, ctrls, cells):
+        for k, (p, c, cl) in enumerate(zip(probs, ctrls, cells)):
             ctx = S.solid_lbm_init(p)
             r = S.objective_and_grad(ctx, c)
             seq_lups += cl * (r[3].sweeps + r[4].sweeps)
+            print(json.dumps({"stage": "sequential", "instance": k, "grid": [p["nx"], p["ny"]],
+                              "steps": r[3].steps, "wall_s": round(time.perf_counter() - t0, 3)}), flush=True)
             del ctx
         seq = time.perf_counter() - t0
         out.update({"sequential_wall_s": round(seq, 3), "sequential_mlups": round(seq_lups / seq / 1e6, 1),

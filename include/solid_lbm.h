@@ -273,6 +273,14 @@ int batch_objective_and_grad(slbm_batch *batch, const double *const *controls, d
                              double *const *grads, int32_t ptr_kind, slbm_solve_info *primal_info,
                              slbm_solve_info *adjoint_info);
 
+/* Adjoints and gradients of every instance at the state of the last
+ * batch_objective_and_grad call (made with grads = NULL, so that a caller can
+ * report between the two halves): grads[i] (length per the instance's
+ * control kind, per ptr_kind; none may be NULL); adjoint_info: NULL or count
+ * entries.  SLBM_ESTATE if an instance has no completed primal solve;
+ * SLBM_NOT_CONVERGED (> 0) if an adjoint did not reach tol. */
+int batch_gradient(slbm_batch *batch, double *const *grads, int32_t ptr_kind, slbm_solve_info *adjoint_info);
+
 /* Fused launch shape of the batch's periodic instances (as solid_lbm_set_tuning). */
 int solid_lbm_batch_set_tuning(slbm_batch *batch, int32_t steps_per_launch, int32_t rows_per_wave);
 

@@ -1260,12 +1260,13 @@ struct slbm_batch {
     BatchInst* d_inst = nullptr;
     std::vector<BatchInst> h_inst;
     int2* d_all = nullptr;         // every instance: (instance, block) of a single-step sweep
-    int2* d_plate = nullptr;       // plate instances only
-    int2* d_tb = nullptr;          // periodic instances: (instance, strip) of a fused launch
-    int64_t n_all = 0, n_plate = 0, n_tb = 0, tb_cap = 0;
+    int2* d_tb = nullptr;          // wave-strip instances: (instance, strip) of a fused launch
+    int2* d_tile = nullptr;        // tiled instances: (instance, tile) of a fused launch
+    int64_t n_all = 0, n_tb = 0, tb_cap = 0, n_tile = 0, tile_cap = 0;
     int tb_T = -1, tb_H = 0;       // tuning (-1 / 0: automatic)
     int T = 1, H = 0;              // effective fused shape of the current tables
-    bool any_periodic = false, any_plate = false;
+    std::vector<char> tiled;       // per instance: fused by the LDS-tiled kernel
+    bool any_masked = false, tile_attr = false;
     double tol = 0.0;
     int64_t max_steps = 0;
     hipEvent_t ev[2] = {nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
@@ -1304,12 +1305,11 @@ void batch_shape(slbm_batch* b, int* T, int* H)
 {
     int t = b->tb_T < 0 ? 8 : b->tb_T;
     if (t != 2 && t != 4 && t != 6 && t != 8) t = 1;
-    if (!b->any_periodic) t = 1;
     int h = b->tb_H;
     if (h <= 0) {
         int maxny = 0;
-        for (auto* c : b->ctx)
-            if (!c->masked) maxny = std::max(maxny, c->ny);
+        for (size_t i = 0; i < b->ctx.size(); ++i)
+            if (!b->tiled[i]) maxny = std::max(maxny, b->ctx[i]->ny);
         h = maxny <= 1536 ? 24 : 48;
     }
     if (t > 1 && h < 2 * t) h = 2 * t;
@@ -1324,7 +1324,9 @@ int batch_tables(slbm_batch* b, bool adjoint)
     int T, H;
     batch_shape(b, &T, &H);
     const int B = (int)b->ctx.size();
-    std::vector<int2> tb;
+    // tiled instances: halo = T, 32 x 32 regions
+    const int tw = std::max(2, 32 - 2 * T);
+    std::vector<int2> tb, tl;
     for (int i = 0; i < B; ++i) {
         slbm_ctx* c = b->ctx[i];
         BatchInst I;
@@ -1358,18 +1360,47 @@ int batch_tables(slbm_batch* b, bool adjoint)
                 t.kd = s.kd;
                 t.scale = s.scale;
                 (k ? I.tadj : I.tprim)[par] = t;
+                TileArgs l;
+                std::memset(&l, 0, sizeof(l));
+                l.src = s.src;
+                l.dst = s.dst;
+                l.g = s.g;
+                l.E = s.E;
+                l.code = s.code;
+                l.bnodes = s.bnodes;
+                l.status = b->status + i;
+                l.nx = c->nx;
+                l.ny = c->ny;
+                l.N = c->N;
+                l.k11 = s.k11;
+                l.ks = s.ks;
+                l.kd = s.kd;
+                l.E0 = s.E0;
+                l.nu = s.nu;
+                l.scale = s.scale;
+                l.tw = tw;
+                l.th = tw;
+                l.halo = T;
+                l.steps = T;
+                l.tiles_x = (c->nx + tw - 1) / tw;
+                (k ? I.ladj : I.lprim)[par] = l;
             }
         }
         I.status = b->status + i;
         I.inv_nx = c->inv_nx;
         I.masked = c->masked ? 1 : 0;
         I.efield = c->efield_on ? 1 : 0;
+        I.tiled = b->tiled[i] ? 1 : 0;
         I.nblk = c->nblk;
-        if (!c->masked && !c->efield_on && T > 1) {
+        if (!b->tiled[i] && T > 1) {
             int V = 64 - 2 * T;
             int sx = (c->nx + V - 1) / V, sy = (c->ny + std::min(H, c->ny) - 1) / std::min(H, c->ny);
             I.sx = sx;
             for (int k = 0; k < sx * sy; ++k) tb.push_back(make_int2(i, k));
+        }
+        if (b->tiled[i] && T > 1) {
+            const int ntiles = ((c->nx + tw - 1) / tw) * ((c->ny + tw - 1) / tw);
+            for (int k = 0; k < ntiles; ++k) tl.push_back(make_int2(i, k));
         }
         b->h_inst[i] = I;
     }
@@ -1384,8 +1415,26 @@ int batch_tables(slbm_batch* b, bool adjoint)
     }
     if (!tb.empty())
         BHIPCHK(b, hipMemcpyAsync(b->d_tb, tb.data(), tb.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+    if ((int64_t)tl.size() > b->tile_cap) {
+        void* q = nullptr;
+        int rc = balloc(b, &q, tl.size() * sizeof(int2));
+        if (rc) return rc;
+        b->d_tile = (int2*)q;
+        b->tile_cap = (int64_t)tl.size();
+    }
+    if (!tl.empty())
+        BHIPCHK(b, hipMemcpyAsync(b->d_tile, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+    if (!tl.empty() && !b->tile_attr) {
+        const int lmax = (int)tile_lds_bytes(kTileMaxNodes, true);
+        BHIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile_batch<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+        BHIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile_batch<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+        b->tile_attr = true;
+    }
     BHIPCHK(b, hipStreamSynchronize(b->stream));
     b->n_tb = (int64_t)tb.size();
+    b->n_tile = (int64_t)tl.size();
     b->T = T;
     b->H = H;
     return SLBM_OK;
@@ -1420,6 +1469,18 @@ void launch_batch_fused(slbm_batch* b, bool adjoint, int pp)
         BTB_CASE(8)
     }
 #undef BTB_CASE
+}
+
+void launch_batch_tile(slbm_batch* b, bool adjoint, int pl)
+{
+    if (b->n_tile <= 0) return;
+    const int R = (std::max(2, 32 - 2 * b->T) + 2 * b->T) * (std::max(2, 32 - 2 * b->T) + 2 * b->T);
+    const size_t lds = tile_lds_bytes(R, b->any_masked);
+    dim3 grid((unsigned)b->n_tile), block(kTileBlock);
+    if (adjoint)
+        hipLaunchKernelGGL(k_sweep_tile_batch<true>, grid, block, lds, b->stream, b->d_inst, b->d_tile, pl, b->T);
+    else
+        hipLaunchKernelGGL(k_sweep_tile_batch<false>, grid, block, lds, b->stream, b->d_inst, b->d_tile, pl, b->T);
 }
 
 // Advances every instance from buffer 0 in lock-step (step index s), each
@@ -1458,7 +1519,7 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
         if (lo || hi || s == last) {
             launch_batch_step(b, adjoint, b->d_all, b->n_all, pp, pl, lo, hi);
             for (int i = 0; i < B; ++i) {
-                int par = (b->ctx[i]->masked || b->ctx[i]->kind == SLBM_CTRL_E_NODAL) ? pl : pp;
+                int par = b->tiled[i] ? pl : pp;
                 if ((i < 64 ? (lo >> i) : (hi >> (i - 64))) & 1ull) checks[i].emplace_back(s, par);
                 if (s == last) last_in[i] = par;
             }
@@ -1491,12 +1552,10 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
         if (T > 1 && run >= T) {
             int64_t nT = run / T;
             for (int64_t j = 0; j < nT; ++j) {
-                launch_batch_fused(b, adjoint, pp);
+                if (b->n_tb > 0) launch_batch_fused(b, adjoint, pp);
                 pp ^= 1;
-                for (int k = 0; k < T; ++k) {
-                    launch_batch_step(b, adjoint, b->d_plate, b->n_plate, pp, pl, 0, 0);
-                    pl ^= 1;
-                }
+                launch_batch_tile(b, adjoint, pl);
+                pl ^= 1;
             }
             s += nT * T;
             run -= nT * T;
@@ -1537,6 +1596,8 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
     return SLBM_OK;
 }
 
+int batch_adjoint(slbm_batch* b, double* const* grads, int ptr_kind, slbm_solve_info* ainfo);
+
 int batch_solve(slbm_batch* b, const double* const* controls, int ptr_kind, double* J, double* const* grads,
                 slbm_solve_info* pinfo, slbm_solve_info* ainfo)
 {
@@ -1575,12 +1636,29 @@ int batch_solve(slbm_batch* b, const double* const* controls, int ptr_kind, doub
             pinfo[i].converged = conv[i];
         }
     if (!grads) return (b->tol > 0.0 && !all_conv) ? SLBM_NOT_CONVERGED : SLBM_OK;
-    // adjoints
+    rc = batch_adjoint(b, grads, ptr_kind, ainfo);
+    if (rc < 0) return rc;
+    return (b->tol > 0.0 && (!all_conv || rc == SLBM_NOT_CONVERGED)) ? SLBM_NOT_CONVERGED : SLBM_OK;
+}
+
+// Adjoints and gradients of every instance after a completed batch primal.
+int batch_adjoint(slbm_batch* b, double* const* grads, int ptr_kind, slbm_solve_info* ainfo)
+{
+    const int B = (int)b->ctx.size();
+    int rc;
+    auto w1 = std::chrono::steady_clock::now();
     for (int i = 0; i < B; ++i) {
         slbm_ctx* c = b->ctx[i];
+        if (!c->prim_done) return bfail(b, SLBM_ESTATE, "instance " + std::to_string(i) + ": no completed primal");
         if ((rc = adjoint_prepare(c)) || (rc = project_source(c)))
             return bfail(b, rc, "instance " + std::to_string(i) + ": " + c->err);
     }
+    std::vector<int64_t> t;
+    std::vector<int> X;
+    std::vector<char> conv;
+    std::vector<double> res;
+    double dms = 0.0;
+    bool all_conv = true;
     if ((rc = batch_loop(b, true, t, X, conv, res, &dms))) return rc;
     for (int i = 0; i < B; ++i) {
         slbm_ctx* c = b->ctx[i];
@@ -1633,25 +1711,19 @@ int solid_lbm_batch_init(const slbm_problem* problems, int32_t count, slbm_batch
     void* q = nullptr;
     if (!rc && !(rc = balloc(b, &q, count * sizeof(Status)))) b->status = (Status*)q;
     if (!rc && !(rc = balloc(b, &q, count * sizeof(BatchInst)))) b->d_inst = (BatchInst*)q;
-    std::vector<int2> all, plate;
+    std::vector<int2> all;
+    b->tiled.assign(count, 0);
     for (int i = 0; i < count; ++i) {
         slbm_ctx* c = b->ctx[i];
         c->status = b->status + i;  // the instance's sweeps and the batch share its flag
-        // instances that cannot use fused launches (plates, E fields) step one by one
-        bool single = c->masked || c->kind == SLBM_CTRL_E_NODAL;
-        for (int64_t k = 0; k < c->nblk; ++k) {
-            all.push_back(make_int2(i, (int)k));
-            if (single) plate.push_back(make_int2(i, (int)k));
-        }
-        if (single) b->any_plate = true;
-        else b->any_periodic = true;
+        // plates, E fields and periodic grids up to 512 x 512 fuse in LDS tiles,
+        // larger periodic grids in wave strips
+        b->tiled[i] = (c->masked || c->kind == SLBM_CTRL_E_NODAL || c->N <= kTileAutoMaxNodes) ? 1 : 0;
+        if (c->masked) b->any_masked = true;
+        for (int64_t k = 0; k < c->nblk; ++k) all.push_back(make_int2(i, (int)k));
     }
     if (!rc && !(rc = balloc(b, &q, all.size() * sizeof(int2)))) b->d_all = (int2*)q;
-    if (!rc && !(rc = balloc(b, &q, std::max<size_t>(1, plate.size()) * sizeof(int2)))) b->d_plate = (int2*)q;
     if (!rc && hipMemcpy(b->d_all, all.data(), all.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
-        rc = SLBM_EHIP;
-    if (!rc && !plate.empty() &&
-        hipMemcpy(b->d_plate, plate.data(), plate.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
         rc = SLBM_EHIP;
     if (!rc && hipHostMalloc((void**)&b->h_status, 2 * count * sizeof(Status), hipHostMallocDefault) != hipSuccess)
         rc = SLBM_EHIP;
@@ -1663,7 +1735,6 @@ int solid_lbm_batch_init(const slbm_problem* problems, int32_t count, slbm_batch
         return bfail(nullptr, rc, "batch allocation failed");
     }
     b->n_all = (int64_t)all.size();
-    b->n_plate = (int64_t)plate.size();
     b->h_inst.resize(count);
     // defined contents for timing sweeps before any solve
     for (auto* c : b->ctx) {
@@ -1685,6 +1756,15 @@ int batch_objective_and_grad(slbm_batch* b, const double* const* controls, doubl
     if (!b) return SLBM_EINVAL;
     if (!controls || !J) return bfail(b, SLBM_EINVAL, "controls and J are required");
     return batch_solve(b, controls, ptr_kind, J, grads, primal_info, adjoint_info);
+}
+
+int batch_gradient(slbm_batch* b, double* const* grads, int32_t ptr_kind, slbm_solve_info* adjoint_info)
+{
+    if (!b) return SLBM_EINVAL;
+    if (!grads) return bfail(b, SLBM_EINVAL, "grads is required");
+    for (int i = 0; i < (int)b->ctx.size(); ++i)
+        if (!grads[i]) return bfail(b, SLBM_EINVAL, "grads[" + std::to_string(i) + "] is NULL");
+    return batch_adjoint(b, grads, ptr_kind, adjoint_info);
 }
 
 int solid_lbm_batch_set_tuning(slbm_batch* b, int32_t steps_per_launch, int32_t rows_per_wave)
@@ -1711,12 +1791,10 @@ int solid_lbm_batch_time_sweeps(slbm_batch* b, int32_t adjoint, int64_t n, doubl
     BHIPCHK(b, hipEventRecord(b->t0, b->stream));
     for (int64_t s = 0; s < n;) {
         if (b->T > 1 && n - s >= b->T) {
-            launch_batch_fused(b, adjoint != 0, pp);
+            if (b->n_tb > 0) launch_batch_fused(b, adjoint != 0, pp);
             pp ^= 1;
-            for (int k = 0; k < b->T; ++k) {
-                launch_batch_step(b, adjoint != 0, b->d_plate, b->n_plate, pp, pl, 0, 0);
-                pl ^= 1;
-            }
+            launch_batch_tile(b, adjoint != 0, pl);
+            pl ^= 1;
             s += b->T;
         } else {
             launch_batch_step(b, adjoint != 0, b->d_all, b->n_all, pp, pl, 0, 0);

@@ -769,13 +769,13 @@ __host__ __device__ constexpr size_t tile_lds_bytes(int region, bool masked)
     return (size_t)8 * region * sizeof(double) + (masked ? (size_t)kTileMaxB * sizeof(BNode) : 0);
 }
 
+// One tile (index `tile` of the problem's tiles_x x tiles_y) of a tiled launch;
+// lds: 8 planes of the region, then the staged boundary records.
 template <bool MASKED, bool EFIELD, bool ADJ>
-__global__ __launch_bounds__(kTileBlock) void k_sweep_tile(TileArgs a)
+__device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* lds)
 {
-    if (a.status->stop) return;
-    extern __shared__ __align__(16) double lds[];    // 8 planes of RX * RY doubles, then staged records
     const int h = a.halo, RX = a.tw + 2 * h, RY = a.th + 2 * h, R = RX * RY;
-    const int bx = blockIdx.x % a.tiles_x, by = blockIdx.x / a.tiles_x;
+    const int bx = tile % a.tiles_x, by = tile / a.tiles_x;
     const int x0 = bx * a.tw - h, y0 = by * a.th - h;   // unwrapped origin of the region
     const int nx = a.nx, ny = a.ny;
     const int64_t N = a.N;
@@ -913,6 +913,14 @@ __global__ __launch_bounds__(kTileBlock) void k_sweep_tile(TileArgs a)
     }
 }
 
+template <bool MASKED, bool EFIELD, bool ADJ>
+__global__ __launch_bounds__(kTileBlock) void k_sweep_tile(TileArgs a)
+{
+    if (a.status->stop) return;
+    extern __shared__ __align__(16) double lds[];    // 8 planes of RX * RY doubles, then staged records
+    tile_body<MASKED, EFIELD, ADJ>(a, blockIdx.x, lds);
+}
+
 }  // namespace slbm
 
 namespace slbm {
@@ -926,12 +934,14 @@ namespace slbm {
 struct BatchInst {
     SweepArgs prim[2];    // primal args by buffer parity (src = buffer p, dst = buffer p^1)
     SweepArgs adj[2];     // adjoint args by buffer parity
-    TBArgs tprim[2], tadj[2];
+    TBArgs tprim[2], tadj[2];      // wave-strip fused launches
+    TileArgs lprim[2], ladj[2];    // LDS-tiled fused launches
     Status* status;
     double inv_nx;
     int32_t masked;
-    int32_t efield;       // E plane per node (E control): single-step kernels only
-    int32_t sx;           // strips per row of fused launches (periodic instances)
+    int32_t efield;       // E plane per node (E control)
+    int32_t tiled;        // fused by the LDS-tiled kernel (else by the wave strips)
+    int32_t sx;           // strips per row of wave-strip launches
     int64_t nblk;         // blocks of one single-step sweep
 };
 
@@ -948,7 +958,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchInst* __restr
     const int2 e = table[blockIdx.x];
     const BatchInst& I = inst[e.x];
     if (I.status->stop) return;
-    const int par = (I.masked || I.efield) ? par_plate : par_periodic;   // single-step instances
+    const int par = I.tiled ? par_plate : par_periodic;   // parity of the tiled / wave-strip class
     const SweepArgs& a = ADJ ? I.adj[par] : I.prim[par];
     const bool check = mask_bit(check_lo, check_hi, e.x);
     const int64_t n = (int64_t)e.y * kBlock + threadIdx.x;
@@ -984,6 +994,27 @@ __global__ __launch_bounds__(64) void k_sweep_tb_batch(const BatchInst* __restri
     if (I.status->stop) return;
     const TBArgs a = ADJ ? I.tadj[par_periodic] : I.tprim[par_periodic];
     tb_strip<T, ADJ>(a, e.y % I.sx, e.y / I.sx);
+}
+
+// Tiled instances of a batch: `steps` <= halo sweeps of every listed tile.
+template <bool ADJ>
+__global__ __launch_bounds__(kTileBlock) void k_sweep_tile_batch(const BatchInst* __restrict__ inst,
+                                                                 const int2* __restrict__ table, int par,
+                                                                 int steps)
+{
+    const int2 e = table[blockIdx.x];
+    const BatchInst& I = inst[e.x];
+    if (I.status->stop) return;
+    extern __shared__ __align__(16) double lds[];
+    TileArgs a = ADJ ? I.ladj[par] : I.lprim[par];
+    a.steps = steps;
+    const int sel = (I.masked ? 2 : 0) | (I.efield ? 1 : 0);
+    switch (sel) {
+        case 0: tile_body<false, false, ADJ>(a, e.y, lds); break;
+        case 1: tile_body<false, true, ADJ>(a, e.y, lds); break;
+        case 2: tile_body<true, false, ADJ>(a, e.y, lds); break;
+        default: tile_body<true, true, ADJ>(a, e.y, lds); break;
+    }
 }
 
 // One block per instance: instances flagged in the mask test their residual.

@@ -27,7 +27,7 @@ EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_gra
            "solid_lbm_run_steps", "solid_lbm_run_adjoint_steps", "solid_lbm_get_field",
            "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_set_tiles", "solid_lbm_last_error",
            "solid_lbm_destroy",
-           "solid_lbm_batch_init", "batch_objective_and_grad", "solid_lbm_batch_set_tuning",
+           "solid_lbm_batch_init", "batch_objective_and_grad", "batch_gradient", "solid_lbm_batch_set_tuning",
            "solid_lbm_batch_time_sweeps", "solid_lbm_batch_instance", "solid_lbm_batch_last_error",
            "solid_lbm_batch_destroy")
 
@@ -87,6 +87,7 @@ def _load():
     lib.solid_lbm_batch_init.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32, pp]
     lib.batch_objective_and_grad.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, info, info]
+    lib.batch_gradient.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, info]
     lib.solid_lbm_batch_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.solid_lbm_batch_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_batch_instance.argtypes = [P, ctypes.c_int32]
@@ -386,6 +387,23 @@ def batch_objective_and_grad(batch, controls, grads=None, want_grad=True):
     pi, ai = (SolveInfo * B)(), (SolveInfo * B)()
     rc = _bcheck(batch, LIB.batch_objective_and_grad(batch.handle, cptr, J, gptr, kind, pi, ai))
     return rc, np.array(J[:]), grads, list(pi), list(ai)
+
+
+def batch_gradient(batch, grads=None):
+    """After batch_objective_and_grad(..., want_grad=False) with host controls:
+    (rc, grads, adjoint infos)."""
+    B = len(batch)
+    if grads is None:
+        grads = [np.zeros(ctx.grad_len()) for ctx in batch.contexts]
+    kinds = {PTR_DEVICE if (_is_torch(g) and g.is_cuda) else PTR_HOST for g in grads}
+    if len(kinds) != 1:
+        raise ValueError("grads must all be host or all device")
+    gptr = (ctypes.c_void_p * B)()
+    for i, g in enumerate(grads):
+        gptr[i] = g.data_ptr() if _is_torch(g) else g.ctypes.data
+    ai = (SolveInfo * B)()
+    rc = _bcheck(batch, LIB.batch_gradient(batch.handle, gptr, kinds.pop(), ai))
+    return rc, grads, list(ai)
 
 
 def solid_lbm_batch_set_tuning(batch, steps_per_launch=-1, rows_per_wave=0):

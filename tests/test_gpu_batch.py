@@ -14,7 +14,7 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def mixed_problems(S, tol=1e-10):
+def mixed_problems(S, tol=1e-10, large=True):
     probs, ctrls = [], []
     n = 32
     probs.append(dict(nx=n, ny=n, dx=1 / n, E=1.0, nu=0.3, domain=0, target=I.two_mode_target(n),
@@ -44,6 +44,19 @@ def mixed_problems(S, tol=1e-10):
     probs.append(dict(nx=n, ny=n, dx=1 / n, E=0.11, nu=0.8, domain=0, target=sol["d"],
                       control_kind=S.CTRL_E_SCALAR_SQ, fixed_force=sol["F"]))
     ctrls.append(np.array([np.sqrt(0.13)]))
+    # E field on a plate (tiled class, per-node moduli)
+    cp = I.clamped_plate(40, 25)
+    tgt = 1e-4 * np.stack([cp["X"], cp["Y"]]) * cp["active"]
+    probs.append(dict(nx=40, ny=25, dx=cp["dx"], E=1.0, nu=0.3, domain=S.MASKED,
+                      node_mask=cp["active"].astype(np.uint8), link_bc=cp["bc"], link_wall=cp["wall"],
+                      link_normal=cp["normal"], target=tgt, control_kind=S.CTRL_E_NODAL))
+    ctrls.append(1.0 + 0.3 * np.tanh(I.grf(40, 25, cp["dx"], 1.0, 0.3, 12)[0]))
+    if large:
+        # above the tiled-class size: wave-strip fused launches
+        n = 520
+        probs.append(dict(nx=n, ny=n, dx=1 / n, E=1.0, nu=0.3, domain=0, target=I.two_mode_target(n),
+                          control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=I.two_mode_basis(n)))
+        ctrls.append(np.array([0.2, -0.1]))
     for p in probs:
         p.update(tol=tol, max_steps=2_000_000)
     return probs, ctrls
@@ -96,3 +109,24 @@ def test_batch_fixed_steps_and_tuning():
         assert rel(J, out[0][0]) < 1e-13
         for g, g0 in zip(grads, out[0][1]):
             assert rel(g, g0) < 1e-12
+
+
+def test_batch_gradient_after_primal_equals_one_call():
+    """batch_objective_and_grad without gradients, then batch_gradient, gives the
+    gradients of a single batch_objective_and_grad call."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_31347_amd import slbm as S
+    probs, ctrls = mixed_problems(S, large=False)
+    batch = S.solid_lbm_batch_init(probs)
+    rc, J, grads, pi, ai = S.batch_objective_and_grad(batch, ctrls)
+    batch2 = S.solid_lbm_batch_init(probs)
+    with pytest.raises(S.SlbmError):
+        S.batch_gradient(batch2)                      # no primal yet
+    rc, J2, _, pi2, _ = S.batch_objective_and_grad(batch2, ctrls, want_grad=False)
+    rc, grads2, ai2 = S.batch_gradient(batch2)
+    assert np.array_equal(J, J2)
+    for g, g2, a, a2 in zip(grads, grads2, ai, ai2):
+        assert a.steps == a2.steps
+        assert np.array_equal(np.asarray(g), np.asarray(g2))

@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--instances", type=int, default=96, help="batch mode: number of instances")
     ap.add_argument("--plates", type=int, default=24, help="batch mode: how many of them are plates")
     ap.add_argument("--sequential", action="store_true", help="batch mode: also solve them one by one")
+    ap.add_argument("--sweeps-only", action="store_true",
+                    help="batch mode: fixed sweep counts of the whole mix (batched vs one by one) instead of "
+                         "solves to tol")
     ap.add_argument("--train-samples", type=int, default=4000, help="warmstart mode: training solves")
     ap.add_argument("--train-iters", type=int, default=3000, help="warmstart mode: Adam iterations")
     ap.add_argument("--train-lr", type=float, default=5e-4, help="warmstart mode: peak Adam learning rate")
@@ -196,6 +199,8 @@ def batch_mode(args):
     from paper_2609_31347_amd import slbm as S
     from paper_2609_31347_amd.autotune import autotune_batch
     torch.cuda.set_device(0)
+    if args.sweeps_only:
+        return batch_sweeps(args)
     probs, ctrls = batch_instances(args.instances, args.plates, args.tol)
     cells = [p["nx"] * p["ny"] for p in probs]
     batch = S.solid_lbm_batch_init(probs)
@@ -230,6 +235,37 @@ def batch_mode(args):
         out.update({"sequential_wall_s": round(seq, 3), "sequential_mlups": round(seq_lups / seq / 1e6, 1),
                     "speedup": round(seq / wall, 2)})
     print(json.dumps(out), flush=True)
+
+
+def batch_sweeps(args):
+    """Throughput of the seeded mix over a fixed number of sweeps: args.sweeps
+    primal and args.sweeps adjoint sweeps of every instance in shared launches,
+    against the same sweeps of each instance in its own context (automatic
+    launch shapes), all timed with HIP events on the library's stream."""
+    from paper_2609_31347_amd import slbm as S
+    from paper_2609_31347_amd.autotune import autotune_batch
+    probs, ctrls = batch_instances(args.instances, args.plates, 0.0, max_steps=10)
+    cells = [p["nx"] * p["ny"] for p in probs]
+    n = args.sweeps
+    batch = S.solid_lbm_batch_init(probs)
+    tune = autotune_batch(batch, ctrls)
+    S.batch_objective_and_grad(batch, ctrls, want_grad=False)     # 10 fixed steps: forcing and residuals
+    S.solid_lbm_batch_time_sweeps(batch, 0, 16)
+    ms_b = S.solid_lbm_batch_time_sweeps(batch, 0, n) + S.solid_lbm_batch_time_sweeps(batch, 1, n)
+    print(json.dumps({"stage": "batched", "ms": round(ms_b, 3), "tuning": tune}), flush=True)
+    ms_s = 0.0
+    for k, (p, c) in enumerate(zip(probs, ctrls)):
+        ctx = S.solid_lbm_init(p)
+        S.primal_solve(ctx, c)                                     # 10 fixed steps
+        S.solid_lbm_time_sweeps(ctx, 0, 16)
+        ms_s += S.solid_lbm_time_sweeps(ctx, 0, n) + S.solid_lbm_time_sweeps(ctx, 1, n)
+        del ctx
+    lups = 2 * n * sum(cells)
+    print(json.dumps({"mode": "batch", "measure": "sweeps", "instances": len(probs), "plates": args.plates,
+                      "total_cells": int(sum(cells)), "sweeps": n,
+                      "batched_ms": round(ms_b, 3), "batched_glups": round(lups / ms_b / 1e6, 2),
+                      "one_by_one_ms": round(ms_s, 3), "one_by_one_glups": round(lups / ms_s / 1e6, 2),
+                      "speedup": round(ms_s / ms_b, 2)}), flush=True)
 
 
 def warmstart_mode(args):

@@ -52,7 +52,7 @@ def mixed_problems(S, tol=1e-10, large=True):
                       link_normal=cp["normal"], target=tgt, control_kind=S.CTRL_E_NODAL))
     ctrls.append(1.0 + 0.3 * np.tanh(I.grf(40, 25, cp["dx"], 1.0, 0.3, 12)[0]))
     if large:
-        # above the tiled-class size: wave-strip fused launches
+        # a large periodic instance next to the small ones
         n = 520
         probs.append(dict(nx=n, ny=n, dx=1 / n, E=1.0, nu=0.3, domain=0, target=I.two_mode_target(n),
                           control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=I.two_mode_basis(n)))

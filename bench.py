@@ -44,10 +44,12 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=40)
-    ap.add_argument("--mode", choices=("gradient", "sweeps", "lbfgs", "batch", "warmstart"), default="gradient",
+    ap.add_argument("--mode", choices=("gradient", "sweeps", "lbfgs", "batch", "warmstart", "nodal"),
+                    default="gradient",
                     help="sweeps: time fixed counts of primal/adjoint sweeps and a reference copy "
                          "(for rocprofv3 kernel traces and counters)")
     ap.add_argument("--plate", action="store_true", help="sweeps mode: the elliptic plate with an E field")
+    ap.add_argument("--nodal-sizes", default="80,1024", help="nodal mode: grid sizes N")
     ap.add_argument("--tiles", default="", help="sweeps mode: tile w,h of the LDS-tiled plate sweeps")
     ap.add_argument("--sweeps", type=int, default=200)
     ap.add_argument("--fuse", type=int, default=-1, help="time steps fused per launch (-1 automatic)")
@@ -237,6 +239,56 @@ def batch_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def nodal_mode(args):
+    """Distributed force control (2 N^2 DOF) through torch.autograd: reference
+    control = two-mode force + GRF (variance 0.05, length 0.1, seed 0, zero
+    mean), target = its steady state solved to tol on the GPU, gradient of the
+    misfit at control -F_ref by displacement() (primal solve) + backward
+    (adjoint VJP) with checkpointing.  Every long solve reports its progress."""
+    import torch
+    from paper_2609_31347_amd import autograd as AG
+    from paper_2609_31347_amd import inputs as I
+    from paper_2609_31347_amd import slbm as S
+    torch.cuda.set_device(0)
+    for n in [int(v) for v in args.nodal_sizes.split(",")]:
+        F_ref = I.grf_force_control(n, 0)
+        F_ref = F_ref - F_ref.mean((1, 2), keepdims=True)
+        prob = dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC, target=np.zeros((2, n, n)),
+                    normalize_objective=0, control_kind=S.CTRL_FORCE_NODAL, tol=args.tol, max_steps=50_000_000)
+
+        def report(phase, step, res, n=n, what=""):
+            print(json.dumps({"stage": "progress", "n": n, "solve": what, "phase": "adjoint" if phase else "primal",
+                              "step": step, "residual": res}), flush=True)
+
+        ref = AG.Solver(prob, tune=True, tune_control=F_ref)
+        S.solid_lbm_set_progress(ref.ctx, lambda ph, st, r: report(ph, st, r, what="target"), 30.0)
+        t0 = time.perf_counter()
+        tgt = ref.solve(torch.tensor(F_ref, device="cuda")).cpu().numpy()
+        print(json.dumps({"stage": "target", "n": n, "steps": ref.last_info.steps,
+                          "wall_s": round(time.perf_counter() - t0, 3)}), flush=True)
+        del ref
+        solver = AG.Solver(dict(prob, target=tgt, normalize_objective=1), tune=True, tune_control=-F_ref)
+        S.solid_lbm_set_progress(solver.ctx, lambda ph, st, r: report(ph, st, r, what="gradient"), 30.0)
+        alpha = torch.tensor(-F_ref, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = AG.misfit(AG.displacement(alpha, solver), tgt, 1.0 / n)
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        pi, ai = solver.last_info, solver.last_adjoint_info
+        g = alpha.grad
+        print(json.dumps({"mode": "nodal", "n": n, "dof": 2 * n * n, "J": float(L.item()),
+                          "grad_norm": float(g.norm().item()), "grad_mean_abs": float(g.mean((1, 2)).abs().max()),
+                          "primal_steps": pi.steps, "adjoint_steps": ai.steps,
+                          "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+                          "time_to_gradient_s": round(t2 - t0, 3),
+                          "mlups": round(n * n * (pi.sweeps + ai.sweeps) / (t2 - t0) / 1e6, 1),
+                          "converged": bool(pi.converged and ai.converged)}), flush=True)
+        del solver
+
+
 def batch_sweeps(args):
     """Throughput of the seeded mix over a fixed number of sweeps: args.sweeps
     primal and args.sweeps adjoint sweeps of every instance in shared launches,
@@ -393,6 +445,10 @@ def cpu_baseline(n, steps, a):
 
 def main():
     args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
+              f"decomposition is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
     if args.mode == "sweeps":
         return sweeps_mode(args)
     if args.mode == "lbfgs":
@@ -401,10 +457,8 @@ def main():
         return batch_mode(args)
     if args.mode == "warmstart":
         return warmstart_mode(args)
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
-              f"decomposition is a design note, not built)", file=sys.stderr)
-        sys.exit(2)
+    if args.mode == "nodal":
+        return nodal_mode(args)
     import torch
     from paper_2609_31347_amd import inputs as I
     from paper_2609_31347_amd import slbm as S

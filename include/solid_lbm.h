@@ -244,6 +244,16 @@ int solid_lbm_set_tuning(slbm_ctx *ctx, int32_t steps_per_launch, int32_t rows_p
  * values, or a region over 1024 nodes. */
 int solid_lbm_set_tiles(slbm_ctx *ctx, int32_t tile_w, int32_t tile_h);
 
+/* Progress report of long solves: fn(user, phase, step, residual) is called
+ * on the calling thread from inside primal_solve / adjoint_solve /
+ * objective_and_grad (and the other solving calls) when a residual check has
+ * been read back and at least every_s seconds have passed since the last
+ * report; phase 0 = primal, 1 = adjoint; step and residual are those of the
+ * latest completed check.  fn = NULL turns reports off.  The callback must not
+ * call into the library with the same ctx. */
+typedef void (*slbm_progress_fn)(void *user, int32_t phase, int64_t step, double residual);
+int solid_lbm_set_progress(slbm_ctx *ctx, slbm_progress_fn fn, void *user, double every_s);
+
 /* Message of the last error on ctx (or of the last failed init if ctx is NULL). */
 const char *solid_lbm_last_error(const slbm_ctx *ctx);
 

@@ -51,6 +51,9 @@ struct slbm_ctx {
     int tb_T = -1;     // steps fused per launch (0/1: single-step sweeps; -1: automatic)
     int tb_H = 0;      // rows per wave of the fused sweeps (0: automatic)
     int tile_w = 0, tile_h = 0;  // tile of the LDS-tiled fused sweeps (0: automatic)
+    slbm_progress_fn progress = nullptr;  // optional report from the solve loops
+    void* progress_user = nullptr;
+    double progress_every = 0.0;          // seconds between reports
     bool tile_attr = false;      // LDS limits of the plate tile kernels raised
     int64_t nblk = 0;  // blocks of one sweep
     int64_t pcap = 0;  // capacity of the partial-sum buffer in blocks
@@ -346,6 +349,7 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
     }
     std::vector<std::pair<int64_t, int>> checks;  // (step, input buffer) of every check sweep
     int last_in = start;
+    auto last_report = std::chrono::steady_clock::now();
     while (s <= last && !stopped) {
         int64_t end = use_tol ? std::min(last, (s / K + 1) * K - 1) : last;
         if (!use_tol && end - s > 4096 * T) end = s + 4096 * T - 1;
@@ -390,7 +394,15 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
             HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
             if (chunk >= 1) {
                 HIPCHK(c, hipEventSynchronize(c->ev[slot ^ 1]));
-                if (c->h_status[slot ^ 1].stop) stopped = true;
+                const Status& hs = c->h_status[slot ^ 1];
+                if (hs.stop) stopped = true;
+                if (c->progress && hs.t_last >= 0) {
+                    auto now = std::chrono::steady_clock::now();
+                    if (std::chrono::duration<double>(now - last_report).count() >= c->progress_every) {
+                        last_report = now;
+                        c->progress(c->progress_user, adjoint ? 1 : 0, hs.t_last, hs.res);
+                    }
+                }
             }
             ++chunk;
         }
@@ -1200,6 +1212,16 @@ int solid_lbm_objective(slbm_ctx* c, double* J)
     if (!c || !J) return SLBM_EINVAL;
     if (!c->prim_done) return fail(c, SLBM_ESTATE, "no completed primal_solve");
     *J = c->J;
+    return SLBM_OK;
+}
+
+int solid_lbm_set_progress(slbm_ctx* c, slbm_progress_fn fn, void* user, double every_s)
+{
+    if (!c) return SLBM_EINVAL;
+    if (!(every_s >= 0.0)) return fail(c, SLBM_EINVAL, "every_s must be >= 0");
+    c->progress = fn;
+    c->progress_user = user;
+    c->progress_every = every_s;
     return SLBM_OK;
 }
 

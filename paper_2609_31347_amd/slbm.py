@@ -25,11 +25,15 @@ EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_gra
            "adjoint_solve_vjp",
            "solid_lbm_restore_solve", "solid_lbm_objective", "solid_lbm_set_control",
            "solid_lbm_run_steps", "solid_lbm_run_adjoint_steps", "solid_lbm_get_field",
-           "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_set_tiles", "solid_lbm_last_error",
+           "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_set_tiles", "solid_lbm_set_progress",
+           "solid_lbm_last_error",
            "solid_lbm_destroy",
            "solid_lbm_batch_init", "batch_objective_and_grad", "batch_gradient", "solid_lbm_batch_set_tuning",
            "solid_lbm_batch_time_sweeps", "solid_lbm_batch_instance", "solid_lbm_batch_last_error",
            "solid_lbm_batch_destroy")
+
+
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double)
 
 
 class SlbmError(RuntimeError):
@@ -76,6 +80,7 @@ def _load():
     lib.solid_lbm_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.solid_lbm_set_tiles.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.solid_lbm_set_progress.argtypes = [P, PROGRESS_FN, P, ctypes.c_double]
     lib.adjoint_solve_vjp.argtypes = [P, P, P, ctypes.c_int32, info]
     lib.objective_and_grad_from.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double), P, ctypes.c_int32, info, info]
     lib.solid_lbm_restore_solve.argtypes = [P, P, P, ctypes.c_int32]
@@ -308,6 +313,17 @@ def solid_lbm_objective(ctx):
 
 def solid_lbm_set_tuning(ctx, steps_per_launch=-1, rows_per_wave=0):
     return _check(ctx, LIB.solid_lbm_set_tuning(ctx.handle, int(steps_per_launch), int(rows_per_wave)))
+
+
+def solid_lbm_set_progress(ctx, fn=None, every_s=30.0):
+    """fn(phase, step, residual) is called from inside long solves at least
+    every_s seconds apart (phase 0 primal, 1 adjoint); None turns it off."""
+    if fn is None:
+        ctx._progress = None
+        return _check(ctx, LIB.solid_lbm_set_progress(ctx.handle, PROGRESS_FN(), None, 0.0))
+    cb = PROGRESS_FN(lambda user, phase, step, res: fn(int(phase), int(step), float(res)))
+    ctx._progress = cb                        # keeps the C callback alive with the context
+    return _check(ctx, LIB.solid_lbm_set_progress(ctx.handle, cb, None, float(every_s)))
 
 
 def solid_lbm_set_tiles(ctx, tile_w=0, tile_h=0):

@@ -319,3 +319,28 @@ def test_fused_and_single_step_solves_agree(S):
     assert out[0][2:] == out[1][2:]
     assert abs(out[0][0] - out[1][0]) <= 1e-13 * out[0][0]
     assert rel(out[1][1], out[0][1]) < 1e-12
+
+
+def test_progress_reports_from_inside_the_solves(S):
+    """The progress callback is called from the solve loops with the latest
+    residual check (every poll when every_s = 0), for both halves of
+    objective_and_grad, and can be switched off."""
+    n = 96
+    modes = I.two_mode_basis(n)
+    p = periodic_problem(n, n, 1 / n, 1.0, 0.3, I.two_mode_target(n), S.CTRL_FORCE_MODES, n_modes=2,
+                         force_modes=modes, tol=1e-10)
+    ctx = S.solid_lbm_init(p)
+    seen = []
+    S.solid_lbm_set_progress(ctx, lambda ph, st, r: seen.append((ph, st, r)), 0.0)
+    rc, J, g, pi, ai = S.objective_and_grad(ctx, np.array([0.1, 0.1]))
+    prim = [x for x in seen if x[0] == 0]
+    adj = [x for x in seen if x[0] == 1]
+    assert len(prim) >= 3 and len(adj) >= 3
+    for part, info in ((prim, pi), (adj, ai)):
+        steps = [x[1] for x in part]
+        assert steps == sorted(steps) and steps[-1] <= info.steps
+        assert all(np.isfinite(x[2]) and x[2] >= 0 for x in part)
+    S.solid_lbm_set_progress(ctx, None)
+    seen.clear()
+    S.objective_and_grad(ctx, np.array([0.1, 0.1]))
+    assert seen == []

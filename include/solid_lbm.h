@@ -187,6 +187,22 @@ int objective_and_grad_from(slbm_ctx *ctx, const double *control, const double *
                             double *grad, int32_t ptr_kind, slbm_solve_info *primal_info,
                             slbm_solve_info *adjoint_info);
 
+/* Forward-mode (tangent) solve, the f-AD of Sec. "Forward automatic
+ * differentiation" on the GPU: J at `control` and its directional derivative
+ * dJ = (dJ/dcontrol) . direction, from one iteration that carries every
+ * population together with its derivative along the direction (dual numbers
+ * through the same node map, closures and gamma included) to the K-lag test
+ * on both the value and the derivative displacement, then the two-step
+ * average.  direction has the length of the control; force directions are
+ * projected to zero mean as the control is.  One solve per direction (the
+ * cost that makes the adjoint preferable for many controls); a cross-check
+ * of the adjoint gradient and the gradient for scalar controls.  control and
+ * direction per ptr_kind; J, dJ host.  The primal state of ctx is
+ * invalidated (primal_solve afresh before adjoint_solve).  SLBM_NOT_CONVERGED
+ * (> 0) if max_steps ended the iteration first. */
+int tangent_solve(slbm_ctx *ctx, const double *control, const double *direction, double *J, double *dJ,
+                  int32_t ptr_kind, slbm_solve_info *info);
+
 /* ---- helpers ---- */
 
 /* Reinstates a converged primal state from a checkpoint: sets the control
@@ -248,7 +264,7 @@ int solid_lbm_set_tiles(slbm_ctx *ctx, int32_t tile_w, int32_t tile_h);
  * on the calling thread from inside primal_solve / adjoint_solve /
  * objective_and_grad (and the other solving calls) when a residual check has
  * been read back and at least every_s seconds have passed since the last
- * report; phase 0 = primal, 1 = adjoint; step and residual are those of the
+ * report; phase 0 = primal, 1 = adjoint, 2 = tangent; step and residual are those of the
  * latest completed check.  fn = NULL turns reports off.  The callback must not
  * call into the library with the same ctx. */
 typedef void (*slbm_progress_fn)(void *user, int32_t phase, int64_t step, double residual);

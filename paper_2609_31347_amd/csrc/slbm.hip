@@ -51,6 +51,9 @@ struct slbm_ctx {
     int tb_T = -1;     // steps fused per launch (0/1: single-step sweeps; -1: automatic)
     int tb_H = 0;      // rows per wave of the fused sweeps (0: automatic)
     int tile_w = 0, tile_h = 0;  // tile of the LDS-tiled fused sweeps (0: automatic)
+    // tangent (forward-mode) solves: allocated at the first tangent_solve
+    double *tv[2] = {nullptr, nullptr}, *td[2] = {nullptr, nullptr}, *gdot = nullptr, *Edot = nullptr,
+           *snapd = nullptr, *tpart = nullptr, *tdir = nullptr;
     slbm_progress_fn progress = nullptr;  // optional report from the solve loops
     void* progress_user = nullptr;
     double progress_every = 0.0;          // seconds between reports
@@ -314,6 +317,188 @@ void launch_tile(slbm_ctx* c, bool adjoint, const SweepArgs& s, int steps, int h
         TL_CASE(7, true, true, true)
     }
 #undef TL_CASE
+}
+
+// ---------------------------------------------------------------- tangent solves
+int64_t control_len(const slbm_ctx* c);
+int dot(slbm_ctx* c, const double* a, const double* w, int64_t n, double* out_host);
+
+int tangent_buffers(slbm_ctx* c)
+{
+    if (c->tv[0]) return SLBM_OK;
+    const size_t P8 = 8 * c->N * sizeof(double), P2 = 2 * c->N * sizeof(double);
+    int rc;
+    for (int k = 0; k < 2; ++k) {
+        if ((rc = dalloc(c, (void**)&c->tv[k], P8))) return rc;
+        if ((rc = dalloc(c, (void**)&c->td[k], P8))) return rc;
+    }
+    if ((rc = dalloc(c, (void**)&c->gdot, P2))) return rc;
+    if ((rc = dalloc(c, (void**)&c->Edot, c->N * sizeof(double)))) return rc;
+    if ((rc = dalloc(c, (void**)&c->snapd, P2))) return rc;
+    if ((rc = dalloc(c, (void**)&c->tpart, (size_t)c->pcap * 4 * sizeof(double)))) return rc;
+    if ((rc = dalloc(c, (void**)&c->tdir, (size_t)std::max<int64_t>(2 * c->N, 64) * sizeof(double)))) return rc;
+    return SLBM_OK;
+}
+
+// Derivative of the forcing / modulus along `dir` (control space), the same
+// maps as apply_control applied to the direction.
+int tangent_direction(slbm_ctx* c, const double* dir, int ptr_kind, bool* use_gdot, bool* use_Edot, double* E0dot)
+{
+    const int64_t len = control_len(c);
+    if (!dir) return fail(c, SLBM_EINVAL, "direction is NULL");
+    std::vector<double> h(len);
+    if (ptr_kind == SLBM_PTR_DEVICE) {
+        HIPCHK(c, hipMemcpyAsync(h.data(), dir, len * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::memcpy(h.data(), dir, len * sizeof(double));
+    }
+    if (!finite_all(h.data(), len)) return fail(c, SLBM_ENONFINITE, "direction has non-finite entries");
+    *use_gdot = *use_Edot = false;
+    *E0dot = 0.0;
+    switch (c->kind) {
+        case SLBM_CTRL_FORCE_MODES:
+            HIPCHK(c, hipMemcpyAsync(c->tdir, h.data(), len * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            hipLaunchKernelGGL(k_force_modes, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->modes,
+                               c->tdir, c->nmodes, 2 * c->N, c->dx2, c->gdot);
+            HIPCHK(c, hipGetLastError());
+            if (c->masked) {
+                hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->gdot,
+                                   (const double*)nullptr, c->code, c->N, 1.0, c->gdot);
+                HIPCHK(c, hipGetLastError());
+            }
+            *use_gdot = true;
+            break;
+        case SLBM_CTRL_FORCE_NODAL: {
+            HIPCHK(c, hipMemcpyAsync(c->tdir, h.data(), len * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            const double* mean = nullptr;
+            if (c->project) {
+                double m[2];
+                for (int k = 0; k < 2; ++k) {
+                    int rc = dot(c, c->tdir + k * c->N, nullptr, c->N, &m[k]);
+                    if (rc) return rc;
+                    m[k] /= (double)c->N;
+                }
+                HIPCHK(c, hipMemcpyAsync(c->work, m, 2 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                mean = c->work;
+            }
+            hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->tdir, mean,
+                               c->masked ? c->code : (const int32_t*)nullptr, c->N, c->dx2, c->gdot);
+            HIPCHK(c, hipGetLastError());
+            *use_gdot = true;
+            break;
+        }
+        case SLBM_CTRL_E_NODAL:
+            HIPCHK(c, hipMemcpyAsync(c->Edot, h.data(), len * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            *use_Edot = true;
+            break;
+        default:  // E = alpha^2
+            *E0dot = 2.0 * c->alpha_sq * h[0];
+            break;
+    }
+    return SLBM_OK;
+}
+
+void launch_tangent(slbm_ctx* c, const TangentArgs& a, bool check)
+{
+    const int sel = (c->masked ? 4 : 0) | (c->efield_on ? 2 : 0) | (check ? 1 : 0);
+    dim3 grid(grid_of(c->N)), block(kBlock);
+    const double inv = c->inv_nx;
+#define TG_CASE(i, M, EF, CH) \
+    case i: hipLaunchKernelGGL((k_tangent<M, EF, CH>), grid, block, 0, c->stream, a, inv); break;
+    switch (sel) {
+        TG_CASE(0, false, false, false)
+        TG_CASE(1, false, false, true)
+        TG_CASE(2, false, true, false)
+        TG_CASE(3, false, true, true)
+        TG_CASE(4, true, false, false)
+        TG_CASE(5, true, false, true)
+        TG_CASE(6, true, true, false)
+        TG_CASE(7, true, true, true)
+    }
+#undef TG_CASE
+}
+
+// Tangent iteration from zero (value and derivative), checks every K steps;
+// returns the final step t, the buffer X holding the input of step t, the
+// last residual and whether the test passed.
+int tangent_loop(slbm_ctx* c, const TangentArgs& base, int64_t* t_out, int* x_out, double* res_out, bool* conv_out,
+                 double* dev_ms)
+{
+    hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(1), 0, c->stream, c->status);
+    HIPCHK(c, hipGetLastError());
+    const bool use_tol = c->tol > 0.0;
+    const int64_t K = c->K, last = c->max_steps;
+    TangentArgs a = base;
+    int cur = 0, last_in = 0, chunk = 0;
+    int64_t s = 0;
+    bool stopped = false;
+    std::vector<std::pair<int64_t, int>> checks;
+    auto last_report = std::chrono::steady_clock::now();
+    HIPCHK(c, hipEventRecord(c->t0, c->stream));
+    while (s <= last && !stopped) {
+        int64_t end = use_tol ? std::min(last, (s / K + 1) * K - 1) : last;
+        if (!use_tol && end - s > 4096) end = s + 4095;
+        while (s <= end) {
+            const bool check = use_tol && s > 0 && s % K == 0;
+            a.srcv = c->tv[cur];
+            a.srcd = c->td[cur];
+            a.dstv = c->tv[cur ^ 1];
+            a.dstd = c->td[cur ^ 1];
+            launch_tangent(c, a, check);
+            if (check) {
+                hipLaunchKernelGGL(k_residual2, dim3(1), dim3(kBlock), 0, c->stream, c->tpart, c->nblk, c->status,
+                                   c->tol, s);
+                checks.emplace_back(s, cur);
+            }
+            if (s == last) last_in = cur;
+            cur ^= 1;
+            ++s;
+        }
+        HIPCHK(c, hipGetLastError());
+        if (use_tol) {
+            const int slot = chunk & 1;
+            HIPCHK(c, hipMemcpyAsync(&c->h_status[slot], c->status, sizeof(Status), hipMemcpyDeviceToHost,
+                                     c->stream));
+            HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
+            if (chunk >= 1) {
+                HIPCHK(c, hipEventSynchronize(c->ev[slot ^ 1]));
+                const Status& hs = c->h_status[slot ^ 1];
+                if (hs.stop) stopped = true;
+                if (c->progress && hs.t_last >= 0) {
+                    auto now = std::chrono::steady_clock::now();
+                    if (std::chrono::duration<double>(now - last_report).count() >= c->progress_every) {
+                        last_report = now;
+                        c->progress(c->progress_user, 2, hs.t_last, hs.res);
+                    }
+                }
+            }
+            ++chunk;
+        }
+    }
+    HIPCHK(c, hipEventRecord(c->t1, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float f = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&f, c->t0, c->t1));
+    *dev_ms = f;
+    Status st;
+    HIPCHK(c, hipMemcpy(&st, c->status, sizeof(Status), hipMemcpyDeviceToHost));
+    *res_out = st.res;
+    if (use_tol && st.stop) {
+        int xin = -1;
+        for (auto& ck : checks)
+            if (ck.first == st.t_conv) xin = ck.second;
+        if (xin < 0) return fail(c, SLBM_EHIP, "internal: converged step without a check sweep");
+        *t_out = st.t_conv;
+        *x_out = xin;
+        *conv_out = true;
+    } else {
+        *t_out = last;
+        *x_out = last_in;
+        *conv_out = false;
+    }
+    return SLBM_OK;
 }
 
 // Runs sweeps with indices 0 .. last (inclusive) from buffer parity `start`,
@@ -1213,6 +1398,77 @@ int solid_lbm_objective(slbm_ctx* c, double* J)
     if (!c->prim_done) return fail(c, SLBM_ESTATE, "no completed primal_solve");
     *J = c->J;
     return SLBM_OK;
+}
+
+int tangent_solve(slbm_ctx* c, const double* control, const double* direction, double* J, double* dJ,
+                  int32_t ptr_kind, slbm_solve_info* info)
+{
+    if (!c) return SLBM_EINVAL;
+    if (!J || !dJ) return fail(c, SLBM_EINVAL, "J and dJ are required");
+    auto w0 = std::chrono::steady_clock::now();
+    int rc;
+    if ((rc = tangent_buffers(c))) return rc;
+    if ((rc = apply_control(c, control, ptr_kind))) return rc;
+    // the primal state no longer belongs to the current control
+    c->prim_valid = false;
+    c->prim_done = false;
+    c->adj_done = false;
+    bool use_gdot, use_Edot;
+    double E0dot;
+    if ((rc = tangent_direction(c, direction, ptr_kind, &use_gdot, &use_Edot, &E0dot))) return rc;
+    for (int k = 0; k < 2; ++k) {
+        if ((rc = fill(c, c->tv[k], 8 * c->N, 0.0)) || (rc = fill(c, c->td[k], 8 * c->N, 0.0))) return rc;
+    }
+    if ((rc = fill(c, c->snap, 2 * c->N, 0.0)) || (rc = fill(c, c->snapd, 2 * c->N, 0.0))) return rc;
+    TangentArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = c->g;
+    a.gdot = use_gdot ? c->gdot : nullptr;
+    a.E = c->efield_on ? c->Efield : nullptr;
+    a.Edot = use_Edot ? c->Edot : nullptr;
+    a.code = c->code;
+    a.bnodes = c->bnodes;
+    a.snapv = c->snap;
+    a.snapd = c->snapd;
+    a.partial = c->tpart;
+    a.status = c->status;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.N = c->N;
+    a.E0 = c->E_cur;
+    a.E0dot = E0dot;
+    a.nu = c->nu;
+    int64_t t;
+    int X;
+    double res, dms;
+    bool conv;
+    if ((rc = tangent_loop(c, a, &t, &X, &res, &conv, &dms))) return rc;
+    if (c->masked)
+        hipLaunchKernelGGL(k_tangent_finalize<true>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->tv[X],
+                           c->td[X], c->tv[X ^ 1], c->td[X ^ 1], c->g, a.gdot, c->code, c->target, c->obs, c->nx,
+                           c->ny, c->N, c->inv_nx, c->tpart);
+    else
+        hipLaunchKernelGGL(k_tangent_finalize<false>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->tv[X],
+                           c->td[X], c->tv[X ^ 1], c->td[X ^ 1], c->g, a.gdot, c->code, c->target, c->obs, c->nx,
+                           c->ny, c->N, c->inv_nx, c->tpart);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_sum_partials2, dim3(1), dim3(kBlock), 0, c->stream, c->tpart, c->nblk, c->work);
+    HIPCHK(c, hipGetLastError());
+    double sums[2];
+    HIPCHK(c, hipMemcpyAsync(sums, c->work, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *J = 0.5 * sums[0] * c->dx2 / c->cbar;
+    *dJ = sums[1] * c->dx2 / c->cbar;
+    auto w1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->steps = t;
+        info->sweeps = t + 1;
+        info->residual = c->tol > 0.0 ? res : 0.0;
+        info->wall_s = std::chrono::duration<double>(w1 - w0).count();
+        info->device_ms = dms;
+        info->converged = conv ? 1 : 0;
+    }
+    return (c->tol > 0.0 && !conv) ? SLBM_NOT_CONVERGED : SLBM_OK;
 }
 
 int solid_lbm_set_progress(slbm_ctx* c, slbm_progress_fn fn, void* user, double every_s)

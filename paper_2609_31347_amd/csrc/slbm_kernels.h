@@ -539,6 +539,195 @@ __global__ __launch_bounds__(kBlock) void k_stress(const double* __restrict__ fb
 
 namespace slbm {
 
+// ---------------------------------------------------------------- tangent (forward-mode) sweeps
+// Forward-mode differentiation of the primal iteration (f-AD, Sec. "Forward
+// automatic differentiation"): every population carries its derivative with
+// respect to a scalar control direction (Dual value + eps derivative), the
+// control's derivative enters as g-dot (force controls) or E-dot (modulus
+// controls), and the sweep is the primal one evaluated in dual numbers
+// through the same node map (collision, gamma, closures).  At the fixed point
+// the derivative part is the tangent d-dot = (dd/dalpha) . direction.
+struct TangentArgs {
+    const double* __restrict__ srcv;   // 8 planes: values
+    const double* __restrict__ srcd;   // 8 planes: derivatives
+    double* __restrict__ dstv;
+    double* __restrict__ dstd;
+    const double* __restrict__ g;      // 2 planes
+    const double* __restrict__ gdot;   // 2 planes or null
+    const double* __restrict__ E;      // E plane (E field) or null
+    const double* __restrict__ Edot;   // its derivative plane or null
+    const int32_t* __restrict__ code;
+    const BNode* __restrict__ bnodes;
+    double* __restrict__ snapv;        // check sweeps: 2 planes each
+    double* __restrict__ snapd;
+    double* __restrict__ partial;      // check sweeps: 4 doubles per block
+    const Status* __restrict__ status;
+    int32_t nx, ny;
+    int64_t N;
+    double E0, E0dot, nu;              // uniform modulus and its derivative
+};
+
+__device__ __forceinline__ void block_sum4(double a, double b, double c, double d, double* out)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+        c += __shfl_xor(c, o);
+        d += __shfl_xor(d, o);
+    }
+    __shared__ double s4[4][kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { s4[0][w] = a; s4[1][w] = b; s4[2][w] = c; s4[3][w] = d; }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double x = 0.0;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) x += s4[threadIdx.x][i];
+        out[threadIdx.x] = x;
+    }
+}
+
+template <bool MASKED, bool EFIELD, bool CHECK>
+__global__ __launch_bounds__(kBlock) void k_tangent(TangentArgs a, double inv_nx)
+{
+    if (a.status->stop) return;
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double nv = 0.0, dv = 0.0, nd = 0.0, dd = 0.0;
+    const int code = (n < a.N) ? (MASKED ? a.code[n] : 0) : -1;
+    if (code >= 0) {
+        const int iy = row_of(n, a.nx, inv_nx);
+        const int ix = (int)(n - (int64_t)iy * a.nx);
+        int64_t idx[8];
+        neighbours(ix, iy, a.nx, a.ny, idx, +1);
+        const int64_t N = a.N;
+        Dual f[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) f[q] = Dual(a.srcv[q * N + idx[q]], a.srcd[q * N + idx[q]]);
+        Dual gg[2] = {Dual(a.g[n], a.gdot ? a.gdot[n] : 0.0), Dual(a.g[N + n], a.gdot ? a.gdot[N + n] : 0.0)};
+        const Dual E = EFIELD ? Dual(a.E[n], a.Edot ? a.Edot[n] : 0.0) : Dual(a.E0, a.E0dot);
+        const Relax<Dual> r = relax_from_E<Dual>(E, a.nu, code > 0);
+        const BNode* bn = (MASKED && code > 0) ? a.bnodes + (code - 1) : nullptr;
+        Dual fC[8], h[8], mb[5];
+        node_map<Dual>(f, gg, r, bn, true, fC, h, mb);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            a.dstv[q * N + n] = fC[q].v;
+            a.dstd[q * N + n] = fC[q].d;
+        }
+        if (bn) {
+            const uint32_t cut = bn->cut;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if ((cut >> q) & 1u) {
+                    a.dstv[q * N + idx[q]] = h[q].v;
+                    a.dstd[q * N + idx[q]] = h[q].d;
+                }
+        }
+        if (CHECK) {
+            const double v0 = mb[0].v, v1 = mb[1].v, e0 = mb[0].d, e1 = mb[1].d;
+            const double s0 = a.snapv[n], s1 = a.snapv[N + n], t0 = a.snapd[n], t1 = a.snapd[N + n];
+            nv = (v0 - s0) * (v0 - s0) + (v1 - s1) * (v1 - s1);
+            dv = v0 * v0 + v1 * v1;
+            nd = (e0 - t0) * (e0 - t0) + (e1 - t1) * (e1 - t1);
+            dd = e0 * e0 + e1 * e1;
+            a.snapv[n] = v0;
+            a.snapv[N + n] = v1;
+            a.snapd[n] = e0;
+            a.snapd[N + n] = e1;
+        }
+    }
+    if (CHECK) block_sum4(nv, dv, nd, dd, a.partial + 4 * (int64_t)blockIdx.x);
+}
+
+// K-lag residual of a tangent sweep: the larger of the value and derivative residuals.
+__global__ __launch_bounds__(kBlock) void k_residual2(const double* __restrict__ partial, int64_t nblk,
+                                                     Status* st, double tol, int64_t t)
+{
+    if (st->stop) return;
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+    for (int64_t k = threadIdx.x; k < nblk; k += kBlock) {
+        a += partial[4 * k];
+        b += partial[4 * k + 1];
+        c += partial[4 * k + 2];
+        d += partial[4 * k + 3];
+    }
+    __shared__ double o[4];
+    block_sum4(a, b, c, d, o);
+    if (threadIdx.x == 0) {
+        const double rv = o[1] > 0.0 ? sqrt(o[0] / o[1]) : (o[0] > 0.0 ? INFINITY : 0.0);
+        const double rd = o[3] > 0.0 ? sqrt(o[2] / o[3]) : (o[2] > 0.0 ? INFINITY : 0.0);
+        const double r = rv > rd ? rv : rd;
+        st->res = r;
+        st->t_last = t;
+        if (r < tol) {
+            st->stop = 1;
+            st->t_conv = t;
+        }
+    }
+}
+
+// Two-step averages of value and derivative displacements from X (f^C(t-1))
+// and Y (f^C(t)); partial sums of |r|^2 and r . d-dot over the observed
+// domain nodes (2 doubles per block), r = d - d*.
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_tangent_finalize(
+    const double* __restrict__ Xv, const double* __restrict__ Xd, const double* __restrict__ Yv,
+    const double* __restrict__ Yd, const double* __restrict__ g, const double* __restrict__ gdot,
+    const int32_t* __restrict__ code, const double* __restrict__ target, const uint8_t* __restrict__ obs,
+    int nx, int ny, int64_t N, double inv_nx, double* __restrict__ partial)
+{
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double sj = 0.0, sd = 0.0;
+    if (n < N && (!MASKED || code[n] >= 0) && (!obs || obs[n])) {
+        const int iy = row_of(n, nx, inv_nx);
+        const int ix = (int)(n - (int64_t)iy * nx);
+        int64_t idx[8];
+        neighbours(ix, iy, nx, ny, idx, +1);
+        // bared value and derivative displacement of the pull from one buffer pair
+        auto disp = [&](const double* vv, const double* dd, double out[4]) {
+            double fv[8], fd[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                fv[q] = vv[q * N + idx[q]];
+                fd[q] = dd[q * N + idx[q]];
+            }
+            out[0] = (fv[0] - fv[2]) + (fv[4] - fv[5]) + (fv[7] - fv[6]) + 0.5 * g[n];
+            out[1] = (fv[1] - fv[3]) + (fv[4] + fv[5]) - (fv[6] + fv[7]) + 0.5 * g[N + n];
+            out[2] = (fd[0] - fd[2]) + (fd[4] - fd[5]) + (fd[7] - fd[6]) + (gdot ? 0.5 * gdot[n] : 0.0);
+            out[3] = (fd[1] - fd[3]) + (fd[4] + fd[5]) - (fd[6] + fd[7]) + (gdot ? 0.5 * gdot[N + n] : 0.0);
+        };
+        double x[4], y[4], d[2], e[2];
+        disp(Xv, Xd, x);
+        disp(Yv, Yd, y);
+        d[0] = 0.5 * (x[0] + y[0]);
+        d[1] = 0.5 * (x[1] + y[1]);
+        e[0] = 0.5 * (x[2] + y[2]);
+        e[1] = 0.5 * (x[3] + y[3]);
+        const double r0 = d[0] - target[n], r1 = d[1] - target[N + n];
+        sj = r0 * r0 + r1 * r1;
+        sd = r0 * e[0] + r1 * e[1];
+    }
+    block_sum2(sj, sd, partial + 2 * (int64_t)blockIdx.x);
+}
+
+// out[0], out[1] = sums of partial[2 i], partial[2 i + 1] (fixed order)
+__global__ __launch_bounds__(kBlock) void k_sum_partials2(const double* __restrict__ partial, int64_t nblk,
+                                                         double* __restrict__ out)
+{
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < nblk; i += kBlock) {
+        a += partial[2 * i];
+        b += partial[2 * i + 1];
+    }
+    __shared__ double o[2];
+    block_sum2(a, b, o);
+    if (threadIdx.x == 0) {
+        out[0] = o[0];
+        out[1] = o[1];
+    }
+}
+
 // ---------------------------------------------------------------- temporally blocked sweeps
 // T fused time steps of the periodic, uniform-material bulk sweep (primal or
 // adjoint) per launch.  One 64-lane wave owns a strip of 64 consecutive

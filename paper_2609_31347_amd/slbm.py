@@ -22,7 +22,7 @@ PTR_HOST, PTR_DEVICE = 0, 1
 FIELD_COMPS = {FIELD_DISP: 2, FIELD_STRESS: 3, FIELD_ADJ_DISP: 2, FIELD_POPS: 8, FIELD_ADJ_POPS: 8,
                FIELD_RESIDUAL: 2, FIELD_CUR_DISP: 2, FIELD_AVG_POPS: 8}
 EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_grad", "objective_and_grad_from",
-           "adjoint_solve_vjp",
+           "adjoint_solve_vjp", "tangent_solve",
            "solid_lbm_restore_solve", "solid_lbm_objective", "solid_lbm_set_control",
            "solid_lbm_run_steps", "solid_lbm_run_adjoint_steps", "solid_lbm_get_field",
            "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_set_tiles", "solid_lbm_set_progress",
@@ -79,6 +79,8 @@ def _load():
     lib.solid_lbm_get_field.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32]
     lib.solid_lbm_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.tangent_solve.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.c_int32, info]
     lib.solid_lbm_set_tiles.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.solid_lbm_set_progress.argtypes = [P, PROGRESS_FN, P, ctypes.c_double]
     lib.adjoint_solve_vjp.argtypes = [P, P, P, ctypes.c_int32, info]
@@ -294,6 +296,20 @@ def adjoint_solve_vjp(ctx, d_cot, grad=None):
     info = SolveInfo()
     rc = _check(ctx, LIB.adjoint_solve_vjp(ctx.handle, dp, gp, kind, ctypes.byref(info)))
     return rc, grad, info
+
+
+def tangent_solve(ctx, control, direction):
+    """Forward mode: (rc, J, dJ, info) with dJ = grad J . direction."""
+    keep = []
+    cp, kind = _arg(control, keep)
+    dp, kind2 = _arg(direction, keep)
+    if kind2 != kind:
+        raise ValueError("control and direction must live in the same memory kind")
+    J, dJ = ctypes.c_double(), ctypes.c_double()
+    info = SolveInfo()
+    rc = _check(ctx, LIB.tangent_solve(ctx.handle, cp, dp, ctypes.byref(J), ctypes.byref(dJ), kind,
+                                       ctypes.byref(info)))
+    return rc, J.value, dJ.value, info
 
 
 def solid_lbm_restore_solve(ctx, control, avg_pops):

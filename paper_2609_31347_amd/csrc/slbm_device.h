@@ -86,7 +86,7 @@ struct BNode {
 };
 
 // Closure coefficients of one cut link (host, at set-up).  The closures
-// (the paper defers their formulas; this is the build's own first-order
+// (the paper defers their formulas; this is the library's own first-order
 // design, wall point at the link midpoint):
 //   Dirichlet  h_q = fC_qbar + 2 W_q c_q . d_D,   W = 1/3 (axis), 1/12 (diagonal)
 //              (W_q c_q . d are the populations whose moments are N d)

@@ -65,7 +65,7 @@ class SolveInfo(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+        raise ImportError(f"{LIB_PATH} is not built: run `python paper_2609_31347_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     P, pp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)
     info = ctypes.POINTER(SolveInfo)

@@ -370,7 +370,7 @@ def _plate_errors(orc, nxc):
 def test_plate_first_order_eoc(orc):
     """Curved Dirichlet/Neumann boundaries of the elliptic plate give first
     order (paper: EOC 1.06 / 1.07 for d, 1.01 / 0.71 for sigma).  The closures
-    are this build's own (the paper defers them), so only the order is pinned."""
+    are our own design (the paper defers them), so only the order is pinned."""
     ns = [32, 64, 128]
     errs = np.array([_plate_errors(orc, n) for n in ns])
     e = [eoc(ns, errs[:, k]) for k in range(4)]

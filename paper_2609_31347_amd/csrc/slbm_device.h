@@ -189,32 +189,44 @@ __host__ __device__ inline void node_map(const T f[8], const T g[2], const Relax
 
 // ---------------------------------------------------------------- bulk fast paths
 // Bulk collision (gamma = 0) in double: f (in) -> fC (out, may alias f).
-// Returns the bared displacement in d0, d1.
-__device__ __forceinline__ void collide_bulk(double f[8], double gx, double gy, double k11,
-                                             double ks, double kd, double& d0, double& d1)
+// Returns the bared displacement in d0, d1.  The same map as node_map without
+// boundary terms, with shared sums and differences of the populations and the
+// constant factors folded:
+//   fC_0,2 = S+ +- a/2,  fC_1,3 = S- +- b/2,  S+- = (k_s m_s +- k_d m_d)/4,
+//   a = (1 - theta) mb10 + gx/2,  b likewise,
+//   fC_4 = R + P, fC_5 = Q - R, fC_6 = R - P, fC_7 = -(Q + R),
+//   R = k11 m11 / 4,  P = theta (mb10 + mb01) / 4,  Q = theta (mb01 - mb10) / 4.
+__device__ __forceinline__ void collide_bulk(double f[8], double gx, double gy, double k11, double ks,
+                                             double kd, double& d0, double& d1)
 {
-    double m10 = (f[0] - f[2]) + (f[4] - f[5]) + (f[7] - f[6]);
-    double m01 = (f[1] - f[3]) + (f[4] + f[5]) - (f[6] + f[7]);
-    double m11 = (f[4] - f[5]) + (f[6] - f[7]);
-    double ms = (f[0] + f[1] + f[2] + f[3]) + 2.0 * (f[4] + f[5] + f[6] + f[7]);
-    double md = (f[0] - f[1]) + (f[2] - f[3]);
-    double mb10 = m10 + 0.5 * gx;
-    double mb01 = m01 + 0.5 * gy;
+    const double d02 = f[0] - f[2], d13 = f[1] - f[3];
+    const double d45 = f[4] - f[5], d67 = f[6] - f[7];
+    const double p45 = f[4] + f[5], p67 = f[6] + f[7];
+    const double p02 = f[0] + f[2], p13 = f[1] + f[3];
+    const double m10 = d02 + (d45 - d67);
+    const double m01 = d13 + (p45 - p67);
+    const double m11 = d45 + d67;
+    const double ms = (p02 + p13) + 2.0 * (p45 + p67);
+    const double md = p02 - p13;
+    const double mb10 = m10 + 0.5 * gx;
+    const double mb01 = m01 + 0.5 * gy;
     d0 = mb10;
     d1 = mb01;
-    double c10 = mb10 + 0.5 * gx;
-    double c01 = mb01 + 0.5 * gy;
-    double c11 = k11 * m11, cs = ks * ms, cd = kd * md;
-    double c12 = kTheta * mb10, c21 = kTheta * mb01;
-    double a = c10 - c12, b = c01 - c21;
-    f[0] = 0.25 * (2.0 * a + cs + cd);
-    f[2] = 0.25 * (cs + cd - 2.0 * a);
-    f[1] = 0.25 * (2.0 * b + cs - cd);
-    f[3] = 0.25 * (cs - cd - 2.0 * b);
-    f[4] = 0.25 * (c11 + c12 + c21);
-    f[5] = 0.25 * (c21 - c11 - c12);
-    f[6] = 0.25 * (c11 - c12 - c21);
-    f[7] = 0.25 * (c12 - c11 - c21);
+    const double ha = 0.5 * (1.0 - kTheta) * mb10 + 0.25 * gx;
+    const double hb = 0.5 * (1.0 - kTheta) * mb01 + 0.25 * gy;
+    const double S = (0.25 * ks) * ms, D = (0.25 * kd) * md;
+    const double Sp = S + D, Sm = S - D;
+    f[0] = Sp + ha;
+    f[2] = Sp - ha;
+    f[1] = Sm + hb;
+    f[3] = Sm - hb;
+    const double R = (0.25 * k11) * m11;
+    const double P = (0.25 * kTheta) * (mb10 + mb01);
+    const double Q = (0.25 * kTheta) * (mb01 - mb10);
+    f[4] = R + P;
+    f[5] = Q - R;
+    f[6] = R - P;
+    f[7] = -(Q + R);
 }
 
 // psi = M^{-T} phi (adjoint in moment space): (psi10, psi01, psi11, psi_s, psi_d, psi12, psi21)
@@ -230,28 +242,38 @@ __host__ __device__ inline void adj_moments(const double p[8], double psi[7])
 }
 
 // Transposed bulk collision: phi (= phi^S, in) -> phi^C = C^T phi^S - s (r . c_q) (out, may alias).
-// C = M^{-1} A M, so C^T = M^T A^T M^{-T}; A^T maps psi to
+// C = M^{-1} A M, so C^T = M^T A^T M^{-T}; A^T maps psi = M^{-T} phi to
 //   chi10 = psi10 + theta psi12, chi01 = psi01 + theta psi21,
 //   chi11 = k11 psi11, chi_s = ks psi_s, chi_d = kd psi_d   (others 0),
 // and M^T chi gives the populations.  The source -(dJ/df)^T = -s (r_x c_x + r_y c_y)
-// enters as chi10 -= s r_x, chi01 -= s r_y.
+// enters as chi10 -= s r_x, chi01 -= s r_y.  Written out with shared sums and
+// differences:  chi10 = (1 - theta)/2 (p0 - p2) + theta/4 ((p4 - p5) - (p6 - p7)) - s r_x,
+// chi01 = (1 - theta)/2 (p1 - p3) + theta/4 ((p4 + p5) - (p6 + p7)) - s r_y,
+// chi11 = k11/4 ((p4 - p5) + (p6 - p7)), chi_s = ks/4 ((p0 + p2) + (p1 + p3)),
+// chi_d = kd/4 ((p0 + p2) - (p1 + p3)).
 __device__ __forceinline__ void adj_collide_bulk(double p[8], double srx, double sry, double k11,
                                                  double ks, double kd)
 {
-    double psi[7];
-    adj_moments(p, psi);
-    double x10 = psi[0] + kTheta * psi[5] - srx;
-    double x01 = psi[1] + kTheta * psi[6] - sry;
-    double x11 = k11 * psi[2], xs = ks * psi[3], xd = kd * psi[4];
-    p[0] = x10 + xs + xd;
-    p[2] = xs + xd - x10;
-    p[1] = x01 + xs - xd;
-    p[3] = xs - xd - x01;
-    double t = 2.0 * xs;
-    p[4] = t + x11 + (x10 + x01);
-    p[5] = t - x11 + (x01 - x10);
-    p[6] = t + x11 - (x10 + x01);
-    p[7] = t - x11 + (x10 - x01);
+    const double d02 = p[0] - p[2], d13 = p[1] - p[3];
+    const double d45 = p[4] - p[5], d67 = p[6] - p[7];
+    const double p45 = p[4] + p[5], p67 = p[6] + p[7];
+    const double s02 = p[0] + p[2], s13 = p[1] + p[3];
+    const double x10 = 0.5 * (1.0 - kTheta) * d02 + (0.25 * kTheta) * (d45 - d67) - srx;
+    const double x01 = 0.5 * (1.0 - kTheta) * d13 + (0.25 * kTheta) * (p45 - p67) - sry;
+    const double x11 = (0.25 * k11) * (d45 + d67);
+    const double xs = (0.25 * ks) * (s02 + s13);
+    const double xd = (0.25 * kd) * (s02 - s13);
+    const double Ep = xs + xd, Em = xs - xd;
+    p[0] = Ep + x10;
+    p[2] = Ep - x10;
+    p[1] = Em + x01;
+    p[3] = Em - x01;
+    const double G = x10 + x01, H = x10 - x01;
+    const double T4 = 2.0 * xs + x11, T5 = 2.0 * xs - x11;
+    p[4] = T4 + G;
+    p[6] = T4 - G;
+    p[5] = T5 - H;
+    p[7] = T5 + H;
 }
 
 // Transposed map of a boundary node (eq. adjoint_collision at nodes with cut

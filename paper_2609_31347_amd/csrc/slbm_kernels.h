@@ -792,9 +792,9 @@ __device__ __forceinline__ int wrapi(int v, int n)
 
 // One pipeline step of a strip: `o` holds row r as loaded (level 0) and
 // returns level T's output (row r - T).
-template <int T, bool ADJ>
+template <int T, bool ADJ, bool SMALL>
 __device__ __forceinline__ void tb_row(double (&p2)[T][3], double (&p1a)[T][3], double (&p1b)[T][2],
-                                       double (&o)[8], const TBArgs& a, int r, int x)
+                                       double (&o)[8], const TBArgs& a, int r, int rw, int x)
 {
     constexpr int A0 = ADJ ? 3 : 1, A1 = ADJ ? 6 : 4, A2 = ADJ ? 7 : 5;   // planes pulled from row y-1
     const int64_t N = a.N;
@@ -830,7 +830,17 @@ __device__ __forceinline__ void tb_row(double (&p2)[T][3], double (&p1a)[T][3], 
         p1a[k - 1][2] = o[A2];
         p1b[k - 1][0] = o[0];
         p1b[k - 1][1] = o[2];
-        const int64_t gi = (int64_t)wrapi(r - k, a.ny) * a.nx + x;
+        // forcing row r - k; rw = r wrapped into [0, ny).  With T <= ny one
+        // conditional add (a select, no branch: the loads of all levels can be
+        // issued early) wraps it; grids with fewer rows than T use the modulo
+        int yy;
+        if (SMALL) {
+            yy = wrapi(r - k, a.ny);
+        } else {
+            yy = rw - k;
+            yy += yy < 0 ? a.ny : 0;
+        }
+        const int64_t gi = (int64_t)yy * a.nx + x;
         if (!ADJ) {
             double d0, d1;
             collide_bulk(f, a.g[gi], a.g[N + gi], a.k11, a.ks, a.kd, d0, d1);
@@ -843,8 +853,8 @@ __device__ __forceinline__ void tb_row(double (&p2)[T][3], double (&p1a)[T][3], 
 }
 
 // One strip (sx, sy) of a fused launch, run by one 64-lane wave.
-template <int T, bool ADJ>
-__device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
+template <int T, bool ADJ, bool SMALL>
+__device__ __forceinline__ void tb_strip_impl(const TBArgs& a, int sx, int sy)
 {
     constexpr int V = 64 - 2 * T;
     const int lane = threadIdx.x;
@@ -867,8 +877,10 @@ __device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
     }
     const int iters = (y1 - y0) + 2 * T;
     int r = y0 - T;
-    auto load = [&](int row, double (&v)[8]) {
-        const int64_t base = (int64_t)wrapi(row, ny) * nx + x;
+    int rw = wrapi(r, ny);                              // r wrapped into [0, ny)
+    auto next = [&](int v) { return v + 1 == ny ? 0 : v + 1; };
+    auto load = [&](int roww, double (&v)[8]) {
+        const int64_t base = (int64_t)roww * nx + x;
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = a.src[q * N + base];
     };
@@ -885,31 +897,42 @@ __device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
     int it = 0;
     for (; it + 1 < iters; it += 2, r += 2) {
         double o0[8], o1[8];
-        load(r, o0);
-        load(r + 1, o1);
-        tb_row<T, ADJ>(p2, p1a, p1b, o0, a, r, x);
+        const int rw1 = next(rw);
+        load(rw, o0);
+        load(rw1, o1);
+        tb_row<T, ADJ, SMALL>(p2, p1a, p1b, o0, a, r, rw, x);
         store(r, o0);
-        tb_row<T, ADJ>(p2, p1a, p1b, o1, a, r + 1, x);
+        tb_row<T, ADJ, SMALL>(p2, p1a, p1b, o1, a, r + 1, rw1, x);
         store(r + 1, o1);
+        rw = next(rw1);
     }
     if (it < iters) {
         double o0[8];
-        load(r, o0);
-        tb_row<T, ADJ>(p2, p1a, p1b, o0, a, r, x);
+        load(rw, o0);
+        tb_row<T, ADJ, SMALL>(p2, p1a, p1b, o0, a, r, rw, x);
         store(r, o0);
     }
 #else
     double nxt[8];
-    load(r, nxt);
+    load(rw, nxt);
     for (int it = 0; it < iters; ++it, ++r) {
         double o[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) o[q] = nxt[q];
-        if (it + 1 < iters) load(r + 1, nxt);
-        tb_row<T, ADJ>(p2, p1a, p1b, o, a, r, x);
+        const int rw1 = next(rw);
+        if (it + 1 < iters) load(rw1, nxt);
+        tb_row<T, ADJ, SMALL>(p2, p1a, p1b, o, a, r, rw, x);
         store(r, o);
+        rw = rw1;
     }
 #endif
+}
+
+template <int T, bool ADJ>
+__device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
+{
+    if (a.ny >= T) tb_strip_impl<T, ADJ, false>(a, sx, sy);
+    else tb_strip_impl<T, ADJ, true>(a, sx, sy);
 }
 
 template <int T, bool ADJ>

@@ -792,12 +792,11 @@ __device__ __forceinline__ int wrapi(int v, int n)
 
 // One pipeline step of a strip: `o` holds row r as loaded (level 0) and
 // returns level T's output (row r - T).
-template <int T, bool ADJ, bool SMALL>
+template <int T, bool ADJ>
 __device__ __forceinline__ void tb_row(double (&p2)[T][3], double (&p1a)[T][3], double (&p1b)[T][2],
-                                       double (&o)[8], const TBArgs& a, int r, int rw, int x)
+                                       double (&o)[8], const TBArgs& a, const double (&gh)[T][2])
 {
     constexpr int A0 = ADJ ? 3 : 1, A1 = ADJ ? 6 : 4, A2 = ADJ ? 7 : 5;   // planes pulled from row y-1
-    const int64_t N = a.N;
 #pragma unroll
     for (int k = 1; k <= T; ++k) {
         // pull of row y = r - k from level k-1
@@ -830,22 +829,12 @@ __device__ __forceinline__ void tb_row(double (&p2)[T][3], double (&p1a)[T][3], 
         p1a[k - 1][2] = o[A2];
         p1b[k - 1][0] = o[0];
         p1b[k - 1][1] = o[2];
-        // forcing row r - k; rw = r wrapped into [0, ny).  With T <= ny one
-        // conditional add (a select, no branch: the loads of all levels can be
-        // issued early) wraps it; grids with fewer rows than T use the modulo
-        int yy;
-        if (SMALL) {
-            yy = wrapi(r - k, a.ny);
-        } else {
-            yy = rw - k;
-            yy += yy < 0 ? a.ny : 0;
-        }
-        const int64_t gi = (int64_t)yy * a.nx + x;
+        // forcing (primal) or residual (adjoint) of row r - k from the history
         if (!ADJ) {
             double d0, d1;
-            collide_bulk(f, a.g[gi], a.g[N + gi], a.k11, a.ks, a.kd, d0, d1);
+            collide_bulk(f, gh[k - 1][0], gh[k - 1][1], a.k11, a.ks, a.kd, d0, d1);
         } else {
-            adj_collide_bulk(f, a.scale * a.g[gi], a.scale * a.g[N + gi], a.k11, a.ks, a.kd);
+            adj_collide_bulk(f, a.scale * gh[k - 1][0], a.scale * gh[k - 1][1], a.k11, a.ks, a.kd);
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) o[q] = f[q];
@@ -853,8 +842,8 @@ __device__ __forceinline__ void tb_row(double (&p2)[T][3], double (&p1a)[T][3], 
 }
 
 // One strip (sx, sy) of a fused launch, run by one 64-lane wave.
-template <int T, bool ADJ, bool SMALL>
-__device__ __forceinline__ void tb_strip_impl(const TBArgs& a, int sx, int sy)
+template <int T, bool ADJ>
+__device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
 {
     constexpr int V = 64 - 2 * T;
     const int lane = threadIdx.x;
@@ -868,21 +857,35 @@ __device__ __forceinline__ void tb_strip_impl(const TBArgs& a, int sx, int sy)
     // histories of level k's outputs (k = 0..T-1): p2 = row two back, p1 = row one back.
     // primal: rows y-1 feed planes {1,4,5}, rows y+1 feed {3,6,7};
     // adjoint: rows y-1 feed {3,6,7}, rows y+1 feed {1,4,5}.
-    double p2[T][3], p1a[T][3], p1b[T][2];
+    // gh[j] = forcing (or residual) of row r - 1 - j: each row's is loaded
+    // once, with its populations, and consumed by level j + 1 one row later
+    double p2[T][3], p1a[T][3], p1b[T][2], gh[T][2];
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         p2[k][0] = p2[k][1] = p2[k][2] = 0.0;
         p1a[k][0] = p1a[k][1] = p1a[k][2] = 0.0;
         p1b[k][0] = p1b[k][1] = 0.0;
+        gh[k][0] = gh[k][1] = 0.0;
     }
     const int iters = (y1 - y0) + 2 * T;
     int r = y0 - T;
     int rw = wrapi(r, ny);                              // r wrapped into [0, ny)
     auto next = [&](int v) { return v + 1 == ny ? 0 : v + 1; };
-    auto load = [&](int roww, double (&v)[8]) {
+    auto load = [&](int roww, double (&v)[8], double (&gr)[2]) {
         const int64_t base = (int64_t)roww * nx + x;
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = a.src[q * N + base];
+        gr[0] = a.g[base];
+        gr[1] = a.g[N + base];
+    };
+    auto shift = [&](const double (&gr)[2]) {
+#pragma unroll
+        for (int j = T - 1; j > 0; --j) {
+            gh[j][0] = gh[j - 1][0];
+            gh[j][1] = gh[j - 1][1];
+        }
+        gh[0][0] = gr[0];
+        gh[0][1] = gr[1];
     };
     auto store = [&](int row, const double (&v)[8]) {
         const int yo = row - T;
@@ -896,43 +899,39 @@ __device__ __forceinline__ void tb_strip_impl(const TBArgs& a, int sx, int sy)
     // two rows per trip: the second row's early levels overlap the first's late ones
     int it = 0;
     for (; it + 1 < iters; it += 2, r += 2) {
-        double o0[8], o1[8];
+        double o0[8], o1[8], g0[2], g1[2];
         const int rw1 = next(rw);
-        load(rw, o0);
-        load(rw1, o1);
-        tb_row<T, ADJ, SMALL>(p2, p1a, p1b, o0, a, r, rw, x);
+        load(rw, o0, g0);
+        load(rw1, o1, g1);
+        tb_row<T, ADJ>(p2, p1a, p1b, o0, a, gh);
         store(r, o0);
-        tb_row<T, ADJ, SMALL>(p2, p1a, p1b, o1, a, r + 1, rw1, x);
+        shift(g0);
+        tb_row<T, ADJ>(p2, p1a, p1b, o1, a, gh);
         store(r + 1, o1);
+        shift(g1);
         rw = next(rw1);
     }
     if (it < iters) {
-        double o0[8];
-        load(rw, o0);
-        tb_row<T, ADJ, SMALL>(p2, p1a, p1b, o0, a, r, rw, x);
+        double o0[8], g0[2];
+        load(rw, o0, g0);
+        tb_row<T, ADJ>(p2, p1a, p1b, o0, a, gh);
         store(r, o0);
     }
 #else
-    double nxt[8];
-    load(rw, nxt);
+    double nxt[8], gn[2];
+    load(rw, nxt, gn);
     for (int it = 0; it < iters; ++it, ++r) {
-        double o[8];
+        double o[8], gr[2] = {gn[0], gn[1]};
 #pragma unroll
         for (int q = 0; q < 8; ++q) o[q] = nxt[q];
         const int rw1 = next(rw);
-        if (it + 1 < iters) load(rw1, nxt);
-        tb_row<T, ADJ, SMALL>(p2, p1a, p1b, o, a, r, rw, x);
+        if (it + 1 < iters) load(rw1, nxt, gn);
+        tb_row<T, ADJ>(p2, p1a, p1b, o, a, gh);
         store(r, o);
+        shift(gr);
         rw = rw1;
     }
 #endif
-}
-
-template <int T, bool ADJ>
-__device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
-{
-    if (a.ny >= T) tb_strip_impl<T, ADJ, false>(a, sx, sy);
-    else tb_strip_impl<T, ADJ, true>(a, sx, sy);
 }
 
 template <int T, bool ADJ>

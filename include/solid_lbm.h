@@ -242,9 +242,10 @@ int solid_lbm_time_sweeps(slbm_ctx *ctx, int32_t adjoint, int64_t n, double *ms)
  * launch: 2, 4, 6 or 8 for periodic, uniform-material problems (wave-strip
  * kernel), 2 .. 8 for plates, E-field controls and problems given a tile by
  * solid_lbm_set_tiles (LDS-tiled kernel).  Automatic: the LDS-tiled kernel
- * for plates, E fields and periodic grids up to 262144 nodes (8 steps up to
+ * for plates, E fields and periodic grids up to 131072 nodes (8 steps up to
  * 131072 nodes, 6 above), the wave-strip kernel with 8 steps for larger
- * periodic grids.  rows_per_wave: rows each wave of a wave-strip launch
+ * periodic grids, with as many rows per wave as keep the wave count at or
+ * below the device's SIMD count.  rows_per_wave: rows each wave of a wave-strip launch
  * covers (0 = automatic).  Every setting gives the same result bit for bit:
  * a fused launch performs exactly the arithmetic of its single sweeps.
  * SLBM_EINVAL if the value is out of range, or if a tile set by

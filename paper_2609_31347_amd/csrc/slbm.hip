@@ -51,6 +51,7 @@ struct slbm_ctx {
     int tb_T = -1;     // steps fused per launch (0/1: single-step sweeps; -1: automatic)
     int tb_H = 0;      // rows per wave of the fused sweeps (0: automatic)
     int tile_w = 0, tile_h = 0;  // tile of the LDS-tiled fused sweeps (0: automatic)
+    int simds = 1024;            // SIMDs of the device (4 per compute unit)
     // tangent (forward-mode) solves: allocated at the first tangent_solve
     double *tv[2] = {nullptr, nullptr}, *td[2] = {nullptr, nullptr}, *gdot = nullptr, *Edot = nullptr,
            *snapd = nullptr, *tpart = nullptr, *tdir = nullptr;
@@ -173,10 +174,10 @@ void launch_sweep(slbm_ctx* c, bool adjoint, const SweepArgs& a, bool check)
 // fused kernels cover the periodic, uniform-material bulk.
 // The LDS-tiled kernel serves plates and E fields always, periodic uniform
 // problems when a tile shape was set, and, with automatic tuning, periodic
-// uniform grids up to 512 x 512 (measured on MI355X: 128^2 1.3 vs 4.7 us per
-// step, 256^2 1.8 vs 5.0, 512^2 4.0 vs 5.7 for the best wave-strip shape;
-// from 1024^2 on the wave strips are faster).
-constexpr int64_t kTileAutoMaxNodes = 262144;
+// uniform grids up to 131072 nodes (measured on MI355X: 128^2 1.3 vs 3.5 us
+// per step, 256^2 1.7 vs 3.9 for the best wave-strip shape; from 512^2 on the
+// wave strips are faster).
+constexpr int64_t kTileAutoMaxNodes = 131072;
 bool use_tiles(const slbm_ctx* c)
 {
     return c->masked || c->efield_on || c->tile_w > 0 || (c->tb_T < 0 && c->N <= kTileAutoMaxNodes);
@@ -191,13 +192,18 @@ int fused_steps(const slbm_ctx* c)
     return T;
 }
 
+// Automatic rows per wave: a strip launch runs one wave per (strip, row
+// block) and each wave carries a whole pipeline, so the time of a launch is
+// that of the slowest SIMD; the best shapes measured on MI355X keep the wave
+// count just at or below the SIMD count (1024^2, T = 8: 24 rows, 946 waves;
+// 2048^2: 96 rows, 946 waves).  Smallest multiple of 4 in [12, 96] that does.
 int fused_rows(const slbm_ctx* c, int T)
 {
     if (c->tb_H > 0) return std::min(c->tb_H, c->ny);
-    // measured on MI355X (periodic 1024^2 and 2048^2): 24 rows per wave up to
-    // ~1.5k rows, 48 beyond; the autotuner refines this per problem
-    int H = c->ny <= 1536 ? 24 : 48;
-    if (H < 2 * T) H = 2 * T;
+    const int strips = (c->nx + (64 - 2 * T) - 1) / (64 - 2 * T);
+    const int blocks = std::max(1, c->simds / strips);
+    int H = (c->ny + blocks - 1) / blocks;
+    H = std::min(96, std::max(12, (H + 3) / 4 * 4));
     return std::min(H, c->ny);
 }
 
@@ -1046,6 +1052,12 @@ int solid_lbm_init(const slbm_problem* p, slbm_ctx** out)
     c->nu = p->nu;
     c->tol = p->tol;
     c->inv_nx = 1.0 / nx;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            c->simds = 4 * cus;
+    }
     c->max_steps = p->max_steps;
     c->K = p->check_interval > 0 ? p->check_interval
                                  : 2 * (int64_t)std::ceil(0.005 / (c->dx2) - 1e-9);

@@ -6,8 +6,9 @@ grow like ln(e_0 / tol) / (1 - |lambda_slow|), so a better initial
 displacement d_0 saves steps in proportion to ln(1 / e_0).  Here a small
 convolutional network predicts d_0 from the modulus field E(x):
 
-  input  (4 channels): 1/E - 1 on the plate, the plate mask, and the
+  input  (7 channels): u = 1/E - 1 on the plate, the plate mask, the
          displacement of the same plate with E = 1 (d_ref, 2 channels, scaled),
+         and u averaged over 4 and 16 nodes and over the whole plate,
   output (2 channels): (d - d_ref) / s, s = max |d_ref|,
   6 layers of 3x3 convolutions (dilations 1, 2, 4, 8, 4, 1), 32 channels, ReLU
   between them, bf16 weights
@@ -33,7 +34,7 @@ from . import slbm as S
 # (inputs, outputs, ReLU, dilation): six 3x3 layers, 32 channels; the dilations
 # widen the receptive field to 41 nodes, since the displacement depends on E
 # over the whole plate
-LAYERS = ((4, 32, True, 1), (32, 32, True, 2), (32, 32, True, 4), (32, 32, True, 8), (32, 32, True, 4),
+LAYERS = ((7, 32, True, 1), (32, 32, True, 2), (32, 32, True, 4), (32, 32, True, 8), (32, 32, True, 4),
           (32, 2, False, 1))
 NU = 0.3
 
@@ -188,9 +189,26 @@ def solve_batch(cp, fields, tol, chunk=96):
     return np.stack(out), np.array(steps)
 
 
+BLURS = (4.0, 16.0)        # Gaussian widths (nodes) of the non-local input channels
+
+
 def features(E, mask, dref, s):
+    """Input channels: the compliance perturbation u = 1/E - 1 on the plate, the
+    plate mask, d_ref / s (2), u averaged over the plate with Gaussian weights
+    of width 4 and 16 nodes (normalised convolution inside the plate), and the
+    plate mean of u.  The displacement change is a global response to the
+    local source u; the averages hand the 41-node receptive field information
+    from farther away."""
+    from scipy import ndimage
     m = mask.astype(np.float64)
-    return np.stack([(1.0 / E - 1.0) * m, m, dref[0] / s, dref[1] / s]).astype(np.float32)
+    u = (1.0 / E - 1.0) * m
+    ch = [u, m, dref[0] / s, dref[1] / s]
+    for sig in BLURS:
+        num = ndimage.gaussian_filter(u, sig, mode="constant")
+        den = ndimage.gaussian_filter(m, sig, mode="constant")
+        ch.append(num / np.maximum(den, 1e-12) * m)
+    ch.append(np.full_like(u, u[m > 0].mean() if m.any() else 0.0) * m)
+    return np.stack(ch).astype(np.float32)
 
 
 # ------------------------------------------------------------------ training

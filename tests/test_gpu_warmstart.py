@@ -67,7 +67,7 @@ def test_network_gradients_match_reference(W):
     net = W.ConvNet(seed=3)
     rng = np.random.default_rng(7)
     B, H, Wd = 3, 11, 37
-    x = rng.standard_normal((B, 4, H, Wd)).astype(np.float32)
+    x = rng.standard_normal((B, net.layers[0][0], H, Wd)).astype(np.float32)
     t = rng.standard_normal((B, 2, H, Wd)).astype(np.float32) * 0.1
     mask = (rng.random((B, H, Wd)) > 0.3).astype(np.float32)
     # make the last layer non-trivial

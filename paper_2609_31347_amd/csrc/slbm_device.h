@@ -189,44 +189,43 @@ __host__ __device__ inline void node_map(const T f[8], const T g[2], const Relax
 
 // ---------------------------------------------------------------- bulk fast paths
 // Bulk collision (gamma = 0) in double: f (in) -> fC (out, may alias f).
-// Returns the bared displacement in d0, d1.  The same map as node_map without
-// boundary terms, with shared sums and differences of the populations and the
-// constant factors folded:
-//   fC_0,2 = S+ +- a/2,  fC_1,3 = S- +- b/2,  S+- = (k_s m_s +- k_d m_d)/4,
-//   a = (1 - theta) mb10 + gx/2,  b likewise,
-//   fC_4 = R + P, fC_5 = Q - R, fC_6 = R - P, fC_7 = -(Q + R),
-//   R = k11 m11 / 4,  P = theta (mb10 + mb01) / 4,  Q = theta (mb01 - mb10) / 4.
-__device__ __forceinline__ void collide_bulk(double f[8], double gx, double gy, double k11, double ks,
+// hx, hy are a quarter of the forcing (g / 4, exact in binary).  Returns the
+// bared displacement in d0, d1.  The same map as node_map without boundary
+// terms, with shared sums and differences of the populations and the constant
+// factors folded into multiply-adds:
+//   mb10 = m10 + g_x / 2,  fC_0,2 = Sp +- ha,  fC_1,3 = Sm +- hb,
+//   Sp = (ks + kd)/4 (f0 + f2) + (ks - kd)/4 (f1 + f3) + ks/2 (f4 + f5 + f6 + f7),
+//   Sm likewise with (ks + kd) and (ks - kd) swapped,  ha = (1 - theta)/2 mb10 + g_x/4,
+//   fC_4 = U + t mb10, fC_5 = -(V + t mb10), fC_6 = V - t mb10, fC_7 = t mb10 - U,
+//   U, V = k11/4 m11 +- t mb01,  t = theta/4.
+__device__ __forceinline__ void collide_bulk(double f[8], double hx, double hy, double k11, double ks,
                                              double kd, double& d0, double& d1)
 {
     const double d02 = f[0] - f[2], d13 = f[1] - f[3];
     const double d45 = f[4] - f[5], d67 = f[6] - f[7];
     const double p45 = f[4] + f[5], p67 = f[6] + f[7];
     const double p02 = f[0] + f[2], p13 = f[1] + f[3];
-    const double m10 = d02 + (d45 - d67);
-    const double m01 = d13 + (p45 - p67);
-    const double m11 = d45 + d67;
-    const double ms = (p02 + p13) + 2.0 * (p45 + p67);
-    const double md = p02 - p13;
-    const double mb10 = m10 + 0.5 * gx;
-    const double mb01 = m01 + 0.5 * gy;
+    const double mb10 = fma(2.0, hx, d02 + (d45 - d67));
+    const double mb01 = fma(2.0, hy, d13 + (p45 - p67));
     d0 = mb10;
     d1 = mb01;
-    const double ha = 0.5 * (1.0 - kTheta) * mb10 + 0.25 * gx;
-    const double hb = 0.5 * (1.0 - kTheta) * mb01 + 0.25 * gy;
-    const double S = (0.25 * ks) * ms, D = (0.25 * kd) * md;
-    const double Sp = S + D, Sm = S - D;
+    const double ha = fma(0.5 * (1.0 - kTheta), mb10, hx);
+    const double hb = fma(0.5 * (1.0 - kTheta), mb01, hy);
+    const double u = (0.5 * ks) * (p45 + p67);
+    const double A = 0.25 * (ks + kd), B = 0.25 * (ks - kd);
+    const double Sp = fma(A, p02, fma(B, p13, u));
+    const double Sm = fma(B, p02, fma(A, p13, u));
     f[0] = Sp + ha;
     f[2] = Sp - ha;
     f[1] = Sm + hb;
     f[3] = Sm - hb;
-    const double R = (0.25 * k11) * m11;
-    const double P = (0.25 * kTheta) * (mb10 + mb01);
-    const double Q = (0.25 * kTheta) * (mb01 - mb10);
-    f[4] = R + P;
-    f[5] = Q - R;
-    f[6] = R - P;
-    f[7] = -(Q + R);
+    constexpr double t = 0.25 * kTheta;
+    const double R = (0.25 * k11) * (d45 + d67);
+    const double U = fma(t, mb01, R), V = fma(-t, mb01, R);
+    f[4] = fma(t, mb10, U);
+    f[5] = fma(-t, mb10, -V);
+    f[6] = fma(-t, mb10, V);
+    f[7] = fma(t, mb10, -U);
 }
 
 // psi = M^{-T} phi (adjoint in moment space): (psi10, psi01, psi11, psi_s, psi_d, psi12, psi21)

@@ -117,7 +117,7 @@ __device__ __forceinline__ void primal_node(const SweepArgs& a, int64_t n, doubl
             Relax<double> r = relax_from_E<double>(a.E[n], a.nu, false);
             k11 = r.k11; ks = r.ks; kd = r.kd;
         }
-        collide_bulk(f, gx, gy, k11, ks, kd, d0, d1);
+        collide_bulk(f, 0.25 * gx, 0.25 * gy, k11, ks, kd, d0, d1);
 #pragma unroll
         for (int q = 0; q < 8; ++q) a.dst[q * N + n] = f[q];
     } else {
@@ -753,13 +753,9 @@ struct TBArgs {
 // Whole-wave lane shifts of a double: up = value of lane l-1, down = value of
 // lane l+1 (the end lanes keep their own value; they are halo lanes).
 // DPP wave_shr:1 / wave_shl:1 moves (no LDS crossbar) unless built with
-// SLBM_TB_DPP=0 (then ds_bpermute shuffles); SLBM_TB_UNROLL=2 runs two rows per
-// loop trip so the scheduler can overlap their independent levels.
+// SLBM_TB_DPP=0 (then ds_bpermute shuffles).
 #ifndef SLBM_TB_DPP
 #define SLBM_TB_DPP 1
-#endif
-#ifndef SLBM_TB_UNROLL
-#define SLBM_TB_UNROLL 2
 #endif
 __device__ __forceinline__ double lane_up(double v)
 {
@@ -791,17 +787,20 @@ __device__ __forceinline__ int wrapi(int v, int n)
 }
 
 // One pipeline step of a strip: `o` holds row r as loaded (level 0) and
-// returns level T's output (row r - T).
+// returns level T's output (row r - T).  Levels above kmax only advance their
+// input history (their outputs are not needed yet: see tb_strip).
 template <int T, bool ADJ>
 __device__ __forceinline__ void tb_row(double (&p2)[T][3], double (&p1a)[T][3], double (&p1b)[T][2],
-                                       double (&o)[8], const TBArgs& a, const double (&gh)[T][2])
+                                       double (&o)[8], const TBArgs& a, const double (&gh)[T][2], int kmax)
 {
     constexpr int A0 = ADJ ? 3 : 1, A1 = ADJ ? 6 : 4, A2 = ADJ ? 7 : 5;   // planes pulled from row y-1
 #pragma unroll
     for (int k = 1; k <= T; ++k) {
+        const bool on = k <= kmax;
         // pull of row y = r - k from level k-1
         double f[8];
-        if (!ADJ) {
+        if (!on) {
+        } else if (!ADJ) {
             f[0] = lane_up(p1b[k - 1][0]);     // (1,0)   from x-1, row y
             f[2] = lane_down(p1b[k - 1][1]);   // (-1,0)  from x+1, row y
             f[1] = p2[k - 1][0];               // (0,1)   row y-1
@@ -829,12 +828,13 @@ __device__ __forceinline__ void tb_row(double (&p2)[T][3], double (&p1a)[T][3], 
         p1a[k - 1][2] = o[A2];
         p1b[k - 1][0] = o[0];
         p1b[k - 1][1] = o[2];
-        // forcing (primal) or residual (adjoint) of row r - k from the history
+        if (!on) continue;
+        // quarter forcing (primal) or scaled residual (adjoint) of row r - k from the history
         if (!ADJ) {
             double d0, d1;
             collide_bulk(f, gh[k - 1][0], gh[k - 1][1], a.k11, a.ks, a.kd, d0, d1);
         } else {
-            adj_collide_bulk(f, a.scale * gh[k - 1][0], a.scale * gh[k - 1][1], a.k11, a.ks, a.kd);
+            adj_collide_bulk(f, gh[k - 1][0], gh[k - 1][1], a.k11, a.ks, a.kd);
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) o[q] = f[q];
@@ -857,8 +857,8 @@ __device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
     // histories of level k's outputs (k = 0..T-1): p2 = row two back, p1 = row one back.
     // primal: rows y-1 feed planes {1,4,5}, rows y+1 feed {3,6,7};
     // adjoint: rows y-1 feed {3,6,7}, rows y+1 feed {1,4,5}.
-    // gh[j] = forcing (or residual) of row r - 1 - j: each row's is loaded
-    // once, with its populations, and consumed by level j + 1 one row later
+    // gh[j] = forcing / 4 (or scaled residual) of row r - 1 - j: each row's is
+    // loaded once, with its populations, and consumed by level j + 1 one row later
     double p2[T][3], p1a[T][3], p1b[T][2], gh[T][2];
 #pragma unroll
     for (int k = 0; k < T; ++k) {
@@ -867,6 +867,7 @@ __device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
         p1b[k][0] = p1b[k][1] = 0.0;
         gh[k][0] = gh[k][1] = 0.0;
     }
+    const double gsc = ADJ ? a.scale : 0.25;
     const int iters = (y1 - y0) + 2 * T;
     int r = y0 - T;
     int rw = wrapi(r, ny);                              // r wrapped into [0, ny)
@@ -895,43 +896,58 @@ __device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
             for (int q = 0; q < 8; ++q) a.dst[q * N + base] = v[q];
         }
     };
-#if SLBM_TB_UNROLL >= 2
-    // two rows per trip: the second row's early levels overlap the first's late ones
+    // Rows are loaded one trip (two rows) ahead of their use, so a trip's
+    // loads are in flight while the previous trip computes (one wave per SIMD:
+    // no other wave hides the latency).  The loads are issued on every trip (a
+    // branch around them would make the compiler wait for all loads where the
+    // paths join); the last trip re-reads its own rows (L2 hits) instead.
     int it = 0;
+    double n0[8], n1[8], gn0[2], gn1[2];                // rows it, it + 1
+    load(rw, n0, gn0);
+    load(next(rw), n1, gn1);
+    auto take = [&](double (&o0)[8], double (&o1)[8], double (&g0)[2], double (&g1)[2], bool more) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            o0[q] = n0[q];
+            o1[q] = n1[q];
+        }
+        g0[0] = gsc * gn0[0];
+        g0[1] = gsc * gn0[1];
+        g1[0] = gsc * gn1[0];
+        g1[1] = gsc * gn1[1];
+        if (more) rw = next(next(rw));
+        load(rw, n0, gn0);
+        load(next(rw), n1, gn1);
+    };
+    // Pipeline fill: level k first produces a row that a later level (or the
+    // output) reads at iteration 2k (its row r - k = y0 - T + k lies in the
+    // halo of width T - k that level k must cover), so the first T trips of two
+    // rows run levels 1..trip only; nothing is stored before iteration 2T.
+    // A prefetched row past the strip's last (it + 3 = iters) is a valid,
+    // wrapped row that is never used.
+    for (int j = 0; j < T; ++j, it += 2, r += 2) {
+        double o0[8], o1[8], g0[2], g1[2];
+        take(o0, o1, g0, g1, true);
+        tb_row<T, ADJ>(p2, p1a, p1b, o0, a, gh, j);
+        shift(g0);
+        tb_row<T, ADJ>(p2, p1a, p1b, o1, a, gh, j);
+        shift(g1);
+    }
+    // two rows per trip: the second row's early levels overlap the first's late ones
     for (; it + 1 < iters; it += 2, r += 2) {
         double o0[8], o1[8], g0[2], g1[2];
-        const int rw1 = next(rw);
-        load(rw, o0, g0);
-        load(rw1, o1, g1);
-        tb_row<T, ADJ>(p2, p1a, p1b, o0, a, gh);
+        take(o0, o1, g0, g1, it + 2 < iters);
+        tb_row<T, ADJ>(p2, p1a, p1b, o0, a, gh, T);
         store(r, o0);
         shift(g0);
-        tb_row<T, ADJ>(p2, p1a, p1b, o1, a, gh);
+        tb_row<T, ADJ>(p2, p1a, p1b, o1, a, gh, T);
         store(r + 1, o1);
         shift(g1);
-        rw = next(rw1);
     }
     if (it < iters) {
-        double o0[8], g0[2];
-        load(rw, o0, g0);
-        tb_row<T, ADJ>(p2, p1a, p1b, o0, a, gh);
-        store(r, o0);
+        tb_row<T, ADJ>(p2, p1a, p1b, n0, a, gh, T);
+        store(r, n0);
     }
-#else
-    double nxt[8], gn[2];
-    load(rw, nxt, gn);
-    for (int it = 0; it < iters; ++it, ++r) {
-        double o[8], gr[2] = {gn[0], gn[1]};
-#pragma unroll
-        for (int q = 0; q < 8; ++q) o[q] = nxt[q];
-        const int rw1 = next(rw);
-        if (it + 1 < iters) load(rw1, nxt, gn);
-        tb_row<T, ADJ>(p2, p1a, p1b, o, a, gh);
-        store(r, o);
-        shift(gr);
-        rw = rw1;
-    }
-#endif
 }
 
 template <int T, bool ADJ>
@@ -1072,7 +1088,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
             if (!ADJ) {
                 if (!MASKED || code == 0) {
                     double d0, d1;
-                    collide_bulk(f, c0[j], c1[j], rl[j].k11, rl[j].ks, rl[j].kd, d0, d1);
+                    collide_bulk(f, 0.25 * c0[j], 0.25 * c1[j], rl[j].k11, rl[j].ks, rl[j].kd, d0, d1);
 #pragma unroll
                     for (int q = 0; q < 8; ++q) out[j][q] = f[q];
                 } else {

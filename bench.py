@@ -29,11 +29,11 @@ PEAK_GBS = 8000.0           # MI355X HBM3E
 # Measured HBM bytes per launch of the dominant kernel, keyed by (N, T, H), from
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors of a plain device copy);
 # see profiles/.  Entries are dropped whenever the kernel changes.
-TRAFFIC_BYTES = {(1024, 8, 24): (2.0 * 117787.8 + 65536.0) * 1024,
-                 (1024, 8, 32): (2.0 * 105685.1 + 65536.0) * 1024,
-                 (1024, 6, 24): (2.0 * 96313.0 + 65536.0) * 1024,
-                 (2048, 8, 48): (2.0 * 367735.8 + 262144.0) * 1024,
-                 (2048, 8, 96): (2.0 * 322591.5 + 262144.0) * 1024}
+TRAFFIC_BYTES = {(1024, 8, 24): (2.0 * 117834.1 + 65536.0) * 1024,
+                 (1024, 8, 32): (2.0 * 105726.5 + 65536.0) * 1024,
+                 (1024, 6, 24): (2.0 * 94197.1 + 65536.0) * 1024,
+                 (2048, 8, 48): (2.0 * 367832.2 + 262144.0) * 1024,
+                 (2048, 8, 96): (2.0 * 322647.1 + 262144.0) * 1024}
 
 
 def parse():

@@ -273,11 +273,13 @@ def test_full_size_converged_matches_closed_form(S):
 # ---------------------------------------------------------------- fused (multi-step) sweeps
 
 @pytest.mark.parametrize("T", [2, 4, 6, 8])
-@pytest.mark.parametrize("nx,ny,H", [(100, 37, 0), (100, 37, 5), (20, 9, 0), (64, 64, 17), (130, 3, 0)])
+@pytest.mark.parametrize("nx,ny,H", [(100, 37, 0), (100, 37, 5), (20, 9, 0), (64, 64, 17), (130, 3, 0),
+                                     (100, 37, 4), (40, 10, 1), (70, 33, 2)])
 def test_fused_sweeps_match_oracle(S, orc, T, nx, ny, H):
     """T time steps fused per launch (column strips with register pipelines)
     give the oracle's populations after a fixed step count, for the primal and
-    the adjoint, including grids narrower than a wave and shorter than 2T rows."""
+    the adjoint, including grids narrower than a wave and shorter than 2T rows,
+    and strips of a single row (the shortest pipeline: fill, then one row)."""
     dx = 1.0 / 48
     F = I.grf(nx, ny, dx, 0.05, 0.1, 21, comps=2) if min(nx, ny) > 4 else np.random.default_rng(1).standard_normal((2, ny, nx))
     F = F - F.mean((1, 2), keepdims=True)

@@ -728,6 +728,23 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials2(const double* __restri
     }
 }
 
+// ---------------------------------------------------------------- global-memory access
+// Loads and stores through pointers that the caller guarantees to address
+// global memory (device buffers).  The fused kernels also run inside batch
+// kernels that read their pointers from a device table; to the compiler
+// such pointers could address LDS or scratch and would take flat
+// instructions, so the accesses state the address space themselves.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ void stg(T* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
 // ---------------------------------------------------------------- temporally blocked sweeps
 // T fused time steps of the periodic, uniform-material bulk sweep (primal or
 // adjoint) per launch.  One 64-lane wave owns a strip of 64 consecutive
@@ -875,9 +892,9 @@ __device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
     auto load = [&](int roww, double (&v)[8], double (&gr)[2]) {
         const int64_t base = (int64_t)roww * nx + x;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = a.src[q * N + base];
-        gr[0] = a.g[base];
-        gr[1] = a.g[N + base];
+        for (int q = 0; q < 8; ++q) v[q] = ldg(a.src + q * N + base);
+        gr[0] = ldg(a.g + base);
+        gr[1] = ldg(a.g + N + base);
     };
     auto shift = [&](const double (&gr)[2]) {
 #pragma unroll
@@ -893,7 +910,7 @@ __device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
         if (out_lane && yo >= y0 && yo < y1) {
             const int64_t base = (int64_t)yo * nx + x;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a.dst[q * N + base] = v[q];
+            for (int q = 0; q < 8; ++q) stg(a.dst + q * N + base, v[q]);
         }
     };
     // Rows are loaded one trip (two rows) ahead of their use, so a trip's
@@ -1013,10 +1030,14 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
     int64_t gn[kTileNPT];
     double c0[kTileNPT], c1[kTileNPT];
     Relax<double> rl[kTileNPT];
-    // staged boundary records
+    // staged boundary records: a node's record is read from LDS (slot bsl) or,
+    // past the cap, from HBM (bng).  The two pointers are kept apart, so each
+    // use is compiled for its own memory (LDS reads, global loads); a pointer
+    // that could be either is a generic one, whose loads are slower.
     __shared__ int nstaged;
     BNode* lbn = reinterpret_cast<BNode*>(lds + 8 * R);
-    const BNode* bnp[kTileNPT];
+    const BNode* bng[kTileNPT];
+    int bsl[kTileNPT];
     if (MASKED) {
         if (threadIdx.x == 0) nstaged = 0;
         __syncthreads();
@@ -1036,31 +1057,32 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
         if (i < R) {
             const int64_t n = (int64_t)wrapi(y0 + ry[j], ny) * nx + wrapi(x0 + rx[j], nx);
             gn[j] = n;
-            cd[j] = MASKED ? a.code[n] : 0;
+            cd[j] = MASKED ? ldg(a.code + n) : 0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) lds[q * R + i] = a.src[q * N + n];
+            for (int q = 0; q < 8; ++q) lds[q * R + i] = ldg(a.src + q * N + n);
             if (cd[j] >= 0) {
                 if (ADJ) {
-                    c0[j] = a.scale * a.g[n];
-                    c1[j] = a.scale * a.g[N + n];
+                    c0[j] = a.scale * ldg(a.g + n);
+                    c1[j] = a.scale * ldg(a.g + N + n);
                 } else {
-                    c0[j] = a.g[n];
-                    c1[j] = a.g[N + n];
+                    c0[j] = ldg(a.g + n);
+                    c1[j] = ldg(a.g + N + n);
                 }
-                if (EFIELD || cd[j] > 0) rl[j] = relax_from_E<double>(EFIELD ? a.E[n] : a.E0, a.nu, cd[j] > 0);
+                if (EFIELD || cd[j] > 0) rl[j] = relax_from_E<double>(EFIELD ? ldg(a.E + n) : a.E0, a.nu, cd[j] > 0);
             }
         }
-        bnp[j] = nullptr;
+        bng[j] = a.bnodes;
+        bsl[j] = -1;
         if (MASKED && i < R && cd[j] > 0) {
             const int k = cd[j] - 1;
             const int slot = atomicAdd(&nstaged, 1);
-            bnp[j] = a.bnodes + k;
+            bng[j] = a.bnodes + k;
             if (slot < kTileMaxB) {
-                const double2* s2 = reinterpret_cast<const double2*>(a.bnodes + k);
-                double2* d2 = reinterpret_cast<double2*>(lbn + slot);
+                const double* s8 = reinterpret_cast<const double*>(a.bnodes + k);
+                double* d8 = reinterpret_cast<double*>(lbn + slot);
 #pragma unroll
-                for (int w = 0; w < (int)(sizeof(BNode) / 16); ++w) d2[w] = s2[w];
-                bnp[j] = lbn + slot;
+                for (int w = 0; w < (int)(sizeof(BNode) / 8); ++w) d8[w] = ldg(s8 + w);
+                bsl[j] = slot;
             }
         }
     }
@@ -1092,20 +1114,23 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
 #pragma unroll
                     for (int q = 0; q < 8; ++q) out[j][q] = f[q];
                 } else {
-                    const BNode* bn = bnp[j];
-                    double gg[2] = {c0[j], c1[j]}, fC[8], hv[8], mb[5];
-                    node_map<double>(f, gg, rl[j], bn, true, fC, hv, mb);
-                    const uint32_t cut = bn->cut;
-                    int64_t idx[8];
-                    if (last) neighbours((int)(n % nx), (int)(n / nx), nx, ny, idx, +1);
+                    auto bnode = [&](const BNode* bn) {
+                        double gg[2] = {c0[j], c1[j]}, fC[8], hv[8], mb[5];
+                        node_map<double>(f, gg, rl[j], bn, true, fC, hv, mb);
+                        const uint32_t cut = bn->cut;
+                        int64_t idx[8];
+                        if (last) neighbours((int)(n % nx), (int)(n / nx), nx, ny, idx, +1);
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        out[j][q] = fC[q];
-                        if ((cut >> q) & 1u) {
-                            if (last) a.dst[q * N + idx[q]] = hv[q];
-                            else lds[q * R + i - (cx(q) + cy(q) * RX)] = hv[q];
+                        for (int q = 0; q < 8; ++q) {
+                            out[j][q] = fC[q];
+                            if ((cut >> q) & 1u) {
+                                if (last) stg(a.dst + q * N + idx[q], hv[q]);
+                                else lds[q * R + i - (cx(q) + cy(q) * RX)] = hv[q];
+                            }
                         }
-                    }
+                    };
+                    if (bsl[j] >= 0) bnode(lbn + bsl[j]);
+                    else bnode(bng[j]);
                 }
             } else {
                 const double srx = c0[j], sry = c1[j];
@@ -1114,17 +1139,20 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
 #pragma unroll
                     for (int q = 0; q < 8; ++q) out[j][q] = f[q];
                 } else {
-                    const BNode* bn = bnp[j];
-                    const uint32_t cut = bn->cut;
-                    double yh[8];
+                    auto bnode = [&](const BNode* bn) {
+                        const uint32_t cut = bn->cut;
+                        double yh[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) yh[q] = ((cut >> q) & 1u) ? lds[q * R + i] : 0.0;
-                    adj_boundary(f, yh, bn, rl[j], srx, sry, out[j]);
+                        for (int q = 0; q < 8; ++q) yh[q] = ((cut >> q) & 1u) ? lds[q * R + i] : 0.0;
+                        adj_boundary(f, yh, bn, rl[j], srx, sry, out[j]);
+                    };
+                    if (bsl[j] >= 0) bnode(lbn + bsl[j]);
+                    else bnode(bng[j]);
                 }
             }
             if (last) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) a.dst[q * N + n] = out[j][q];
+                for (int q = 0; q < 8; ++q) stg(a.dst + q * N + n, out[j][q]);
             }
         }
         if (last) break;

@@ -132,7 +132,11 @@ inline void closure_coefs(int q, bool dirichlet, double w0, double w1, double nx
 //
 // Closures: the affine forms of BNode::coef (see closure_coefs); with_walls
 // = false drops the wall terms (the linear part, for the adjoint Jacobian).
-template <class T>
+// SPARSE reads the coefficients of cut links only, behind a branch per link
+// (a wave skips a link none of its nodes has cut); the default forms all
+// eight links and selects, so that records in HBM are fetched together.
+// Both give the same values.
+template <class T, bool SPARSE = false>
 __host__ __device__ inline void node_map(const T f[8], const T g[2], const Relax<T>& r,
                                          const BNode* bn, bool with_walls, T fC[8], T h[8],
                                          T mb[5])
@@ -179,6 +183,10 @@ __host__ __device__ inline void node_map(const T f[8], const T g[2], const Relax
     const uint32_t cut = bn->cut, dir = bn->dirichlet;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
+        if (SPARSE) {
+            h[q] = T(0.0);
+            if (!((cut >> q) & 1u)) continue;
+        }
         const double* k = bn->coef[q];
         T lin = T(k[0]) * sxx + T(k[1]) * syy + T(k[2]) * sxy;
         if (with_walls) lin = lin + T(k[3]);
@@ -284,6 +292,8 @@ __device__ __forceinline__ void adj_collide_bulk(double p[8], double srx, double
 // C_b = M^{-1} A_b M differs from the bulk collision by m_f = 0 after the
 // collision, m22 = -gamma k_s m_s; the transpose runs through the moments as
 // adj_collide_bulk does and equals it for gamma = 0 and no cut links.
+// SPARSE: as in node_map, only cut links (yh is 0 on the others) are read.
+template <bool SPARSE = false>
 __host__ __device__ inline void adj_boundary(const double yf[8], const double yh[8], const BNode* bn,
                                              const Relax<double>& r, double srx, double sry, double out[8])
 {
@@ -292,8 +302,10 @@ __host__ __device__ inline void adj_boundary(const double yf[8], const double yh
 #pragma unroll
     for (int q = 0; q < 8; ++q) z[q] = yf[q];
     double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+    const uint32_t cut = SPARSE ? bn->cut : 0xffu;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
+        if (!((cut >> q) & 1u)) continue;
         const double y = yh[q];
         z[opp(q)] += ((dir >> q) & 1u) ? y : -y;
         w0 += y * bn->coef[q][0];

@@ -16,6 +16,7 @@
 // closures' dropped outgoing populations exact.
 #pragma once
 #include "slbm_device.h"
+#include <type_traits>
 
 namespace slbm {
 
@@ -1114,12 +1115,13 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
 #pragma unroll
                     for (int q = 0; q < 8; ++q) out[j][q] = f[q];
                 } else {
-                    auto bnode = [&](const BNode* bn) {
+                    auto bnode = [&](const BNode* bn, auto sparse) {
                         double gg[2] = {c0[j], c1[j]}, fC[8], hv[8], mb[5];
-                        node_map<double>(f, gg, rl[j], bn, true, fC, hv, mb);
+                        node_map<double, decltype(sparse)::value>(f, gg, rl[j], bn, true, fC, hv, mb);
                         const uint32_t cut = bn->cut;
                         int64_t idx[8];
-                        if (last) neighbours((int)(n % nx), (int)(n / nx), nx, ny, idx, +1);
+                        // the last sweep covers nodes of the grid proper only (no wrap)
+                        if (last) neighbours(x0 + rx[j], y0 + ry[j], nx, ny, idx, +1);
 #pragma unroll
                         for (int q = 0; q < 8; ++q) {
                             out[j][q] = fC[q];
@@ -1129,8 +1131,8 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
                             }
                         }
                     };
-                    if (bsl[j] >= 0) bnode(lbn + bsl[j]);
-                    else bnode(bng[j]);
+                    if (bsl[j] >= 0) bnode(lbn + bsl[j], std::true_type());
+                    else bnode(bng[j], std::false_type());
                 }
             } else {
                 const double srx = c0[j], sry = c1[j];
@@ -1139,15 +1141,15 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
 #pragma unroll
                     for (int q = 0; q < 8; ++q) out[j][q] = f[q];
                 } else {
-                    auto bnode = [&](const BNode* bn) {
+                    auto bnode = [&](const BNode* bn, auto sparse) {
                         const uint32_t cut = bn->cut;
                         double yh[8];
 #pragma unroll
                         for (int q = 0; q < 8; ++q) yh[q] = ((cut >> q) & 1u) ? lds[q * R + i] : 0.0;
-                        adj_boundary(f, yh, bn, rl[j], srx, sry, out[j]);
+                        adj_boundary<decltype(sparse)::value>(f, yh, bn, rl[j], srx, sry, out[j]);
                     };
-                    if (bsl[j] >= 0) bnode(lbn + bsl[j]);
-                    else bnode(bng[j]);
+                    if (bsl[j] >= 0) bnode(lbn + bsl[j], std::true_type());
+                    else bnode(bng[j], std::false_type());
                 }
             }
             if (last) {

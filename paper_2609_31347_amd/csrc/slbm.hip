@@ -271,14 +271,12 @@ int tile_lds_limits(slbm_ctx* c)
 {
     if (c->tile_attr) return SLBM_OK;
     const int lmax = (int)tile_lds_bytes(kTileMaxNodes, true);
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<true, false, false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<true, true, false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<true, false, true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<true, true, true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+    // plates: two copies of a region and the staged records exceed the default 64 KiB
+    const void* fns[4] = {reinterpret_cast<const void*>(&k_sweep_tile<true, false, false>),
+                          reinterpret_cast<const void*>(&k_sweep_tile<true, true, false>),
+                          reinterpret_cast<const void*>(&k_sweep_tile<true, false, true>),
+                          reinterpret_cast<const void*>(&k_sweep_tile<true, true, true>)};
+    for (const void* fn : fns) HIPCHK(c, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
     c->tile_attr = true;
     return SLBM_OK;
 }

@@ -979,15 +979,18 @@ __global__ __launch_bounds__(64) void k_sweep_tb(TBArgs a)
 // Several sweeps of a plate (masked domain with boundary closures) or of a
 // per-node modulus field per launch.  A workgroup owns a tile of tw x th
 // nodes; it loads the tile plus a halo of `halo` nodes (all 8 planes) into
-// LDS, runs `steps` <= halo sweeps there in place, and writes only the
-// tile's own nodes (and the ghost slots of its boundary nodes) back to HBM.
-// Sweep s computes the tile grown by steps - s nodes, so every value it
-// pulls was produced by sweep s - 1 inside the region.  Each sweep reads all
-// pulls first and writes after a barrier; a ghost slot (x - c_q, q) of a cut
-// link is read and written only by its boundary node x (and an adjoint
-// boundary node's own slot of a cut link only by x), so those are written
-// at once.  The per-node arithmetic is the single-step kernels' own, so a
-// launch of k steps equals k single sweeps bit for bit.
+// LDS, runs `steps` <= halo sweeps there, and writes only the tile's own
+// nodes (and the ghost slots of its boundary nodes) back to HBM.  Plates keep
+// two LDS copies of the region: sweep s reads copy (s - 1) % 2 and writes
+// copy s % 2, as the single-step sweeps read one population buffer and write
+// the other, so one barrier per sweep orders them (their slower boundary
+// waves made the second barrier costly).  Unmasked problems sweep one copy in
+// place: all pulls are read, a barrier, then the writes and a second barrier
+// (half the LDS, and measured faster there).  Sweep s computes
+// the tile grown by steps - s nodes, so every value it pulls was produced by
+// sweep s - 1 inside the region.  The per-node arithmetic is the
+// single-step kernels' own, so a launch of k steps equals k single sweeps
+// bit for bit.
 struct TileArgs {
     const double* __restrict__ src;
     double* __restrict__ dst;
@@ -1011,11 +1014,12 @@ constexpr int kTileMaxB = 96;                        // 96 x 272 B
 
 __host__ __device__ constexpr size_t tile_lds_bytes(int region, bool masked)
 {
-    return (size_t)8 * region * sizeof(double) + (masked ? (size_t)kTileMaxB * sizeof(BNode) : 0);
+    return (size_t)(masked ? 16 : 8) * region * sizeof(double) + (masked ? (size_t)kTileMaxB * sizeof(BNode) : 0);
 }
 
 // One tile (index `tile` of the problem's tiles_x x tiles_y) of a tiled launch;
-// lds: 8 planes of the region, then the staged boundary records.
+// lds: the region's 8 planes (two copies for plates), then the staged
+// boundary records.
 template <bool MASKED, bool EFIELD, bool ADJ>
 __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* lds)
 {
@@ -1036,7 +1040,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
     // use is compiled for its own memory (LDS reads, global loads); a pointer
     // that could be either is a generic one, whose loads are slower.
     __shared__ int nstaged;
-    BNode* lbn = reinterpret_cast<BNode*>(lds + 8 * R);
+    BNode* lbn = reinterpret_cast<BNode*>(lds + (MASKED ? 16 : 8) * R);
     const BNode* bng[kTileNPT];
     int bsl[kTileNPT];
     if (MASKED) {
@@ -1059,8 +1063,15 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
             const int64_t n = (int64_t)wrapi(y0 + ry[j], ny) * nx + wrapi(x0 + rx[j], nx);
             gn[j] = n;
             cd[j] = MASKED ? ldg(a.code + n) : 0;
+            // plates fill both copies: slots that no sweep writes (outside
+            // nodes, which adjoint boundary nodes pull from) must read their
+            // stored values
 #pragma unroll
-            for (int q = 0; q < 8; ++q) lds[q * R + i] = ldg(a.src + q * N + n);
+            for (int q = 0; q < 8; ++q) {
+                const double v = ldg(a.src + q * N + n);
+                lds[q * R + i] = v;
+                if (MASKED) lds[(8 + q) * R + i] = v;
+            }
             if (cd[j] >= 0) {
                 if (ADJ) {
                     c0[j] = a.scale * ldg(a.g + n);
@@ -1090,6 +1101,8 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
     __syncthreads();
     for (int s = 1; s <= a.steps; ++s) {
         const bool last = s == a.steps;
+        const double* cur = MASKED ? lds + ((s - 1) & 1) * 8 * R : lds;   // written by sweep s - 1
+        double* nxt = MASKED ? lds + (s & 1) * 8 * R : lds;
         const int m = h - (a.steps - s);             // this sweep computes [m, RX - m) x [m, RY - m)
         double out[kTileNPT][8];
         bool act[kTileNPT];
@@ -1106,7 +1119,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int off = cx(q) + cy(q) * RX;
-                f[q] = lds[q * R + (ADJ ? i + off : i - off)];
+                f[q] = cur[q * R + (ADJ ? i + off : i - off)];
             }
             if (!ADJ) {
                 if (!MASKED || code == 0) {
@@ -1127,7 +1140,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
                             out[j][q] = fC[q];
                             if ((cut >> q) & 1u) {
                                 if (last) stg(a.dst + q * N + idx[q], hv[q]);
-                                else lds[q * R + i - (cx(q) + cy(q) * RX)] = hv[q];
+                                else nxt[q * R + i - (cx(q) + cy(q) * RX)] = hv[q];
                             }
                         }
                     };
@@ -1145,7 +1158,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
                         const uint32_t cut = bn->cut;
                         double yh[8];
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) yh[q] = ((cut >> q) & 1u) ? lds[q * R + i] : 0.0;
+                        for (int q = 0; q < 8; ++q) yh[q] = ((cut >> q) & 1u) ? cur[q * R + i] : 0.0;
                         adj_boundary<decltype(sparse)::value>(f, yh, bn, rl[j], srx, sry, out[j]);
                     };
                     if (bsl[j] >= 0) bnode(lbn + bsl[j], std::true_type());
@@ -1158,13 +1171,13 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
             }
         }
         if (last) break;
-        __syncthreads();
+        if (!MASKED) __syncthreads();               // in place: every pull read before the writes
 #pragma unroll
         for (int j = 0; j < kTileNPT; ++j) {
             if (!act[j]) continue;
             const int i = threadIdx.x + j * kTileBlock;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) lds[q * R + i] = out[j][q];
+            for (int q = 0; q < 8; ++q) nxt[q * R + i] = out[j][q];
         }
         __syncthreads();
     }
@@ -1174,7 +1187,7 @@ template <bool MASKED, bool EFIELD, bool ADJ>
 __global__ __launch_bounds__(kTileBlock) void k_sweep_tile(TileArgs a)
 {
     if (a.status->stop) return;
-    extern __shared__ __align__(16) double lds[];    // 8 planes of RX * RY doubles, then staged records
+    extern __shared__ __align__(16) double lds[];    // 8 planes of RX * RY doubles (2 copies for plates), then staged records
     tile_body<MASKED, EFIELD, ADJ>(a, blockIdx.x, lds);
 }
 

@@ -255,8 +255,9 @@ int solid_lbm_set_tuning(slbm_ctx *ctx, int32_t steps_per_launch, int32_t rows_p
 /* Interior tile (tile_w x tile_h nodes) of each workgroup of the LDS-tiled
  * fused sweeps (selects that kernel also for periodic uniform problems); the
  * tile plus a halo of
- * steps_per_launch nodes on every side must hold at most 1024 nodes (8 FP64
- * planes in 64 KiB of LDS).  0, 0 = automatic (a 32 x 32 region).  Does not
+ * steps_per_launch nodes on every side must hold at most 1024 nodes (one
+ * node per thread of a 1024-thread workgroup; 8 FP64 planes in 64 KiB of
+ * LDS, two copies for plates).  0, 0 = automatic (a 32 x 32 region).  Does not
  * change results.  SLBM_EINVAL for one zero and one nonzero value, negative
  * values, or a region over 1024 nodes. */
 int solid_lbm_set_tiles(slbm_ctx *ctx, int32_t tile_w, int32_t tile_h);

@@ -265,8 +265,9 @@ void tile_shape(const slbm_ctx* c, int h, int* tw, int* th)
     *th = std::max(2, 32 - 2 * h);
 }
 
-// Plate tiles stage boundary data in LDS beyond the default 64 KiB of
-// dynamic LDS: raise the limit of those kernels (once per context).
+// Plate tiles hold two copies of the region and the staged boundary records,
+// beyond the default 64 KiB of dynamic LDS: raise the limit of those kernels
+// (once per context).
 int tile_lds_limits(slbm_ctx* c)
 {
     if (c->tile_attr) return SLBM_OK;

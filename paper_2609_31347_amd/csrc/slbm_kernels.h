@@ -1006,8 +1006,8 @@ struct TileArgs {
 };
 
 constexpr int kTileBlock = 1024;
-constexpr int kTileNPT = 1;                          // region nodes per thread
-constexpr int kTileMaxNodes = kTileBlock * kTileNPT; // region <= 1024 nodes (64 KiB of LDS)
+constexpr int kTileNPT = 1;                          // region nodes per thread (2 with 512 threads measured slower)
+constexpr int kTileMaxNodes = kTileBlock * kTileNPT; // region <= 1024 nodes (64 KiB of LDS per copy)
 // Boundary records staged in LDS once per launch (plates); records beyond
 // the cap are read from HBM / L2 (same values, only slower).
 constexpr int kTileMaxB = 96;                        // 96 x 272 B

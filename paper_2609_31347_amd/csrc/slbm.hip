@@ -306,6 +306,7 @@ void launch_tile(slbm_ctx* c, bool adjoint, const SweepArgs& s, int steps, int h
     tile_shape(c, halo, &a.tw, &a.th);
     a.tiles_x = (c->nx + a.tw - 1) / a.tw;
     const int tiles_y = (c->ny + a.th - 1) / a.th;
+    a.order_by_kind = c->masked && (int64_t)a.tiles_x * tiles_y <= c->simds / 4 ? 1 : 0;
     const size_t lds = tile_lds_bytes((a.tw + 2 * halo) * (a.th + 2 * halo), c->masked);
     dim3 grid((unsigned)(a.tiles_x * tiles_y)), block(kTileBlock);
     int sel = (c->masked ? 4 : 0) | (c->efield_on ? 2 : 0) | (adjoint ? 1 : 0);

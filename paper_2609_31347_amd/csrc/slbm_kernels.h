@@ -1003,6 +1003,7 @@ struct TileArgs {
     int64_t N;
     double k11, ks, kd, E0, nu, scale;
     int32_t tw, th, halo, steps, tiles_x;
+    int32_t order_by_kind;           // plates: threads take bulk, then boundary, then outside nodes
 };
 
 constexpr int kTileBlock = 1024;
@@ -1043,13 +1044,76 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
     BNode* lbn = reinterpret_cast<BNode*>(lds + (MASKED ? 16 : 8) * R);
     const BNode* bng[kTileNPT];
     int bsl[kTileNPT];
+    // Thread j-pass node: region node threadIdx.x + j * kTileBlock, or, with
+    // order_by_kind (plates), a stable order by kind -- bulk nodes first, then
+    // boundary nodes, then outside nodes -- so that the few boundary nodes
+    // (whose node map is several times the bulk work) fill one or two waves
+    // instead of diverging in many, and outside nodes leave whole waves idle.
+    // Each node's arithmetic is unchanged, only the thread that runs it.  The
+    // order costs a round trip to HBM for the node codes before the other
+    // loads; measured, it pays where a launch has no more tiles than the GPU
+    // has CUs (each workgroup's latency sets the time), not beyond.
+    int ni[kTileNPT];
+#pragma unroll
+    for (int j = 0; j < kTileNPT; ++j) ni[j] = threadIdx.x + j * kTileBlock;
     if (MASKED) {
         if (threadIdx.x == 0) nstaged = 0;
-        __syncthreads();
+        if (a.order_by_kind) {
+            constexpr int W = kTileBlock / 64;
+            __shared__ int wcount[kTileNPT][2][W];      // bulk / boundary nodes per wave
+            __shared__ short order[kTileMaxNodes];      // region node of each slot
+            const int w = threadIdx.x / 64;
+            const uint64_t below = __lanemask_lt();
+            uint64_t b0[kTileNPT], b1[kTileNPT];
+            int kd_[kTileNPT];
+#pragma unroll
+            for (int j = 0; j < kTileNPT; ++j) {
+                const int i = ni[j];
+                int c = -1;
+                if (i < R) c = ldg(a.code + (int64_t)wrapi(y0 + i / RX, ny) * nx + wrapi(x0 + i % RX, nx));
+                kd_[j] = c < 0 ? 2 : (c > 0 ? 1 : 0);
+                b0[j] = __ballot(kd_[j] == 0);
+                b1[j] = __ballot(kd_[j] == 1);
+                if ((threadIdx.x & 63) == 0) {
+                    wcount[j][0][w] = __popcll(b0[j]);
+                    wcount[j][1][w] = __popcll(b1[j]);
+                }
+            }
+            __syncthreads();
+            // totals and the counts of earlier waves (pass j's waves come after pass j - 1's)
+            int tot0 = 0, tot1 = 0;
+            int pre0[kTileNPT], pre1[kTileNPT];
+#pragma unroll
+            for (int j = 0; j < kTileNPT; ++j) {
+                pre0[j] = tot0;
+                pre1[j] = tot1;
+                for (int v = 0; v < W; ++v) {
+                    const int n0 = wcount[j][0][v], n1 = wcount[j][1][v];
+                    if (v < w) {
+                        pre0[j] += n0;
+                        pre1[j] += n1;
+                    }
+                    tot0 += n0;
+                    tot1 += n1;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kTileNPT; ++j) {
+                const int i = ni[j];
+                const int r0 = pre0[j] + __popcll(b0[j] & below), r1 = pre1[j] + __popcll(b1[j] & below);
+                const int slot = kd_[j] == 0 ? r0 : kd_[j] == 1 ? tot0 + r1 : tot0 + tot1 + (i - r0 - r1);
+                order[slot] = (short)i;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kTileNPT; ++j) ni[j] = order[threadIdx.x + j * kTileBlock];
+        } else {
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int j = 0; j < kTileNPT; ++j) {
-        const int i = threadIdx.x + j * kTileBlock;
+        const int i = ni[j];
         rx[j] = i % RX;
         ry[j] = i / RX;
         cd[j] = -1;
@@ -1108,7 +1172,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
         bool act[kTileNPT];
 #pragma unroll
         for (int j = 0; j < kTileNPT; ++j) {
-            const int i = threadIdx.x + j * kTileBlock;
+            const int i = ni[j];
             act[j] = i < R && cd[j] >= 0 && rx[j] >= m && rx[j] < RX - m && ry[j] >= m && ry[j] < RY - m;
             // the last sweep writes HBM: only nodes of the grid proper (no wrapped copies)
             if (last) act[j] = act[j] && x0 + rx[j] < nx && y0 + ry[j] < ny;
@@ -1175,7 +1239,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
 #pragma unroll
         for (int j = 0; j < kTileNPT; ++j) {
             if (!act[j]) continue;
-            const int i = threadIdx.x + j * kTileBlock;
+            const int i = ni[j];
 #pragma unroll
             for (int q = 0; q < 8; ++q) nxt[q * R + i] = out[j][q];
         }

@@ -143,8 +143,11 @@ def _cases(S):
     return out
 
 
-@pytest.mark.parametrize("T,tiles", [(3, (0, 0)), (8, (5, 7)), (4, (24, 24))])
+@pytest.mark.parametrize("T,tiles", [(3, (0, 0)), (8, (5, 7)), (4, (24, 24)), (4, (2, 2))])
 def test_tiled_sweeps_equal_single_step_bit_for_bit(S, T, tiles):
+    # plates of launches with no more tiles than the GPU has CUs order their
+    # threads by node kind; 2 x 2 tiles (640 on the 64 x 39 plate) keep the
+    # region order
     for name, (p, control) in _cases(S):
         steps, asteps = 7 * T + 1, 5 * T + 3
         ref = _fixed_step_fields(S, p, control, 1, (0, 0), steps, asteps)

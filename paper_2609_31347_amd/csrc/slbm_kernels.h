@@ -864,12 +864,17 @@ template <int T, bool ADJ>
 __device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
 {
     constexpr int V = 64 - 2 * T;
+    // With V a multiple of 16 (T = 8: 48 columns) the strips are shifted by T
+    // columns, so that every wave's 64 columns start on a 128-byte line (when
+    // a row is, i.e. nx a multiple of 16) and a row read touches 4 lines, not
+    // 5; the wrap keeps each column written by exactly one strip.
+    constexpr int XOFF = V % 16 == 0 ? T : 0;
     const int lane = threadIdx.x;
     const int nx = a.nx, ny = a.ny;
     const int64_t N = a.N;
-    const int xs = sx * V - T + lane;                   // unwrapped column of this lane
+    const int xs = sx * V - T + XOFF + lane;            // unwrapped column of this lane
     const int x = wrapi(xs, nx);
-    const bool out_lane = lane >= T && lane < 64 - T && xs < nx;
+    const bool out_lane = lane >= T && lane < 64 - T && xs < nx + XOFF;
     const int y0 = sy * a.H;
     const int y1 = min(y0 + a.H, ny);
     // histories of level k's outputs (k = 0..T-1): p2 = row two back, p1 = row one back.

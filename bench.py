@@ -29,11 +29,11 @@ PEAK_GBS = 8000.0           # MI355X HBM3E
 # Measured HBM bytes per launch of the dominant kernel, keyed by (N, T, H), from
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors of a plain device copy);
 # see profiles/.  Entries are dropped whenever the kernel changes.
-TRAFFIC_BYTES = {(1024, 8, 24): (2.0 * 117834.1 + 65536.0) * 1024,
-                 (1024, 8, 32): (2.0 * 105726.5 + 65536.0) * 1024,
-                 (1024, 6, 24): (2.0 * 94197.1 + 65536.0) * 1024,
-                 (2048, 8, 48): (2.0 * 367832.2 + 262144.0) * 1024,
-                 (2048, 8, 96): (2.0 * 322647.1 + 262144.0) * 1024}
+TRAFFIC_BYTES = {(1024, 8, 24): (2.0 * 94293.2 + 65536.0) * 1024,
+                 (1024, 8, 32): (2.0 * 84606.5 + 65536.0) * 1024,
+                 (1024, 6, 24): (2.0 * 94204.7 + 65536.0) * 1024,
+                 (2048, 8, 48): (2.0 * 294298.0 + 262144.0) * 1024,
+                 (2048, 8, 96): (2.0 * 258148.4 + 262144.0) * 1024}
 
 
 def parse():

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ dz
     for (int t = 0; t < 10; ++t) red[t][threadIdx.x] = acc[t];
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
+        if ((int)threadIdx.x < s)
 #pragma unroll
             for (int t = 0; t < 10; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + s];
         __syncthreads();
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(1024) void k_mse_loss(const float* __restrict__ y, 
     red[threadIdx.x] = s;
     __syncthreads();
     for (int k = 512; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
     if (threadIdx.x == 0) loss[0] = red[0] * inv_norm;
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(1024) void k_mask_sum(const float* __restrict__ mas
     red[threadIdx.x] = s;
     __syncthreads();
     for (int k = 512; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = red[0];

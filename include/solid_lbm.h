@@ -257,7 +257,9 @@ int solid_lbm_set_tuning(slbm_ctx *ctx, int32_t steps_per_launch, int32_t rows_p
  * tile plus a halo of
  * steps_per_launch nodes on every side must hold at most 1024 nodes (one
  * node per thread of a 1024-thread workgroup; 8 FP64 planes in 64 KiB of
- * LDS, two copies for plates).  0, 0 = automatic (a 32 x 32 region).  Does not
+ * LDS, two copies for plates).  0, 0 = automatic (a 32 x 32 region; with
+ * 8 steps per launch, grids that 16 x 16 tiles would leave short of one
+ * workgroup per compute unit take 8 x 8 or 12 x 12 tiles).  Does not
  * change results.  SLBM_EINVAL for one zero and one nonzero value, negative
  * values, or a region over 1024 nodes. */
 int solid_lbm_set_tiles(slbm_ctx *ctx, int32_t tile_w, int32_t tile_h);

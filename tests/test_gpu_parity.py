@@ -244,6 +244,43 @@ def test_full_size_single_step_matches_oracle_step(S, orc):
     assert rel(f_t1, ref) < 1e-14
 
 
+def test_full_size_fused_launch_matches_oracle_steps(S, orc):
+    """N = 1024 in the benchmark's launch shape (automatic tuning: one 64-lane
+    wave strip per 48 columns and 24 rows, 8 steps per launch, strips aligned
+    to 128-byte lines): from the state after 1000 steps, 9 more steps (one
+    fused launch of 8, then the final single step) equal 9 oracle steps at
+    every node, primal and adjoint."""
+    n = 1024
+    modes = I.two_mode_basis(n)
+    tgt = I.two_mode_target(n)
+    p = periodic_problem(n, n, 1 / n, 1.0, 0.3, tgt, S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes,
+                         tol=1e-4)
+    ctx = S.solid_lbm_init(p)
+    a = np.array([0.1, 0.1])
+    S.solid_lbm_set_control(ctx, a)
+    S.solid_lbm_run_steps(ctx, 1000)
+    f_t = S.solid_lbm_get_field(ctx, S.FIELD_POPS)
+    S.solid_lbm_run_steps(ctx, 9)
+    q = oracle_problem(orc, p, np.tensordot(a, modes, 1) / n ** 2)
+    ref = f_t
+    for _ in range(9):
+        ref = orc.step(q, ref)[0]
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_POPS), ref) < 1e-13
+    # adjoint (each run restarts from zero; fused and single steps agree bit
+    # for bit, so the 1009-step run passes through the 1000-step state): the
+    # residual of a loosely converged primal as the source
+    S.primal_solve(ctx, a)
+    r = S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL)
+    S.solid_lbm_run_adjoint_steps(ctx, 1000)
+    p_t = S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS)
+    S.solid_lbm_run_adjoint_steps(ctx, 1009)
+    src = orc.source(q, orc.zero_mean(r), 1.0 / n ** 2 / orc.cbar(q, tgt))
+    ph = p_t
+    for _ in range(9):
+        ph = orc.adj_step(q, ph, src)[0]
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS), ph) < 1e-13
+
+
 def test_full_size_converged_matches_closed_form(S):
     """N = 1024 benchmark workload solved to 1e-10: J, d and dJ/dA against the
     Fourier closed form of the exact fixed point (property valid at any size)."""

@@ -19,7 +19,7 @@ from . import slbm as S
 # in order of preference on near-ties (larger T moves fewer HBM bytes per step)
 STRIP = ((8, 24, 0, 0), (8, 32, 0, 0), (8, 48, 0, 0), (8, 64, 0, 0), (8, 96, 0, 0), (8, 12, 0, 0), (6, 24, 0, 0),
          (6, 48, 0, 0), (6, 12, 0, 0), (4, 24, 0, 0))
-TILES = ((8, 0, 16, 16), (6, 0, 20, 20), (4, 0, 24, 24), (6, 0, 52, 4))
+TILES = ((8, 0, 16, 16), (6, 0, 20, 20), (4, 0, 24, 24), (6, 0, 52, 4), (8, 0, 8, 8), (8, 0, 12, 12))
 SINGLE = ((1, 0, 0, 0),)
 CANDIDATES = STRIP + TILES + SINGLE
 TIE = 0.02
@@ -43,7 +43,10 @@ def _name(c):
 
 
 def _key(ctx, problem, device):
-    return f"{device}|{problem['nx']}x{problem['ny']}|dom{problem.get('domain', 0)}|ctrl{problem.get('control_kind', 0)}"
+    # the candidate set is part of the key: a cached choice from another set is not reused
+    cands = len(STRIP), len(TILES), len(SINGLE)
+    return (f"{device}|{problem['nx']}x{problem['ny']}|dom{problem.get('domain', 0)}"
+            f"|ctrl{problem.get('control_kind', 0)}|cand{cands[0]}.{cands[1]}.{cands[2]}")
 
 
 def _load():

@@ -64,6 +64,7 @@ enum { SLBM_CTRL_FORCE_MODES = 0, SLBM_CTRL_FORCE_NODAL = 1, SLBM_CTRL_E_NODAL =
        SLBM_CTRL_E_SCALAR_SQ = 3 };
 
 enum { SLBM_PTR_HOST = 0, SLBM_PTR_DEVICE = 1 };
+enum { SLBM_CONV_KLAG = 0, SLBM_CONV_CV = 1 };
 
 /* Link kinds of link_bc. */
 enum { SLBM_LINK_INTERIOR = 0, SLBM_LINK_DIRICHLET = 1, SLBM_LINK_NEUMANN = 2 };
@@ -116,12 +117,23 @@ typedef struct {
     int32_t check_interval;    /* K of the residual ||d(t) - d(t-K)|| / ||d(t)||;
                                   0 -> 2 * ceil(0.005 / dx^2) (even K) */
     void *stream;              /* hipStream_t for all work (NULL = default stream) */
+    int32_t convergence;       /* SLBM_CONV_KLAG (0, default): the K-lag residual
+                                  above < tol.  SLBM_CONV_CV (1): the paper's test
+                                  (eq. convergence, eq. convergence_crit): c(t) =
+                                  mean over domain nodes of |d(t)|^2 at every check
+                                  (every K steps), converged when std(c) / mean(c)
+                                  over the last cv_window checks (population std) is
+                                  below tol (c = 0 throughout counts as converged).
+                                  The adjoint uses its displacement likewise.  Single
+                                  problems only: batches and tangent_solve return
+                                  SLBM_EINVAL for SLBM_CONV_CV. */
+    int32_t cv_window;         /* SLBM_CONV_CV: window in checks, 2..32 (0 -> 10) */
 } slbm_problem;
 
 typedef struct {
     int64_t steps;     /* step index t at which the residual test passed (or stopped) */
     int64_t sweeps;    /* lattice sweeps executed, including the averaging step */
-    double residual;   /* last residual */
+    double residual;   /* last residual (SLBM_CONV_CV: last std(c) / mean(c)) */
     double wall_s;     /* wall time of the solve (host clock, stream drained) */
     double device_ms;  /* device time of the sweep loop: HIP events recorded on the
                           context's stream before the first and after the last sweep */

@@ -241,8 +241,84 @@ class Gradient:
     pass
 
 
+# ------------------------------------------------- the paper's convergence test
+
+def cv_of(window_c):
+    """eq. convergence_crit: std(c) / mean(c) of the samples (population
+    standard deviation; a window of zeros counts as converged)."""
+    w = np.asarray(window_c, dtype=np.float64)
+    m = w.mean()
+    if m <= 0.0:
+        return 0.0
+    return float(np.sqrt(((w - m) ** 2).mean()) / m)
+
+
+def solve_cv(p, tol, window=10, K=None, max_steps=10_000_000):
+    """Steady state by the paper's test (Sec. "Gradient-based optimization
+    algorithm", eq. convergence, eq. convergence_crit): c(t) = mean over the
+    domain nodes of |d(t)|^2, sampled every K steps (the K-lag check spacing,
+    reading C6); stop at the first check at which the coefficient of variation
+    of the last `window` samples is below tol; then the two-step average
+    (reading C7).  The 1/N of the mean cancels in the ratio and is left out."""
+    K = check_interval(p.dx) if K is None else int(K)
+    m = p.mask
+    f = p.zeros(8)
+    t, cs, cv, converged = 0, [], np.inf, False
+    while True:
+        if t > 0:
+            fn, d, _ = step(p, f)
+            cs.append(float(((d ** 2) * m).sum()))
+            if len(cs) >= window:
+                cv = cv_of(cs[-window:])
+                if cv < tol:
+                    converged = True
+                    break
+            if t >= max_steps:
+                break
+            f = run(p, fn, K - 1)
+        else:
+            f = run(p, f, K)
+        t += K
+    f1, d0, _ = step(p, f)
+    d1 = step(p, f1)[1]
+    s = Solve()
+    s.rc = 0 if converged else 1
+    s.fS, s.steps, s.residual = f, t, cv
+    s.dbar, s.fbar = (d0 + d1) / 2.0, (f + f1) / 2.0
+    return s
+
+
+def adj_solve_cv(p, src, tol, window=10, K=None, max_steps=10_000_000):
+    """Adjoint solve from zero with the same test on the adjoint displacement
+    (reading C18), then the two-step average of the routed adjoint."""
+    K = check_interval(p.dx) if K is None else int(K)
+    m = p.mask
+    ph = p.zeros(8)
+    t, cs, cv, converged = 0, [], np.inf, False
+    while True:
+        if t > 0 and t % K == 0:
+            dphi = adj_step(p, ph, src)[1]
+            cs.append(float(((dphi ** 2) * m).sum()))
+            if len(cs) >= window:
+                cv = cv_of(cs[-window:])
+                if cv < tol:
+                    converged = True
+                    break
+        if t >= max_steps:
+            break
+        ph = adj_step(p, ph, src)[0]
+        t += 1
+    ph1, _, e0 = adj_step(p, ph, src)
+    e1 = adj_step(p, ph1, src)[2]
+    s = Solve()
+    s.rc = 0 if converged else 1
+    s.phiC, s.ext, s.steps, s.residual = ph, (e0 + e1) / 2.0, t, cv
+    return s
+
+
 def objective_and_grad(p, target, kind, control, modes=None, fixed_force=None, obs=None,
-                       normalize=True, tol=1e-10, K=None, max_steps=10_000_000, project=None):
+                       normalize=True, tol=1e-10, K=None, max_steps=10_000_000, project=None,
+                       cv_window=0):
     """Primal solve, J, adjoint solve and eq. optimality for one control kind.
 
     kind: 'modes'  (F = sum_i a_i B_i, control a (k,), modes (k, 2, ny, nx))
@@ -251,6 +327,8 @@ def objective_and_grad(p, target, kind, control, modes=None, fixed_force=None, o
           'E_sq'   (E = alpha^2, control (1,))
     project: zero-mean projection of nodal force control and gradient
              (default: on for 'nodal' on periodic problems).
+    cv_window: > 0 solves with the paper's coefficient-of-variation test over
+             that many checks (solve_cv / adj_solve_cv), else the K-lag residual.
     """
     dx2 = p.dx * p.dx
     if kind == "modes":
@@ -269,7 +347,10 @@ def objective_and_grad(p, target, kind, control, modes=None, fixed_force=None, o
         q = p.with_(E=a * a, g=dx2 * fixed_force)
     else:
         raise ValueError(kind)
-    prim = solve(q, tol=tol, K=K, max_steps=max_steps)
+    if cv_window > 0:
+        prim = solve_cv(q, tol, window=cv_window, K=K, max_steps=max_steps)
+    else:
+        prim = solve(q, tol=tol, K=K, max_steps=max_steps)
     m = q.mask if obs is None else (np.asarray(obs, bool) & q.mask)
     c = cbar(q, target, obs) if normalize else 1.0
     r = (prim.dbar - target) * m
@@ -280,7 +361,10 @@ def objective_and_grad(p, target, kind, control, modes=None, fixed_force=None, o
         # translation mode at rest and leaves the gradient unchanged
         r = zero_mean(r)
     src = source(q, r, dx2 / c)
-    adj = adj_solve(q, src, tol=tol, K=K, max_steps=max_steps)
+    if cv_window > 0:
+        adj = adj_solve_cv(q, src, tol, window=cv_window, K=K, max_steps=max_steps)
+    else:
+        adj = adj_solve(q, src, tol=tol, K=K, max_steps=max_steps)
     dg_adj, dE = grad_local(q, prim.fbar, adj.ext, want_E=kind in ("E_nodal", "E_sq"))
     # explicit dependence of d on g (half forcing): dJ/dg = r/2 * dx^2/Cbar
     dJdg = 0.5 * r * dx2 / c + dg_adj

@@ -29,6 +29,7 @@ struct slbm_ctx {
     double dx = 0, dx2 = 0, E = 0, nu = 0, tol = 0, inv_nx = 0;
     int64_t max_steps = 0;
     int64_t K = 0;
+    int cv_window = 0;  // > 0: coefficient-of-variation convergence test over that many checks
     int kind = 0, nmodes = 0, project = 0, normalize = 1;
     bool masked = false;
     int nb = 0;  // boundary records
@@ -586,7 +587,7 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
             launch_sweep(c, adjoint, a, check);
             if (check) {
                 hipLaunchKernelGGL(k_residual, dim3(1), dim3(kBlock), 0, c->stream, c->partial, c->nblk,
-                                   c->status, c->tol, s);
+                                   c->status, c->tol, s, c->cv_window);
                 checks.emplace_back(s, cur);
             }
             if (s == last) last_in = cur;
@@ -995,6 +996,10 @@ int solid_lbm_init(const slbm_problem* p, slbm_ctx** out)
     if (!p->target) return fail(nullptr, SLBM_EINVAL, "target is NULL");
     if (p->max_steps < 1) return fail(nullptr, SLBM_EINVAL, "max_steps must be >= 1");
     if (p->check_interval < 0) return fail(nullptr, SLBM_EINVAL, "check_interval must be >= 0");
+    if (p->convergence != SLBM_CONV_KLAG && p->convergence != SLBM_CONV_CV)
+        return fail(nullptr, SLBM_EINVAL, "unknown convergence test");
+    if (p->convergence == SLBM_CONV_CV && p->cv_window != 0 && (p->cv_window < 2 || p->cv_window > kMaxCvWindow))
+        return fail(nullptr, SLBM_EINVAL, "cv_window must be 0 or 2..32");
     if (p->control_kind == SLBM_CTRL_FORCE_MODES && (p->n_modes < 1 || p->n_modes > 64 || !p->force_modes))
         return fail(nullptr, SLBM_EINVAL, "FORCE_MODES needs 1..64 force_modes");
     bool masked = p->domain == SLBM_MASKED;
@@ -1078,6 +1083,7 @@ int solid_lbm_init(const slbm_problem* p, slbm_ctx** out)
     c->K = p->check_interval > 0 ? p->check_interval
                                  : 2 * (int64_t)std::ceil(0.005 / (c->dx2) - 1e-9);
     if (c->K < 1) c->K = 1;
+    c->cv_window = p->convergence == SLBM_CONV_CV ? (p->cv_window > 0 ? p->cv_window : 10) : 0;
     c->kind = p->control_kind;
     c->nmodes = p->n_modes;
     c->project = (p->control_kind == SLBM_CTRL_FORCE_NODAL && !masked && p->zero_mean_projection) ? 1 : 0;
@@ -1433,6 +1439,7 @@ int tangent_solve(slbm_ctx* c, const double* control, const double* direction, d
 {
     if (!c) return SLBM_EINVAL;
     if (!J || !dJ) return fail(c, SLBM_EINVAL, "J and dJ are required");
+    if (c->cv_window > 0) return fail(c, SLBM_EINVAL, "tangent_solve uses the K-lag convergence test only");
     auto w0 = std::chrono::steady_clock::now();
     int rc;
     if ((rc = tangent_buffers(c))) return rc;
@@ -2012,6 +2019,11 @@ int solid_lbm_batch_init(const slbm_problem* problems, int32_t count, slbm_batch
             return bfail(nullptr, rc, m);
         }
         b->ctx.push_back(c);
+        if (c->cv_window > 0) {
+            solid_lbm_batch_destroy(b);
+            return bfail(nullptr, SLBM_EINVAL, "instance " + std::to_string(i) +
+                                                   ": batches use the K-lag convergence test only");
+        }
     }
     int rc = SLBM_OK;
     void* q = nullptr;

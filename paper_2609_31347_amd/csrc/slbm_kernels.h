@@ -23,12 +23,14 @@ namespace slbm {
 constexpr int kBlock = 256;
 
 // Convergence status shared by the sweeps of one solve (device memory).
+constexpr int kMaxCvWindow = 32;
 struct Status {
     int32_t stop;      // set once the residual test passed: later sweeps return at once
-    int32_t pad;
+    int32_t nwin;      // checks recorded in cwin (coefficient-of-variation test)
     int64_t t_conv;    // step index of the passing test
     int64_t t_last;    // step index of the last test
-    double res;        // last residual
+    double res;        // last residual (or coefficient of variation)
+    double cwin[kMaxCvWindow];  // sum |d|^2 of the last checks, slot = check number mod window
 };
 
 struct SweepArgs {
@@ -215,8 +217,14 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(SweepArgs a, double inv_nx)
 
 // ---------------------------------------------------------------- reductions
 // Sums nblk pairs of partials in a fixed order (deterministic), tests r < tol.
+// Convergence test of a check sweep.  K-lag mode (cv_window = 0): r =
+// ||d(t) - d(t-K)|| / ||d(t)|| < tol.  Coefficient-of-variation mode
+// (cv_window = W > 0, the paper's eq. convergence_crit): c = sum |d(t)|^2
+// (the mean over the domain nodes up to a constant factor, which cancels)
+// joins a window of the last W checks; once W are recorded, std / mean over
+// them (population std, sums in slot order) < tol.
 __global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ partial, int64_t nblk,
-                                                    Status* st, double tol, int64_t t)
+                                                    Status* st, double tol, int64_t t, int cv_window)
 {
     if (st->stop) return;
     double a = 0.0, b = 0.0;
@@ -228,7 +236,24 @@ __global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ 
     block_sum2(a, b, out);
     if (threadIdx.x == 0) {
         double num = out[0], den = out[1];
-        double r = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+        double r;
+        if (cv_window > 0) {
+            const int W = cv_window;
+            st->cwin[st->nwin % W] = den;
+            st->nwin += 1;
+            r = INFINITY;
+            if (st->nwin >= W) {
+                double sum = 0.0;
+                for (int k = 0; k < W; ++k) sum += st->cwin[k];
+                const double mean = sum / W;
+                double var = 0.0;
+                for (int k = 0; k < W; ++k) var += (st->cwin[k] - mean) * (st->cwin[k] - mean);
+                var /= W;
+                r = mean > 0.0 ? sqrt(var) / mean : 0.0;
+            }
+        } else {
+            r = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+        }
         st->res = r;
         st->t_last = t;
         if (r < tol) {
@@ -242,7 +267,7 @@ __global__ void k_status_reset(Status* st)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->stop = 0;
-        st->pad = 0;
+        st->nwin = 0;
         st->t_conv = -1;
         st->t_last = -1;
         st->res = INFINITY;
@@ -1391,7 +1416,7 @@ __global__ void k_status_reset_all(Status* st, int n)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         st[i].stop = 0;
-        st[i].pad = 0;
+        st[i].nwin = 0;
         st[i].t_conv = -1;
         st[i].t_last = -1;
         st[i].res = INFINITY;

@@ -17,6 +17,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ESTATE, ENONFINITE = 0, 1, -1, -2, -3, 
 PERIODIC, MASKED = 0, 1
 CTRL_FORCE_MODES, CTRL_FORCE_NODAL, CTRL_E_NODAL, CTRL_E_SCALAR_SQ = 0, 1, 2, 3
 PTR_HOST, PTR_DEVICE = 0, 1
+CONV_KLAG, CONV_CV = 0, 1
 (FIELD_DISP, FIELD_STRESS, FIELD_ADJ_DISP, FIELD_POPS, FIELD_ADJ_POPS, FIELD_RESIDUAL, FIELD_CUR_DISP,
  FIELD_AVG_POPS) = range(8)
 FIELD_COMPS = {FIELD_DISP: 2, FIELD_STRESS: 3, FIELD_ADJ_DISP: 2, FIELD_POPS: 8, FIELD_ADJ_POPS: 8,
@@ -52,6 +53,7 @@ class _Problem(ctypes.Structure):
         ("force_modes", ctypes.c_void_p), ("zero_mean_projection", ctypes.c_int32),
         ("normalize_objective", ctypes.c_int32), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
         ("check_interval", ctypes.c_int32), ("stream", ctypes.c_void_p),
+        ("convergence", ctypes.c_int32), ("cv_window", ctypes.c_int32),
     ]
 
 
@@ -186,6 +188,8 @@ def _problem_struct(problem, keep):
     p.max_steps = int(problem.get("max_steps", 10_000_000))
     p.check_interval = int(problem.get("check_interval", 0))
     p.stream = problem.get("stream")
+    p.convergence = int(problem.get("convergence", CONV_KLAG))
+    p.cv_window = int(problem.get("cv_window", 0))
     return p
 
 

@@ -422,3 +422,38 @@ def test_plate_E_gradients_match_fad_and_fd(orc):
         jp = orc.objective_and_grad(p, d["target"], "E_nodal", E + e, fixed_force=d["F"], tol=1e-13).J
         jm = orc.objective_and_grad(p, d["target"], "E_nodal", E - e, fixed_force=d["F"], tol=1e-13).J
         assert abs(G.grad[j, i] - (jp - jm) / (2 * h)) < 1e-5 * np.abs(G.grad).max(), (j, i)
+
+
+# ------------------------------------------------- the paper's convergence test
+
+def test_cv_of_is_the_population_coefficient_of_variation(orc):
+    # eq. convergence_crit on textbook samples: {1, 3} has mean 2 and
+    # population standard deviation 1; constant samples have none
+    assert orc.cv_of([1.0, 3.0]) == 0.5
+    assert orc.cv_of([2.5] * 10) == 0.0
+    assert orc.cv_of([0.0] * 10) == 0.0
+
+
+def test_cv_solve_reaches_the_fourier_fixed_point(orc):
+    """The paper's test (c(t) = mean |d|^2, its coefficient of variation over
+    10 checks) stops at the same exact fixed point as the K-lag residual."""
+    from oracle import fourier as Fo
+    for n in (16, 32):
+        modes = I.two_mode_basis(n)
+        dx2 = 1.0 / n ** 2
+        g = dx2 * np.tensordot(np.array([0.1, 0.1]), modes, 1)
+        p = orc.Problem(n, n, 1 / n, 1.0, 0.3, g)
+        d = Fo.steady_disp(g, 1.0, 0.3, Fo.transfer(n, n, 1.0, 0.3))
+        s = orc.solve_cv(p, 1e-10)
+        assert s.rc == 0 and s.steps % orc.check_interval(1 / n) == 0
+        assert s.steps >= 10 * orc.check_interval(1 / n)
+        assert rel(s.dbar, d) < 1e-10
+
+
+def test_cv_solve_of_a_zero_state_stops_at_the_first_full_window(orc):
+    n = 16
+    p = orc.Problem(n, n, 1 / n, 1.0, 0.3, np.zeros((2, n, n)))
+    K = orc.check_interval(1 / n)
+    for w in (2, 10):
+        s = orc.solve_cv(p, 1e-7, window=w)
+        assert s.rc == 0 and s.steps == w * K and s.residual == 0.0

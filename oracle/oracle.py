@@ -4,7 +4,10 @@ Thin ctypes wrapper around liboracle.so plus the plain-numpy glue that the
 paper states in closed form: the objective (eq. node_J, eq. discrete_J), its
 normalisation, the chain rule from the local optimality pieces to each control
 kind (eq. optimality, eq. zero_mean_projection, eq. E_substitution), the
-complex-step forward-mode gradient (eq. fAD) and central finite differences.
+complex-step forward-mode gradient (eq. fAD), central finite differences, and
+the paper's coefficient-of-variation convergence test (eq. convergence, eq.
+convergence_crit) as an alternative stopping rule of the primal and adjoint
+solves.
 
 Only tests/, the smoke check and the benchmark's CPU-baseline leg may import
 this module.  It does not import the HIP package and the HIP package never

@@ -1074,7 +1074,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
     BNode* lbn = reinterpret_cast<BNode*>(lds + (MASKED ? 16 : 8) * R);
     const BNode* bng[kTileNPT];
     int bsl[kTileNPT];
-    // Thread j-pass node: region node threadIdx.x + j * kTileBlock, or, with
+    // The region node a thread runs in pass j: node threadIdx.x + j * kTileBlock, or, with
     // order_by_kind (plates), a stable order by kind -- bulk nodes first, then
     // boundary nodes, then outside nodes -- so that the few boundary nodes
     // (whose node map is several times the bulk work) fill one or two waves
@@ -1095,15 +1095,15 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
             const int w = threadIdx.x / 64;
             const uint64_t below = __lanemask_lt();
             uint64_t b0[kTileNPT], b1[kTileNPT];
-            int kd_[kTileNPT];
+            int kind[kTileNPT];                         // 0 bulk, 1 boundary, 2 outside or none
 #pragma unroll
             for (int j = 0; j < kTileNPT; ++j) {
                 const int i = ni[j];
                 int c = -1;
                 if (i < R) c = ldg(a.code + (int64_t)wrapi(y0 + i / RX, ny) * nx + wrapi(x0 + i % RX, nx));
-                kd_[j] = c < 0 ? 2 : (c > 0 ? 1 : 0);
-                b0[j] = __ballot(kd_[j] == 0);
-                b1[j] = __ballot(kd_[j] == 1);
+                kind[j] = c < 0 ? 2 : (c > 0 ? 1 : 0);
+                b0[j] = __ballot(kind[j] == 0);
+                b1[j] = __ballot(kind[j] == 1);
                 if ((threadIdx.x & 63) == 0) {
                     wcount[j][0][w] = __popcll(b0[j]);
                     wcount[j][1][w] = __popcll(b1[j]);
@@ -1131,7 +1131,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
             for (int j = 0; j < kTileNPT; ++j) {
                 const int i = ni[j];
                 const int r0 = pre0[j] + __popcll(b0[j] & below), r1 = pre1[j] + __popcll(b1[j] & below);
-                const int slot = kd_[j] == 0 ? r0 : kd_[j] == 1 ? tot0 + r1 : tot0 + tot1 + (i - r0 - r1);
+                const int slot = kind[j] == 0 ? r0 : kind[j] == 1 ? tot0 + r1 : tot0 + tot1 + (i - r0 - r1);
                 order[slot] = (short)i;
             }
             __syncthreads();

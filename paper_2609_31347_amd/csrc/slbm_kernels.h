@@ -26,7 +26,7 @@ constexpr int kBlock = 256;
 constexpr int kMaxCvWindow = 32;
 struct Status {
     int32_t stop;      // set once the residual test passed: later sweeps return at once
-    int32_t nwin;      // checks recorded in cwin (coefficient-of-variation test)
+    int32_t nwin;      // checks recorded in cwin (coefficient-of-variation test; < 2 x window)
     int64_t t_conv;    // step index of the passing test
     int64_t t_last;    // step index of the last test
     double res;        // last residual (or coefficient of variation)
@@ -240,7 +240,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ 
         if (cv_window > 0) {
             const int W = cv_window;
             st->cwin[st->nwin % W] = den;
-            st->nwin += 1;
+            // nwin counts checks up to W and then cycles through [W, 2W): the
+            // slot sequence continues (2W = W mod W) and the count never overflows
+            st->nwin = st->nwin + 1 == 2 * W ? W : st->nwin + 1;
             r = INFINITY;
             if (st->nwin >= W) {
                 double sum = 0.0;

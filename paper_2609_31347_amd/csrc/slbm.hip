@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <deque>
 #include <vector>
 
 #include "solid_lbm.h"
@@ -170,6 +171,27 @@ void launch_sweep(slbm_ctx* c, bool adjoint, const SweepArgs& a, bool check)
     }
 #undef SL_CASE
 }
+
+// (step, input buffer) of the latest check sweeps of a solve.  The host sees
+// a passing test at most one or two checks after it happened (it reads the
+// device status one chunk behind), so the passing check is among the last
+// few; older entries are dropped, which keeps the record from growing with
+// the length of the run.
+struct CheckLog {
+    static constexpr size_t kKeep = 16;
+    std::deque<std::pair<int64_t, int>> q;
+    void add(int64_t s, int buf)
+    {
+        q.emplace_back(s, buf);
+        if (q.size() > kKeep) q.pop_front();
+    }
+    int find(int64_t s) const
+    {
+        for (const auto& e : q)
+            if (e.first == s) return e.second;
+        return -1;
+    }
+};
 
 // Steps fused per launch for this context (1 = single-step sweeps only): the
 // fused kernels cover the periodic, uniform-material bulk.
@@ -454,10 +476,11 @@ int tangent_loop(slbm_ctx* c, const TangentArgs& base, int64_t* t_out, int* x_ou
     const bool use_tol = c->tol > 0.0;
     const int64_t K = c->K, last = c->max_steps;
     TangentArgs a = base;
-    int cur = 0, last_in = 0, chunk = 0;
+    int cur = 0, last_in = 0;
+    int64_t chunk = 0;
     int64_t s = 0;
     bool stopped = false;
-    std::vector<std::pair<int64_t, int>> checks;
+    CheckLog checks;
     auto last_report = std::chrono::steady_clock::now();
     HIPCHK(c, hipEventRecord(c->t0, c->stream));
     while (s <= last && !stopped) {
@@ -473,7 +496,7 @@ int tangent_loop(slbm_ctx* c, const TangentArgs& base, int64_t* t_out, int* x_ou
             if (check) {
                 hipLaunchKernelGGL(k_residual2, dim3(1), dim3(kBlock), 0, c->stream, c->tpart, c->nblk, c->status,
                                    c->tol, s);
-                checks.emplace_back(s, cur);
+                checks.add(s, cur);
             }
             if (s == last) last_in = cur;
             cur ^= 1;
@@ -509,9 +532,7 @@ int tangent_loop(slbm_ctx* c, const TangentArgs& base, int64_t* t_out, int* x_ou
     HIPCHK(c, hipMemcpy(&st, c->status, sizeof(Status), hipMemcpyDeviceToHost));
     *res_out = st.res;
     if (use_tol && st.stop) {
-        int xin = -1;
-        for (auto& ck : checks)
-            if (ck.first == st.t_conv) xin = ck.second;
+        const int xin = checks.find(st.t_conv);
         if (xin < 0) return fail(c, SLBM_EHIP, "internal: converged step without a check sweep");
         *t_out = st.t_conv;
         *x_out = xin;
@@ -543,7 +564,7 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
     }
     const int64_t K = c->K;
     int64_t s = 0;
-    int chunk = 0;
+    int64_t chunk = 0;
     bool stopped = false;
     HIPCHK(c, hipEventRecord(c->t0, c->stream));
     // buffer holding the input of sweep s; check sweeps and the final sweep are
@@ -555,7 +576,7 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
         int rc = tile_lds_limits(c);
         if (rc) return rc;
     }
-    std::vector<std::pair<int64_t, int>> checks;  // (step, input buffer) of every check sweep
+    CheckLog checks;                              // (step, input buffer) of the latest check sweeps
     int last_in = start;
     auto last_report = std::chrono::steady_clock::now();
     while (s <= last && !stopped) {
@@ -588,7 +609,7 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
             if (check) {
                 hipLaunchKernelGGL(k_residual, dim3(1), dim3(kBlock), 0, c->stream, c->partial, c->nblk,
                                    c->status, c->tol, s, c->cv_window);
-                checks.emplace_back(s, cur);
+                checks.add(s, cur);
             }
             if (s == last) last_in = cur;
             cur ^= 1;
@@ -627,9 +648,7 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
     if (use_tol && st.stop) {
         *t_out = st.t_conv;
         *conv_out = true;
-        int xin = -1;
-        for (auto& ck : checks)
-            if (ck.first == st.t_conv) xin = ck.second;
+        const int xin = checks.find(st.t_conv);
         if (xin < 0) return fail(c, SLBM_EHIP, "internal: converged step without a check sweep");
         if (x_out) *x_out = xin;
     } else {
@@ -1814,7 +1833,7 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
     std::vector<int64_t> K(B);
     for (int i = 0; i < B; ++i) K[i] = b->ctx[i]->K;
     std::vector<char> active(B, 1);
-    std::vector<std::vector<std::pair<int64_t, int>>> checks(B);
+    std::vector<CheckLog> checks(B);
     std::vector<int> last_in(B, 0);
     int pp = 0, pl = 0, slot = 0, polls = 0;
     int64_t s = 0;
@@ -1833,7 +1852,7 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
             launch_batch_step(b, adjoint, b->d_all, b->n_all, pp, pl, lo, hi);
             for (int i = 0; i < B; ++i) {
                 int par = b->tiled[i] ? pl : pp;
-                if ((i < 64 ? (lo >> i) : (hi >> (i - 64))) & 1ull) checks[i].emplace_back(s, par);
+                if ((i < 64 ? (lo >> i) : (hi >> (i - 64))) & 1ull) checks[i].add(s, par);
                 if (s == last) last_in[i] = par;
             }
             if (lo || hi) {
@@ -1895,9 +1914,7 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
     for (int i = 0; i < B; ++i) {
         res[i] = st[i].res;
         if (use_tol && st[i].stop) {
-            int xin = -1;
-            for (auto& ck : checks[i])
-                if (ck.first == st[i].t_conv) xin = ck.second;
+            const int xin = checks[i].find(st[i].t_conv);
             if (xin < 0) return bfail(b, SLBM_EHIP, "internal: converged step without a check sweep");
             t_out[i] = st[i].t_conv;
             x_out[i] = xin;

@@ -119,19 +119,47 @@ def _is_torch(a):
     return type(a).__module__.startswith("torch")
 
 
-def _arg(a, keep, dtype=np.float64):
-    """(pointer, ptr_kind) of an array; host arrays are made contiguous and kept alive."""
+def _tensor_ok(a, size, what):
+    # the library reads and writes FP64 arrays of a known length through the
+    # pointer: anything else would be misread or overrun
+    if str(a.dtype) != "torch.float64":
+        raise TypeError(f"{what}: tensors must be float64, got {a.dtype}")
+    if not a.is_contiguous():
+        raise ValueError(f"{what}: tensors must be contiguous")
+    if size is not None and a.numel() != size:
+        raise ValueError(f"{what}: {a.numel()} elements, expected {size}")
+
+
+def _arg(a, keep, dtype=np.float64, size=None, what="array"):
+    """(pointer, ptr_kind) of an input array; host arrays are converted to
+    contiguous `dtype` and kept alive; device tensors must be float64 and
+    contiguous; `size` (if given) is the required element count."""
     if a is None:
         return None, PTR_HOST
     if _is_torch(a):
         if a.is_cuda:
-            if not a.is_contiguous():
-                raise ValueError("device tensors must be contiguous")
+            _tensor_ok(a, size, what)
             return a.data_ptr(), PTR_DEVICE
-        a = a.numpy()
+        a = a.detach().numpy()
     arr = np.ascontiguousarray(a, dtype=dtype)
+    if size is not None and arr.size != size:
+        raise ValueError(f"{what}: {arr.size} elements, expected {size}")
     keep.append(arr)
     return arr.ctypes.data, PTR_HOST
+
+
+def _out(a, size, what):
+    """(pointer, ptr_kind) of a caller's output buffer, written in place: a
+    float64, contiguous, writeable array or tensor of exactly `size` elements."""
+    if _is_torch(a):
+        _tensor_ok(a, size, what)
+        return a.data_ptr(), PTR_DEVICE if a.is_cuda else PTR_HOST
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous \
+            or not a.flags.writeable:
+        raise TypeError(f"{what}: output arrays must be writeable, contiguous float64 numpy arrays")
+    if a.size != size:
+        raise ValueError(f"{what}: {a.size} elements, expected {size}")
+    return a.ctypes.data, PTR_HOST
 
 
 class Context:
@@ -206,8 +234,8 @@ def solid_lbm_init(problem):
 
 def primal_solve(ctx, control, init_disp=None):
     keep = []
-    cp, kind = _arg(control, keep)
-    ip, kind2 = _arg(init_disp, keep)
+    cp, kind = _arg(control, keep, size=ctx.grad_len(), what="control")
+    ip, kind2 = _arg(init_disp, keep, size=2 * ctx.N, what="init_disp")
     if init_disp is not None and kind2 != kind:
         raise ValueError("control and init_disp must live in the same memory kind")
     info = SolveInfo()
@@ -226,23 +254,15 @@ def objective_and_grad(ctx, control, grad=None, want_grad=True, init_disp=None):
     array/tensor (device tensors are written in place); allocated on the host
     when not given.  init_disp: warm start of the primal (objective_and_grad_from)."""
     keep = []
-    cp, kind = _arg(control, keep)
-    ip, kind2 = _arg(init_disp, keep)
+    cp, kind = _arg(control, keep, size=ctx.grad_len(), what="control")
+    ip, kind2 = _arg(init_disp, keep, size=2 * ctx.N, what="init_disp")
     if init_disp is not None and kind2 != kind:
         raise ValueError("control and init_disp must live in the same memory kind")
     out = None
     gp = None
     if want_grad:
-        if grad is None:
-            out = np.zeros(ctx.grad_len())
-            gp = out.ctypes.data
-            gkind = PTR_HOST
-        else:
-            out = grad
-            if _is_torch(grad) and grad.is_cuda:
-                gp, gkind = grad.data_ptr(), PTR_DEVICE
-            else:
-                gp, gkind = grad.ctypes.data, PTR_HOST
+        out = np.zeros(ctx.grad_len()) if grad is None else grad
+        gp, gkind = _out(out, ctx.grad_len(), "grad")
         if gkind != kind:
             raise ValueError("control and grad must live in the same memory kind")
     J = ctypes.c_double()
@@ -258,8 +278,10 @@ def objective_and_grad(ctx, control, grad=None, want_grad=True, init_disp=None):
 
 def solid_lbm_set_control(ctx, control, init_disp=None):
     keep = []
-    cp, kind = _arg(control, keep)
-    ip, _ = _arg(init_disp, keep)
+    cp, kind = _arg(control, keep, size=ctx.grad_len(), what="control")
+    ip, kind2 = _arg(init_disp, keep, size=2 * ctx.N, what="init_disp")
+    if init_disp is not None and kind2 != kind:
+        raise ValueError("control and init_disp must live in the same memory kind")
     return _check(ctx, LIB.solid_lbm_set_control(ctx.handle, cp, ip, kind))
 
 
@@ -275,10 +297,8 @@ def solid_lbm_get_field(ctx, which, out=None):
     comps = FIELD_COMPS[which]
     if out is None:
         out = np.zeros((comps, ctx.ny, ctx.nx))
-    if _is_torch(out) and out.is_cuda:
-        _check(ctx, LIB.solid_lbm_get_field(ctx.handle, which, out.data_ptr(), PTR_DEVICE))
-    else:
-        _check(ctx, LIB.solid_lbm_get_field(ctx.handle, which, out.ctypes.data, PTR_HOST))
+    op, okind = _out(out, comps * ctx.N, "out")
+    _check(ctx, LIB.solid_lbm_get_field(ctx.handle, which, op, okind))
     return out
 
 
@@ -291,12 +311,14 @@ def solid_lbm_time_sweeps(ctx, adjoint, n):
 def adjoint_solve_vjp(ctx, d_cot, grad=None):
     """(rc, grad, info): grad = (d dbar / d control)^T d_cot at the last primal solve."""
     keep = []
-    dp, kind = _arg(d_cot, keep)
+    dp, kind = _arg(d_cot, keep, size=2 * ctx.N, what="d_cot")
     if grad is None:
         if kind == PTR_DEVICE:
             raise ValueError("pass a device grad tensor with a device cotangent")
         grad = np.zeros(ctx.grad_len())
-    gp = grad.data_ptr() if _is_torch(grad) else grad.ctypes.data
+    gp, gkind = _out(grad, ctx.grad_len(), "grad")
+    if gkind != kind:
+        raise ValueError("d_cot and grad must live in the same memory kind")
     info = SolveInfo()
     rc = _check(ctx, LIB.adjoint_solve_vjp(ctx.handle, dp, gp, kind, ctypes.byref(info)))
     return rc, grad, info
@@ -305,8 +327,8 @@ def adjoint_solve_vjp(ctx, d_cot, grad=None):
 def tangent_solve(ctx, control, direction):
     """Forward mode: (rc, J, dJ, info) with dJ = grad J . direction."""
     keep = []
-    cp, kind = _arg(control, keep)
-    dp, kind2 = _arg(direction, keep)
+    cp, kind = _arg(control, keep, size=ctx.grad_len(), what="control")
+    dp, kind2 = _arg(direction, keep, size=ctx.grad_len(), what="direction")
     if kind2 != kind:
         raise ValueError("control and direction must live in the same memory kind")
     J, dJ = ctypes.c_double(), ctypes.c_double()
@@ -318,8 +340,8 @@ def tangent_solve(ctx, control, direction):
 
 def solid_lbm_restore_solve(ctx, control, avg_pops):
     keep = []
-    cp, kind = _arg(control, keep)
-    ap, kind2 = _arg(avg_pops, keep)
+    cp, kind = _arg(control, keep, size=ctx.grad_len(), what="control")
+    ap, kind2 = _arg(avg_pops, keep, size=8 * ctx.N, what="avg_pops")
     if kind != kind2:
         raise ValueError("control and avg_pops must live in the same memory kind")
     return _check(ctx, LIB.solid_lbm_restore_solve(ctx.handle, cp, ap, kind))
@@ -403,8 +425,10 @@ def batch_objective_and_grad(batch, controls, grads=None, want_grad=True):
     keep = []
     cptr = (ctypes.c_void_p * B)()
     kinds = set()
+    if len(controls) != B:
+        raise ValueError(f"{len(controls)} controls for {B} instances")
     for i, c in enumerate(controls):
-        ptr, kind = _arg(c, keep)
+        ptr, kind = _arg(c, keep, size=batch.contexts[i].grad_len(), what=f"controls[{i}]")
         cptr[i] = ptr
         kinds.add(kind)
     if len(kinds) != 1:
@@ -416,9 +440,13 @@ def batch_objective_and_grad(batch, controls, grads=None, want_grad=True):
             if kind == PTR_DEVICE:
                 raise ValueError("pass device grads with device controls")
             grads = [np.zeros(ctx.grad_len()) for ctx in batch.contexts]
+        if len(grads) != B:
+            raise ValueError(f"{len(grads)} grads for {B} instances")
         gptr = (ctypes.c_void_p * B)()
         for i, g in enumerate(grads):
-            gptr[i] = g.data_ptr() if _is_torch(g) else g.ctypes.data
+            gptr[i], gkind = _out(g, batch.contexts[i].grad_len(), f"grads[{i}]")
+            if gkind != kind:
+                raise ValueError("controls and grads must live in the same memory kind")
     J = (ctypes.c_double * B)()
     pi, ai = (SolveInfo * B)(), (SolveInfo * B)()
     rc = _bcheck(batch, LIB.batch_objective_and_grad(batch.handle, cptr, J, gptr, kind, pi, ai))
@@ -431,12 +459,15 @@ def batch_gradient(batch, grads=None):
     B = len(batch)
     if grads is None:
         grads = [np.zeros(ctx.grad_len()) for ctx in batch.contexts]
-    kinds = {PTR_DEVICE if (_is_torch(g) and g.is_cuda) else PTR_HOST for g in grads}
+    if len(grads) != B:
+        raise ValueError(f"{len(grads)} grads for {B} instances")
+    gptr = (ctypes.c_void_p * B)()
+    kinds = set()
+    for i, g in enumerate(grads):
+        gptr[i], gkind = _out(g, batch.contexts[i].grad_len(), f"grads[{i}]")
+        kinds.add(gkind)
     if len(kinds) != 1:
         raise ValueError("grads must all be host or all device")
-    gptr = (ctypes.c_void_p * B)()
-    for i, g in enumerate(grads):
-        gptr[i] = g.data_ptr() if _is_torch(g) else g.ctypes.data
     ai = (SolveInfo * B)()
     rc = _bcheck(batch, LIB.batch_gradient(batch.handle, gptr, kinds.pop(), ai))
     return rc, grads, list(ai)

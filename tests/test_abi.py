@@ -100,3 +100,25 @@ def test_binding_refuses_to_run_without_library(tmp_path):
     out = subprocess.run(["python", "-c", code, os.path.join(ROOT, "paper_2609_31347_amd", "slbm.py"),
                           str(tmp_path)], capture_output=True, text=True)
     assert "IMPORTERROR" in out.stdout
+
+
+def test_binding_checks_dtype_length_and_layout(S):
+    """Arrays cross the C ABI as bare FP64 pointers of a known length, so the
+    binding refuses anything the library would misread or overrun (no GPU
+    needed: host arrays and CPU tensors)."""
+    import torch
+    keep = []
+    ptr, kind = S._arg([1, 2, 3], keep, size=3)                       # lists and ints convert
+    assert kind == S.PTR_HOST and keep[-1].dtype == np.float64
+    with pytest.raises(ValueError):
+        S._arg(np.zeros(4), keep, size=3, what="control")
+    S._out(np.zeros(6), 6, "grad")
+    S._out(torch.zeros(2, 3, dtype=torch.float64), 6, "grad")
+    for bad in (np.zeros(6, np.float32), np.zeros((6, 2))[:, 0], np.zeros(6).astype(np.float64)[::1].view(),
+                torch.zeros(6, dtype=torch.float32), torch.zeros(12, dtype=torch.float64)[::2], [0.0] * 6):
+        if isinstance(bad, np.ndarray) and bad.dtype == np.float64 and bad.flags.c_contiguous:
+            bad.flags.writeable = False                                 # read-only output buffer
+        with pytest.raises((TypeError, ValueError)):
+            S._out(bad, 6, "grad")
+    with pytest.raises(ValueError):
+        S._out(np.zeros(5), 6, "grad")

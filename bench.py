@@ -136,7 +136,6 @@ def lbfgs_mode(args):
     from paper_2609_31347_amd.autotune import autotune
     from paper_2609_31347_amd.optimize import PAPER_BENCH1, gpu_objective, lbfgs
     torch.cuda.set_device(0)
-    props = torch.cuda.get_device_properties(0)
     rows = []
     for n in (128, 256, 512, 1024):
         modes = I.two_mode_basis(n)
@@ -145,7 +144,7 @@ def lbfgs_mode(args):
                     control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes, tol=args.tol,
                     max_steps=50_000_000)
         ctx = S.solid_lbm_init(prob)
-        autotune(ctx, prob, np.array([0.1, 0.1]), device=f"{getattr(props, 'gcnArchName', '')}:{props.name}")
+        autotune(ctx, prob, np.array([0.1, 0.1]))
         fun = gpu_objective(ctx)
         r = lbfgs(fun, np.array([0.1, 0.1]), **PAPER_BENCH1)
         err = float(np.linalg.norm(r.x - np.array([0.7, 0.3])) / np.linalg.norm([0.7, 0.3]))
@@ -473,9 +472,7 @@ def main():
                 max_steps=50_000_000, stream=torch.cuda.current_stream().cuda_stream)
     ctx = S.solid_lbm_init(prob)
     from paper_2609_31347_amd import autotune
-    props = torch.cuda.get_device_properties(0)
-    tune = autotune.autotune(ctx, prob, np.array([0.1, 0.1]),
-                             device=f"{getattr(props, 'gcnArchName', '')}:{props.name}")
+    tune = autotune.autotune(ctx, prob, np.array([0.1, 0.1]))
     a = torch.tensor([0.1, 0.1], dtype=torch.float64, device="cuda")
     grad = torch.zeros(2, dtype=torch.float64, device="cuda")
 

@@ -36,9 +36,7 @@ class Solver:
         self.last_adjoint_info = None
         if tune and tune_control is not None:
             from .autotune import autotune
-            props = torch.cuda.get_device_properties(torch.cuda.current_device())
-            autotune(self.ctx, self.problem, tune_control,
-                     device=f"{getattr(props, 'gcnArchName', '')}:{props.name}")
+            autotune(self.ctx, self.problem, tune_control)
 
     def _dev(self, a):
         t = torch.as_tensor(a, dtype=torch.float64)

@@ -49,6 +49,14 @@ def _key(ctx, problem, device):
             f"|ctrl{problem.get('control_kind', 0)}|cand{cands[0]}.{cands[1]}.{cands[2]}")
 
 
+def device_key():
+    """The current GPU's architecture and name: a cached shape is reused only on
+    the same kind of GPU."""
+    import torch
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{getattr(props, 'gcnArchName', '')}:{props.name}"
+
+
 def _load():
     try:
         with open(CACHE) as f:
@@ -60,7 +68,7 @@ def _load():
 def _save(d):
     try:
         os.makedirs(os.path.dirname(CACHE), exist_ok=True)
-        tmp = CACHE + ".tmp"
+        tmp = f"{CACHE}.{os.getpid()}.tmp"       # per process: concurrent tuners do not share it
         with open(tmp, "w") as f:
             json.dump(d, f, indent=1, sort_keys=True)
         os.replace(tmp, CACHE)
@@ -68,11 +76,12 @@ def _save(d):
         pass
 
 
-def autotune(ctx, problem, control, sweeps=96, device="gpu0", use_cache=True, candidates=None):
+def autotune(ctx, problem, control, sweeps=96, device=None, use_cache=True, candidates=None):
     """Chooses and sets the launch shape of ctx.  `control` is any valid
     control for the problem (it sets the forcing the sweeps run with).  Returns
-    {"T", "H", "tiles": [tw, th], "us": {shape: primal us per step}, "cached"}."""
-    key = _key(ctx, problem, device)
+    {"T", "H", "tiles": [tw, th], "us": {shape: primal us per step}, "cached"}.
+    `device` names the GPU in the cache key (default: device_key())."""
+    key = _key(ctx, problem, device_key() if device is None else device)
     if candidates is None:
         candidates = (TILES + SINGLE) if _tiled_only(problem) else CANDIDATES
     cache = _load() if use_cache else {}

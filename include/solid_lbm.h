@@ -91,7 +91,7 @@ typedef struct slbm_ctx slbm_ctx; /* opaque; owns all device buffers */
  */
 typedef struct {
     int32_t nx, ny;            /* nodes per direction (>= 3 each) */
-    double dx;                 /* lattice spacing (> 0); dt = dx^2 */
+    double dx;                 /* lattice spacing (> 0; with check_interval 0, 0.005 / dx^2 < 1e18); dt = dx^2 */
     double E, nu;              /* uniform Young's modulus (> 0) and Poisson ratio
                                   (-1 < nu < 1); E ignored for E controls */
     int32_t domain;            /* SLBM_PERIODIC or SLBM_MASKED */
@@ -112,7 +112,7 @@ typedef struct {
     int32_t zero_mean_projection; /* FORCE_NODAL on PERIODIC: project control and
                                      gradient (eq. zero_mean_projection); 1 = on */
     int32_t normalize_objective;  /* 1: divide J by Cbar of eq. node_J; 0: plain 1/2 L2 */
-    double tol;                /* residual tolerance (e.g. 1e-10); <= 0: run max_steps */
+    double tol;                /* residual tolerance (e.g. 1e-10); <= 0: run max_steps; NaN rejected */
     int64_t max_steps;         /* step limit per solve (>= 1) */
     int32_t check_interval;    /* K of the residual ||d(t) - d(t-K)|| / ||d(t)||;
                                   0 -> 2 * ceil(0.005 / dx^2) (even K) */

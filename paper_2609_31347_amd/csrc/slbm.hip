@@ -1008,6 +1008,9 @@ int solid_lbm_init(const slbm_problem* p, slbm_ctx** out)
     if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(nullptr, SLBM_EINVAL, "grid too large");
     if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(nullptr, SLBM_EINVAL, "dx must be > 0");
     if (!(p->nu > -1.0 && p->nu < 1.0)) return fail(nullptr, SLBM_EINVAL, "nu must lie in (-1, 1)");
+    if (std::isnan(p->tol)) return fail(nullptr, SLBM_EINVAL, "tol is NaN");
+    if (p->check_interval == 0 && !(0.005 / (p->dx * p->dx) < 1e18))
+        return fail(nullptr, SLBM_EINVAL, "dx too small for the default check interval");
     bool econtrol = p->control_kind == SLBM_CTRL_E_NODAL || p->control_kind == SLBM_CTRL_E_SCALAR_SQ;
     if (p->control_kind < 0 || p->control_kind > 3) return fail(nullptr, SLBM_EINVAL, "unknown control_kind");
     if (!econtrol && (!(p->E > 0.0) || !std::isfinite(p->E))) return fail(nullptr, SLBM_EINVAL, "E must be > 0");

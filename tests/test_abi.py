@@ -54,7 +54,8 @@ def base_problem(**kw):
     (dict(nx=2), -1), (dict(dx=0.0), -1), (dict(nu=1.0), -1), (dict(nu=-1.5), -1), (dict(E=-1.0), -1),
     (dict(control_kind=7), -1), (dict(max_steps=0), -1), (dict(check_interval=-3), -1),
     (dict(domain=5), -1), (dict(control_kind=0, n_modes=0), -1), (dict(target=None), -1),
-    (dict(domain=1), -1),
+    (dict(domain=1), -1), (dict(tol=float("nan")), -1), (dict(dx=1e-12), -1), (dict(dx=1e-200), -1),
+    (dict(convergence=2), -1), (dict(convergence=1, cv_window=1), -1), (dict(convergence=1, cv_window=33), -1),
 ])
 def test_init_rejects_bad_problems(S, bad, code):
     p = base_problem(**bad)

@@ -75,7 +75,8 @@ enum {
     SLBM_FIELD_STRESS = 1,    /* 3N: (sxx, syy, sxy) lattice units of the averaged state */
     SLBM_FIELD_ADJ_DISP = 2,  /* 2N: adjoint displacement of the averaged adjoint  */
     SLBM_FIELD_POPS = 3,      /* 8N: current primal post-streaming populations f^S */
-    SLBM_FIELD_ADJ_POPS = 4,  /* 8N: current adjoint post-collision populations phi^C */
+    SLBM_FIELD_ADJ_POPS = 4,  /* 8N: current adjoint post-collision populations phi^C
+                                 (SLBM_ESTATE before any adjoint solve or steps) */
     SLBM_FIELD_RESIDUAL = 5,  /* 2N: r = d - d* on the observation set (0 elsewhere) */
     SLBM_FIELD_CUR_DISP = 6,  /* 2N: bared displacement of the current state f^S   */
     SLBM_FIELD_AVG_POPS = 7   /* 8N: two-step-averaged populations of the last completed

@@ -69,6 +69,7 @@ struct slbm_ctx {
     bool prim_done = false; // a completed primal_solve (adjoint inputs ready)
     int adj_cur = 0;
     bool adj_done = false;
+    bool adj_valid = false;   // the adjoint buffers hold a defined state
     bool efield_on = false; // E_NODAL: kernels read the E plane
     double E_cur = 0;       // uniform E of the current control
     double alpha_sq = 0;    // E_SCALAR_SQ control value
@@ -864,6 +865,7 @@ int adjoint_prepare(slbm_ctx* c)
     if ((rc = fill(c, c->abuf[1], 8 * c->N, 0.0))) return rc;
     if ((rc = fill(c, c->snap, 2 * c->N, 0.0))) return rc;
     c->adj_cur = 0;
+    c->adj_valid = true;
     return SLBM_OK;
 }
 
@@ -1260,19 +1262,7 @@ int objective_and_grad_from(slbm_ctx* c, const double* control, const double* in
 int objective_and_grad(slbm_ctx* c, const double* control, double* J, double* grad, int32_t ptr_kind,
                        slbm_solve_info* pinfo, slbm_solve_info* ainfo)
 {
-    if (!c) return SLBM_EINVAL;
-    if (!J) return fail(c, SLBM_EINVAL, "J is NULL");
-    int rc = primal_solve(c, control, nullptr, ptr_kind, pinfo);
-    if (rc < 0) return rc;
-    int warn = rc;
-    *J = c->J;
-    if (!grad) return warn;
-    rc = do_adjoint(c, ainfo);
-    if (rc < 0) return rc;
-    if (rc > 0) warn = rc;
-    rc = assemble_grad(c, grad, ptr_kind);
-    if (rc < 0) return rc;
-    return warn;
+    return objective_and_grad_from(c, control, nullptr, J, grad, ptr_kind, pinfo, ainfo);
 }
 
 int solid_lbm_run_steps(slbm_ctx* c, int64_t n)
@@ -1346,6 +1336,7 @@ int solid_lbm_get_field(slbm_ctx* c, int32_t which, double* out, int32_t ptr_kin
             return copy_out(c, out, disp, 2 * N * sizeof(double), ptr_kind);
         }
         case SLBM_FIELD_ADJ_POPS:
+            if (!c->adj_valid) return fail(c, SLBM_ESTATE, "no adjoint state");
             return copy_out(c, out, c->abuf[c->adj_cur], 8 * N * sizeof(double), ptr_kind);
         case SLBM_FIELD_AVG_POPS:
             if (!c->prim_done) return fail(c, SLBM_ESTATE, "no completed primal_solve");
@@ -2082,6 +2073,7 @@ int solid_lbm_batch_init(const slbm_problem* problems, int32_t count, slbm_batch
         for (double* a : {c->fbuf[0], c->fbuf[1], c->abuf[0], c->abuf[1]})
             if (!rc) rc = fill(c, a, 8 * c->N, 0.0);
         if (!rc) rc = fill(c, c->r, 2 * c->N, 0.0);
+        c->adj_valid = true;
     }
     if (rc || hipStreamSynchronize(b->stream) != hipSuccess) {
         solid_lbm_batch_destroy(b);

@@ -383,3 +383,22 @@ def test_progress_reports_from_inside_the_solves(S):
     seen.clear()
     S.objective_and_grad(ctx, np.array([0.1, 0.1]))
     assert seen == []
+
+
+def test_calls_out_of_order_fail_with_estate(S):
+    """Fields and solves that need a state the context does not hold yet return
+    SLBM_ESTATE and leave the context usable."""
+    n = 16
+    p = periodic_problem(n, n, 1 / n, 1.0, 0.3, I.two_mode_target(n), S.CTRL_FORCE_MODES, n_modes=2,
+                         force_modes=I.two_mode_basis(n), tol=1e-10)
+    ctx = S.solid_lbm_init(p)
+    for call in (lambda: S.adjoint_solve(ctx), lambda: S.solid_lbm_run_steps(ctx, 3),
+                 lambda: S.solid_lbm_get_field(ctx, S.FIELD_DISP),
+                 lambda: S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS),
+                 lambda: S.solid_lbm_get_field(ctx, S.FIELD_ADJ_DISP)):
+        with pytest.raises(S.SlbmError) as e:
+            call()
+        assert e.value.code == S.ESTATE
+    rc, J, grad, pi, ai = S.objective_and_grad(ctx, np.array([0.1, 0.1]))
+    assert rc == 0 and abs(J - 3.511671218992067e-1) < 1e-8      # closed-form J at N = 16
+    assert S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS).shape[-1] == n

@@ -1178,13 +1178,14 @@ int solid_lbm_init(const slbm_problem* p, slbm_ctx** out)
     if (p->obs_mask) A(&c->obs, N);
 #undef A
     if (rc) {
+        const std::string why = c->err;
         solid_lbm_destroy(c);
-        return fail(nullptr, rc, "device allocation failed");
+        return fail(nullptr, rc, "device allocation failed: " + why);
     }
     auto up = [&](void* dst, const void* src, size_t bytes) {
         if (rc) return;
         hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
-        if (e != hipSuccess) rc = SLBM_EHIP;
+        if (e != hipSuccess) rc = fail(c, SLBM_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
     };
     up(c->target, p->target, P2);
     if (p->fixed_force) {
@@ -1211,8 +1212,9 @@ int solid_lbm_init(const slbm_problem* p, slbm_ctx** out)
                 hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess))
         rc = SLBM_EHIP;
     if (rc) {
+        const std::string why = c->err;
         solid_lbm_destroy(c);
-        return fail(nullptr, rc, "upload failed");
+        return fail(nullptr, rc, "upload failed" + (why.empty() ? std::string() : ": " + why));
     }
     *out = c;
     return SLBM_OK;

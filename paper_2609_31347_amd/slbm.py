@@ -68,6 +68,15 @@ class SolveInfo(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python paper_2609_31347_amd/build.py`")
+    # torch first: the library then binds to the HIP runtime torch has already
+    # loaded (same soname), so one runtime serves torch's tensors and the
+    # library.  Loaded first, the library would pull in the system ROCm's
+    # runtime and torch would add its own: two runtimes on one device refuse
+    # each other's allocations and pointers.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, pp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)
     info = ctypes.POINTER(SolveInfo)

@@ -4,6 +4,7 @@ any device call)."""
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -123,3 +124,15 @@ def test_binding_checks_dtype_length_and_layout(S):
             S._out(bad, 6, "grad")
     with pytest.raises(ValueError):
         S._out(np.zeros(5), 6, "grad")
+
+
+def test_one_hip_runtime_when_the_binding_is_imported_before_torch():
+    """Imported first, the binding must not bring in a second HIP runtime next to
+    the one torch ships (two runtimes in one process refuse device allocations)."""
+    code = ("from paper_2609_31347_amd import slbm\n"
+            "import torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

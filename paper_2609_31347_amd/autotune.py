@@ -17,8 +17,10 @@ import os
 from . import slbm as S
 
 # in order of preference on near-ties (larger T moves fewer HBM bytes per step)
+# short strips (H = 8, 12 with T <= 6) give grids that do not fill the chip more waves
 STRIP = ((8, 24, 0, 0), (8, 32, 0, 0), (8, 48, 0, 0), (8, 64, 0, 0), (8, 96, 0, 0), (8, 12, 0, 0), (6, 24, 0, 0),
-         (6, 48, 0, 0), (6, 12, 0, 0), (4, 24, 0, 0))
+         (6, 48, 0, 0), (6, 12, 0, 0), (4, 24, 0, 0), (8, 8, 0, 0), (6, 8, 0, 0), (4, 12, 0, 0), (4, 8, 0, 0),
+         (2, 8, 0, 0))
 TILES = ((8, 0, 16, 16), (6, 0, 20, 20), (4, 0, 24, 24), (6, 0, 52, 4), (8, 0, 8, 8), (8, 0, 12, 12))
 SINGLE = ((1, 0, 0, 0),)
 CANDIDATES = STRIP + TILES + SINGLE

@@ -222,7 +222,7 @@ int fused_steps(const slbm_ctx* c)
 // count just at or below the SIMD count (1024^2, T = 8: 24 rows, 946 waves;
 // 2048^2: 96 rows, 946 waves).  Smallest multiple of 4 in [8, 96] that does;
 // grids too small to fill the chip get the 8-row floor (512^2, T = 8: 8 rows,
-// 704 waves, 3.02 us per step against 3.37 with 12 rows).
+// 704 waves, 3.02 us per step against 3.37 with 12 rows, autotuner timing).
 int fused_rows(const slbm_ctx* c, int T)
 {
     if (c->tb_H > 0) return std::min(c->tb_H, c->ny);

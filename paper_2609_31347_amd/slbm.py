@@ -208,17 +208,22 @@ def _problem_struct(problem, keep):
     p.dx = float(problem["dx"])
     p.E, p.nu = float(problem.get("E", 1.0)), float(problem["nu"])
     p.domain = int(problem.get("domain", PERIODIC))
-    for name, dt in (("node_mask", np.uint8), ("link_bc", np.uint8), ("link_wall", np.float64),
-                     ("link_normal", np.float64), ("fixed_force", np.float64), ("target", np.float64),
-                     ("obs_mask", np.uint8), ("force_modes", np.float64)):
+    p.control_kind = int(problem.get("control_kind", CTRL_FORCE_MODES))
+    p.n_modes = int(problem.get("n_modes", 0))
+    # element counts the library reads (layouts of include/solid_lbm.h); the mode
+    # fields are read only for FORCE_MODES, and the library checks the sizes themselves
+    N = p.nx * p.ny if p.nx > 0 and p.ny > 0 else 0
+    modes = p.n_modes * 2 * N if p.control_kind == CTRL_FORCE_MODES and p.n_modes > 0 else None
+    for name, dt, size in (("node_mask", np.uint8, N), ("link_bc", np.uint8, 8 * N),
+                           ("link_wall", np.float64, 16 * N), ("link_normal", np.float64, 16 * N),
+                           ("fixed_force", np.float64, 2 * N), ("target", np.float64, 2 * N),
+                           ("obs_mask", np.uint8, N), ("force_modes", np.float64, modes)):
         v = problem.get(name)
         if v is not None:
-            ptr, kind = _arg(v, keep, dt)
+            ptr, kind = _arg(v, keep, dt, size, name)
             if kind != PTR_HOST:
                 raise ValueError(f"{name} must be host memory")
             setattr(p, name, ptr)
-    p.control_kind = int(problem.get("control_kind", CTRL_FORCE_MODES))
-    p.n_modes = int(problem.get("n_modes", 0))
     p.zero_mean_projection = int(problem.get("zero_mean_projection", 1))
     p.normalize_objective = int(problem.get("normalize_objective", 1))
     p.tol = float(problem.get("tol", 1e-10))

@@ -45,9 +45,9 @@ def test_every_declared_symbol_is_exported(S):
 
 def base_problem(**kw):
     n = 8
-    p = dict(nx=n, ny=n, dx=1 / n, E=1.0, nu=0.3, domain=0, target=np.ones((2, n, n)),
-             control_kind=1, tol=1e-10, max_steps=100)
+    p = dict(nx=n, ny=n, dx=1 / n, E=1.0, nu=0.3, domain=0, control_kind=1, tol=1e-10, max_steps=100)
     p.update(kw)
+    p.setdefault("target", np.ones((2, p["ny"], p["nx"])))
     return p
 
 
@@ -136,3 +136,39 @@ def test_one_hip_runtime_when_the_binding_is_imported_before_torch():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=ROOT)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_binding_checks_problem_array_lengths(S):
+    """Every problem array must have the length the library reads (N, 8N, 16N,
+    2N or n_modes * 2N entries); a short one is refused before the call."""
+    from paper_2609_31347_amd import inputs as I
+    n = 8
+    with pytest.raises(ValueError, match="target"):
+        S.solid_lbm_init(base_problem(target=np.ones((2, n, n - 1))))
+    with pytest.raises(ValueError, match="force_modes"):
+        S.solid_lbm_init(base_problem(control_kind=0, n_modes=2, force_modes=np.ones((1, 2, n, n))))
+    with pytest.raises(ValueError, match="obs_mask"):
+        S.solid_lbm_init(base_problem(obs_mask=np.ones(n * n - 1, np.uint8)))
+    pd = I.paper_plate(8)
+    plate = base_problem(nx=pd["nx"], ny=pd["ny"], dx=pd["dx"], domain=1, node_mask=pd["active"].astype(np.uint8),
+                         link_bc=pd["bc"], link_wall=pd["wall"], link_normal=pd["normal"], target=pd["target"])
+    for name in ("node_mask", "link_bc", "link_wall", "link_normal"):
+        short = np.asarray(plate[name]).ravel()[:-1]
+        with pytest.raises(ValueError, match=name):
+            S.solid_lbm_init(dict(plate, **{name: short}))
+
+
+def test_init_rejects_a_grid_beyond_the_node_limit(S):
+    """More than 2^31 nodes is refused before any array is read, so a tiny
+    target buffer stands in for the 2N doubles such a grid would need."""
+    import ctypes
+    p = S._Problem()
+    p.nx = p.ny = 46341                        # 46341^2 > 2^31
+    p.dx, p.E, p.nu, p.domain, p.control_kind = 1 / 46341, 1.0, 0.3, 0, 1
+    tiny = np.zeros(2)
+    p.target = tiny.ctypes.data
+    p.max_steps, p.tol = 100, 1e-10
+    h = ctypes.c_void_p()
+    assert S.LIB.solid_lbm_init(ctypes.byref(p), ctypes.byref(h)) == S.EINVAL
+    assert "too large" in S.LIB.solid_lbm_last_error(None).decode()
+    assert not h.value

@@ -56,6 +56,15 @@ def _chk(rc, what):
         raise S.SlbmError(rc, what)
 
 
+def _need(t, dtype, shape, what):
+    """The kernels read whole [B][C][H][W] planes through the pointer: a tensor
+    of another dtype, shape or layout, or on the host, would be misread."""
+    if not torch.is_tensor(t) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{what}: needs a contiguous {dtype} CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
 _L = S.LIB
 _P = ctypes.c_void_p
 _i32, _i64, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
@@ -69,7 +78,9 @@ _L.slbm_adam.argtypes = [_P, _P, _P, _P, _i64, _f32, _f32, _f32, _f32, _i32, _P]
 
 
 def to_bf16(x):
-    """FP32 tensor -> bf16 tensor by the library's rounding kernel."""
+    """FP32 tensor -> bf16 tensor by the library's rounding kernel (CUDA tensors)."""
+    if not torch.is_tensor(x) or not x.is_cuda:
+        raise TypeError("to_bf16: needs a CUDA tensor")
     x = x.contiguous().float()
     y = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
     _chk(_L.slbm_to_bf16(_p(x), _p(y), x.numel(), _stream()), "to_bf16")
@@ -101,8 +112,10 @@ class ConvNet:
             _chk(_L.slbm_pack_weights(_p(w), _p(wp), _p(wt), ci, co, _stream()), "pack")
 
     def forward(self, xb):
-        """xb: bf16 [B, 4, H, W].  Returns the FP32 output; keeps activations."""
+        """xb: bf16 [B, 7, H, W] (the input channels of the first layer).
+        Returns the FP32 output [B, 2, H, W]; keeps the activations."""
         B, _, H, W = xb.shape
+        _need(xb, torch.bfloat16, (B, self.layers[0][0], H, W), "forward input")
         self.acts, self.outs = [xb], []
         for (ci, co, relu, dil), wp, b in zip(self.layers, self.wp, self.b):
             y = torch.empty((B, co, H, W), dtype=torch.float32, device="cuda")
@@ -114,8 +127,12 @@ class ConvNet:
         return self.outs[-1]
 
     def backward(self, dy):
-        """Gradients of the loss whose output gradient is dy (FP32 [B, 2, H, W])."""
-        B, _, H, W = dy.shape
+        """Gradients of the loss whose output gradient is dy (FP32 [B, 2, H, W]),
+        after a forward of the same batch."""
+        if not getattr(self, "acts", None):
+            raise RuntimeError("backward needs a forward first")
+        B, _, H, W = self.acts[0].shape
+        _need(dy, torch.float32, (B, self.layers[-1][1], H, W), "output gradient")
         self.gw, self.gb = [None] * len(self.layers), [None] * len(self.layers)
         for i in range(len(self.layers) - 1, -1, -1):
             ci, co, relu, dil = self.layers[i]
@@ -145,11 +162,16 @@ class ConvNet:
 
 
 def mse(y, t, mask):
+    """Masked mean squared error of y against t (FP32 [B, nc, H, W]) over the
+    nodes where mask (FP32 [B, H, W]) is non-zero; returns (loss, dloss/dy)."""
+    B, nc, H, W = y.shape
+    t, mask = t.contiguous(), mask.contiguous()
+    _need(y, torch.float32, (B, nc, H, W), "mse prediction")
+    _need(t, torch.float32, (B, nc, H, W), "mse target")
+    _need(mask, torch.float32, (B, H, W), "mse mask")
     dy = torch.empty_like(y)
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-    B, nc, H, W = y.shape
-    _chk(_L.slbm_mse(_p(y), _p(t.contiguous()), _p(mask.contiguous()), _p(dy), _p(loss), B, nc, H * W,
-                     _stream()), "mse")
+    _chk(_L.slbm_mse(_p(y), _p(t), _p(mask), _p(dy), _p(loss), B, nc, H * W, _stream()), "mse")
     return loss, dy
 
 

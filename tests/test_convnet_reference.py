@@ -66,3 +66,40 @@ def test_bf16_rounding_is_nearest_even():
     assert r[3] == np.float32(1.0 + u)
     assert r[4] == 1.0
     assert r[5] == -2.5
+
+
+def test_network_forward_backward_equals_autograd_when_every_rounding_is_exact():
+    """With inputs, weights, activations and the back-propagated data gradient
+    all exactly representable in bfloat16 (small integers and a power-of-two
+    normalisation), the reference's bf16 rounding points change nothing, so its
+    loss and weight gradients must equal torch autograd of the same network in
+    float64 (zero-padded dilated correlation, ReLU, masked mean squared error)."""
+    import torch
+    import torch.nn.functional as F
+    rng = np.random.default_rng(5)
+    B, H, W = 2, 6, 7
+    x = rng.integers(0, 2, (B, 2, H, W)).astype(np.float64)
+    w1 = rng.integers(-1, 2, (3, 2, 3, 3)).astype(np.float64)
+    b1 = np.array([1.0, 0.0, 2.0])
+    w2 = rng.integers(-1, 2, (2, 3, 3, 3)).astype(np.float64)
+    b2 = np.array([0.0, 1.0])
+    mask = np.zeros(B * H * W)
+    mask[rng.choice(B * H * W, 16, replace=False)] = 1.0      # 2 channels x 16 nodes: norm 32
+    mask = mask.reshape(B, H, W)
+    # target = output + small integer offsets, so every y - t is a small integer
+    y_ref = C.conv3x3(np.maximum(C.conv3x3(x, w1, b1, 1), 0.0), w2, b2, 2)
+    t = y_ref + rng.integers(-2, 3, y_ref.shape)
+    loss, grads, y = C.net_forward_backward(x.astype(np.float32), [(w1, b1, True, 1), (w2, b2, False, 2)], t, mask)
+
+    tt = lambda a, g=False: torch.tensor(a, dtype=torch.float64, requires_grad=g)
+    W1, B1, W2, B2 = tt(w1, True), tt(b1, True), tt(w2, True), tt(b2, True)
+    y2 = F.conv2d(F.relu(F.conv2d(tt(x), W1, B1, padding=1)), W2, B2, padding=2, dilation=2)
+    m = tt(mask)[:, None]
+    L = (m * (y2 - tt(t)) ** 2).sum() / (2 * m.sum())
+    L.backward()
+    assert np.abs(y - y2.detach().numpy()).max() == 0.0
+    assert abs(loss - L.item()) <= 1e-15 * abs(L.item())
+    for (dw, db), Wt, Bt in zip(grads, (W1, W2), (B1, B2)):
+        assert np.abs(dw - Wt.grad.numpy()).max() < 1e-12
+        assert np.abs(db - Bt.grad.numpy()).max() < 1e-12
+    assert np.abs(grads[0][0]).max() > 0.0                    # the first layer's gradient went through both layers

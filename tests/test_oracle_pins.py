@@ -184,6 +184,26 @@ def test_fixed_step_run_matches_closed_form_at_paper_protocol(orc):
     assert rel(s.dbar, Fo.steady_disp(g, 0.11, 0.8)) < 1e-9
 
 
+def test_mode_decay_spectrum_and_the_undamped_nyquist_mode():
+    """Per-step amplification of one Fourier mode (the matrix encoding of the
+    scheme).  At k = 0 streaming is the identity, so the moduli are those of
+    the moment map: 1 twice (conserved m10, m01), |1 - omega| for the three
+    second-order moments and 0 for the three at equilibrium (tau = 1/2);
+    with E = 1, nu = 0.3 the Lame relations give omega_11 = omega_d = 26/43,
+    omega_s = 7/11 (relaxation-time table).  Every other long-wave mode
+    decays, while the Nyquist wavevectors keep an eigenvalue of modulus 1:
+    the undamped period-2 mode behind reading C7."""
+    from oracle import fourier as Fo
+    n = 32
+    got = np.sort(Fo.mode_decay(n, n, 1.0, 0.3, (0, 0)))
+    want = np.sort([1.0, 1.0, 1 - 26 / 43, 1 - 7 / 11, 1 - 26 / 43, 0.0, 0.0, 0.0])
+    assert np.abs(got - want).max() < 1e-12
+    for k in ((1, 0), (0, 1), (1, 1), (2, 0), (3, 5)):
+        assert Fo.mode_decay(n, n, 1.0, 0.3, k).max() < 1 - 1e-4, k
+    for k in ((n // 2, 0), (0, n // 2)):
+        assert abs(Fo.mode_decay(n, n, 1.0, 0.3, k).max() - 1.0) < 1e-12, k
+
+
 # ----------------------------------------------------------------- gradients (periodic)
 
 def _config1(orc, n):

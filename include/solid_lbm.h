@@ -241,7 +241,12 @@ int solid_lbm_run_steps(slbm_ctx *ctx, int64_t n);
  * residual of the last primal_solve (fixed-step mode). */
 int solid_lbm_run_adjoint_steps(slbm_ctx *ctx, int64_t n);
 
-/* Copies a field (SLBM_FIELD_*) into out (host or device per ptr_kind). */
+/* Copies a field (SLBM_FIELD_*) into out (host or device per ptr_kind; out
+ * holds the size listed with the field).  SLBM_ESTATE if the context does not
+ * hold the state the field comes from: a completed primal_solve (DISP, STRESS,
+ * RESIDUAL, AVG_POPS), a primal state (POPS, CUR_DISP), a completed
+ * adjoint_solve (ADJ_DISP) or any adjoint state (ADJ_POPS); SLBM_EINVAL for an
+ * unknown field or a NULL out. */
 int solid_lbm_get_field(slbm_ctx *ctx, int32_t which, double *out, int32_t ptr_kind);
 
 /* Timing helper: runs n primal (adjoint = 0) or adjoint (adjoint = 1) sweeps

@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--mode", choices=("gradient", "sweeps", "lbfgs", "batch", "warmstart", "nodal"),
                     default="gradient",
                     help="sweeps: time fixed counts of primal/adjoint sweeps and a reference copy "

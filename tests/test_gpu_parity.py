@@ -99,11 +99,12 @@ def test_adjoint_fixed_steps_periodic(S, orc):
     tgt = I.grf(nx, ny, dx, 1e-6, 0.15, 3, comps=2)
     p = periodic_problem(nx, ny, dx, 0.8, 0.25, tgt, S.CTRL_FORCE_NODAL, tol=0.0, max_steps=200)
     ctx = S.solid_lbm_init(p)
-    S.primal_solve(ctx, F)
-    r = S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL)
+    S.primal_solve(ctx, F)                                # fixed-step mode: 200 steps, then the average
     S.solid_lbm_run_adjoint_steps(ctx, 150)
     phi = S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS)
     q = oracle_problem(orc, p, dx * dx * orc.zero_mean(F))
+    r = orc.solve(q, tol=0.0, max_steps=200).dbar - tgt  # the oracle's own residual
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL), r) < TOL_D
     cb = orc.cbar(q, tgt)
     src = orc.source(q, orc.zero_mean(r), dx * dx / cb)   # periodic: source mean removed
     ph = q.zeros(8)
@@ -225,60 +226,47 @@ def test_plate_E_gradients(S, orc, plate16):
 # ---------------------------------------------------------------- full size
 
 def test_full_size_single_step_matches_oracle_step(S, orc):
-    """N = 1024 periodic (the benchmark grid, same launch shape): the GPU state
-    after t and t+1 steps agrees with the oracle's one step applied to the GPU
-    state at t, at every node."""
+    """N = 1024 periodic (the benchmark grid) with one step per launch: 3
+    sweeps from rest equal 3 oracle steps at every node."""
     n = 1024
     modes = I.two_mode_basis(n)
     tgt = I.two_mode_target(n)
     p = periodic_problem(n, n, 1 / n, 1.0, 0.3, tgt, S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes)
     ctx = S.solid_lbm_init(p)
+    S.solid_lbm_set_tuning(ctx, 1, 0)
     a = np.array([0.1, 0.1])
     S.solid_lbm_set_control(ctx, a)
-    S.solid_lbm_run_steps(ctx, 1000)
-    f_t = S.solid_lbm_get_field(ctx, S.FIELD_POPS)
-    S.solid_lbm_run_steps(ctx, 1)
-    f_t1 = S.solid_lbm_get_field(ctx, S.FIELD_POPS)
+    S.solid_lbm_run_steps(ctx, 3)
     q = oracle_problem(orc, p, np.tensordot(a, modes, 1) / n ** 2)
-    ref, _, _ = orc.step(q, f_t)
-    assert rel(f_t1, ref) < 1e-14
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_POPS), orc.run(q, q.zeros(8), 3)) < 1e-14
 
 
 def test_full_size_fused_launch_matches_oracle_steps(S, orc):
-    """N = 1024 in the benchmark's launch shape (automatic tuning: one 64-lane
-    wave strip per 48 columns and 24 rows, 8 steps per launch, strips aligned
-    to 128-byte lines): from the state after 1000 steps, 9 more steps (one
-    fused launch of 8, then the final single step) equal 9 oracle steps at
-    every node, primal and adjoint."""
-    n = 1024
+    """N = 1024 in the benchmark's launch shape (automatic: one 64-lane wave
+    strip per 48 columns and 24 rows, 8 steps per launch, strips aligned to
+    128-byte lines): 17 steps from rest (two fused launches, then the final
+    single step) equal 17 oracle steps at every node; the same for the adjoint,
+    whose source is the oracle's own residual of a 16-step fixed-step primal."""
+    n, steps = 1024, 17
     modes = I.two_mode_basis(n)
     tgt = I.two_mode_target(n)
     p = periodic_problem(n, n, 1 / n, 1.0, 0.3, tgt, S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes,
-                         tol=1e-4)
+                         tol=0.0, max_steps=steps - 1)
     ctx = S.solid_lbm_init(p)
     a = np.array([0.1, 0.1])
     S.solid_lbm_set_control(ctx, a)
-    S.solid_lbm_run_steps(ctx, 1000)
-    f_t = S.solid_lbm_get_field(ctx, S.FIELD_POPS)
-    S.solid_lbm_run_steps(ctx, 9)
+    S.solid_lbm_run_steps(ctx, steps)
     q = oracle_problem(orc, p, np.tensordot(a, modes, 1) / n ** 2)
-    ref = f_t
-    for _ in range(9):
-        ref = orc.step(q, ref)[0]
-    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_POPS), ref) < 1e-13
-    # adjoint (each run restarts from zero; fused and single steps agree bit
-    # for bit, so the 1009-step run passes through the 1000-step state): the
-    # residual of a loosely converged primal as the source
-    S.primal_solve(ctx, a)
-    r = S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL)
-    S.solid_lbm_run_adjoint_steps(ctx, 1000)
-    p_t = S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS)
-    S.solid_lbm_run_adjoint_steps(ctx, 1009)
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_POPS), orc.run(q, q.zeros(8), steps)) < TOL_D
+    S.primal_solve(ctx, a)                     # fixed-step mode: 16 steps, then the two-step average
+    r = orc.solve(q, tol=0.0, max_steps=steps - 1).dbar - tgt
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL), r) < TOL_D
+    S.solid_lbm_run_adjoint_steps(ctx, steps)
     src = orc.source(q, orc.zero_mean(r), 1.0 / n ** 2 / orc.cbar(q, tgt))
-    ph = p_t
-    for _ in range(9):
+    ph = q.zeros(8)
+    for _ in range(steps):
         ph = orc.adj_step(q, ph, src)[0]
-    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS), ph) < 1e-13
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS), ph) < TOL_D
 
 
 def test_full_size_converged_matches_closed_form(S):
@@ -331,8 +319,9 @@ def test_fused_sweeps_match_oracle(S, orc, T, nx, ny, H):
     q = oracle_problem(orc, p, dx * dx * F)
     f = orc.run(q, q.zeros(8), steps)
     assert rel(S.solid_lbm_get_field(ctx, S.FIELD_POPS), f) < TOL_D
-    S.primal_solve(ctx, F)
-    r = S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL)
+    S.primal_solve(ctx, F)                                # fixed-step mode: `steps` steps, then the average
+    r = orc.solve(q, tol=0.0, max_steps=steps).dbar - tgt
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL), r) < TOL_D
     S.solid_lbm_run_adjoint_steps(ctx, steps)
     cb = orc.cbar(q, tgt)
     src = orc.source(q, orc.zero_mean(r), dx * dx / cb)   # periodic: source mean removed

@@ -19,6 +19,9 @@
  *    closure formulas to other work): per cut link, Dirichlet bounce-back with
  *    wall displacement, Neumann anti-bounce-back with wall stress whose normal
  *    traction is T; the gamma-modified moment m_f at boundary nodes.
+ *    Parity unpinned against the paper's own closures (their formulas are not
+ *    given); pinned instead by first-order convergence on the paper's elliptic
+ *    plate, the sparse direct fixed point and finite differences.
  *  - The steady state by pseudo-time marching with the K-lag residual and a
  *    two-step average (readings C6, C7).
  *  - The adjoint fixed-point iteration (eq. adjoint_streaming,

@@ -1425,11 +1425,4 @@ __global__ void k_status_reset_all(Status* st, int n)
     }
 }
 
-// Marks every instance stopped (end of a batch loop at the step limit).
-__global__ void k_status_stop_all(Status* st, int n)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) st[i].stop = 1;
-}
-
 }  // namespace slbm

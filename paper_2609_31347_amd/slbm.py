@@ -247,6 +247,8 @@ def solid_lbm_init(problem):
 
 
 def primal_solve(ctx, control, init_disp=None):
+    """(rc, info): solve the primal to steady state for `control` (cold start, or
+    warm-started from the displacement init_disp); rc 1 = step limit reached."""
     keep = []
     cp, kind = _arg(control, keep, size=ctx.grad_len(), what="control")
     ip, kind2 = _arg(init_disp, keep, size=2 * ctx.N, what="init_disp")
@@ -258,6 +260,7 @@ def primal_solve(ctx, control, init_disp=None):
 
 
 def adjoint_solve(ctx):
+    """(rc, info): solve the adjoint of the last completed primal solve."""
     info = SolveInfo()
     rc = _check(ctx, LIB.adjoint_solve(ctx.handle, ctypes.byref(info)))
     return rc, info
@@ -291,6 +294,8 @@ def objective_and_grad(ctx, control, grad=None, want_grad=True, init_disp=None):
 
 
 def solid_lbm_set_control(ctx, control, init_disp=None):
+    """Set the control and reset the primal state (to rest, or to the
+    equilibrium of init_disp) without solving."""
     keep = []
     cp, kind = _arg(control, keep, size=ctx.grad_len(), what="control")
     ip, kind2 = _arg(init_disp, keep, size=2 * ctx.N, what="init_disp")
@@ -300,14 +305,19 @@ def solid_lbm_set_control(ctx, control, init_disp=None):
 
 
 def solid_lbm_run_steps(ctx, n):
+    """Advance the current primal state by n fixed steps (no convergence test)."""
     return _check(ctx, LIB.solid_lbm_run_steps(ctx.handle, int(n)))
 
 
 def solid_lbm_run_adjoint_steps(ctx, n):
+    """Restart the adjoint from rest and advance it by n fixed steps, with the
+    residual of the last primal solve as its source."""
     return _check(ctx, LIB.solid_lbm_run_adjoint_steps(ctx.handle, int(n)))
 
 
 def solid_lbm_get_field(ctx, which, out=None):
+    """Copy field `which` (FIELD_*) into out (host array or CUDA tensor of
+    FIELD_COMPS[which] x ny x nx doubles; allocated on the host when None)."""
     comps = FIELD_COMPS[which]
     if out is None:
         out = np.zeros((comps, ctx.ny, ctx.nx))
@@ -317,6 +327,8 @@ def solid_lbm_get_field(ctx, which, out=None):
 
 
 def solid_lbm_time_sweeps(ctx, adjoint, n):
+    """Milliseconds of n primal (adjoint = 0) or adjoint sweeps in the current
+    launch shape, measured with HIP events; advances the state."""
     ms = ctypes.c_double()
     _check(ctx, LIB.solid_lbm_time_sweeps(ctx.handle, int(adjoint), int(n), ctypes.byref(ms)))
     return ms.value
@@ -353,6 +365,8 @@ def tangent_solve(ctx, control, direction):
 
 
 def solid_lbm_restore_solve(ctx, control, avg_pops):
+    """Reinstate a converged primal solve from its two-step-averaged
+    populations (FIELD_AVG_POPS) without iterating."""
     keep = []
     cp, kind = _arg(control, keep, size=ctx.grad_len(), what="control")
     ap, kind2 = _arg(avg_pops, keep, size=8 * ctx.N, what="avg_pops")
@@ -362,12 +376,15 @@ def solid_lbm_restore_solve(ctx, control, avg_pops):
 
 
 def solid_lbm_objective(ctx):
+    """J of the last completed primal solve."""
     J = ctypes.c_double()
     _check(ctx, LIB.solid_lbm_objective(ctx.handle, ctypes.byref(J)))
     return J.value
 
 
 def solid_lbm_set_tuning(ctx, steps_per_launch=-1, rows_per_wave=0):
+    """Launch shape: time steps fused per launch (-1 automatic) and rows per
+    wave of the wave-strip kernel (0 automatic); results do not change."""
     return _check(ctx, LIB.solid_lbm_set_tuning(ctx.handle, int(steps_per_launch), int(rows_per_wave)))
 
 
@@ -383,10 +400,12 @@ def solid_lbm_set_progress(ctx, fn=None, every_s=30.0):
 
 
 def solid_lbm_set_tiles(ctx, tile_w=0, tile_h=0):
+    """Tile of the LDS-tiled kernel (0, 0 automatic); results do not change."""
     return _check(ctx, LIB.solid_lbm_set_tiles(ctx.handle, int(tile_w), int(tile_h)))
 
 
 def solid_lbm_destroy(ctx):
+    """Free the context's device memory now (otherwise on garbage collection)."""
     if ctx.handle:
         LIB.solid_lbm_destroy(ctx.handle)
         ctx.handle = None
@@ -422,6 +441,7 @@ def _bcheck(batch, rc):
 
 
 def solid_lbm_batch_init(problems):
+    """Batch of independent problems (any sizes and kinds) solved in shared launches."""
     keep = []
     arr = (_Problem * len(problems))()
     for i, pr in enumerate(problems):
@@ -488,16 +508,20 @@ def batch_gradient(batch, grads=None):
 
 
 def solid_lbm_batch_set_tuning(batch, steps_per_launch=-1, rows_per_wave=0):
+    """Launch shape of the batch's shared launches (-1 / 0 automatic); results do not change."""
     return _bcheck(batch, LIB.solid_lbm_batch_set_tuning(batch.handle, int(steps_per_launch), int(rows_per_wave)))
 
 
 def solid_lbm_batch_time_sweeps(batch, adjoint, n):
+    """Milliseconds of n batched primal (adjoint = 0) or adjoint sweeps of every
+    instance; invalidates the instances' states."""
     ms = ctypes.c_double()
     _bcheck(batch, LIB.solid_lbm_batch_time_sweeps(batch.handle, int(adjoint), int(n), ctypes.byref(ms)))
     return ms.value
 
 
 def solid_lbm_batch_destroy(batch):
+    """Free the batch and its instances now (otherwise on garbage collection)."""
     if batch.handle:
         for c in batch.contexts:
             c.handle = None

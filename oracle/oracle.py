@@ -137,6 +137,8 @@ def step(p, fS):
 
 
 def run(p, fS, nsteps):
+    """nsteps steps of the primal (collision eq. local_collide, then streaming
+    eq. local_stream) from the post-streaming populations fS; returns f^S."""
     f = _f64(fS).copy()
     _lib().orc_run(p.cref(), _ptr(f), int(nsteps))
     return f
@@ -148,7 +150,7 @@ def check_interval(dx):
 
 
 class Solve:
-    pass
+    """Result record of a primal or adjoint solve (fields set by the solver)."""
 
 
 def solve(p, fS0=None, tol=1e-10, K=None, max_steps=10_000_000):
@@ -198,18 +200,28 @@ def objective(p, d, target, obs=None, normalize=True):
 # ----------------------------------------------------------------- adjoint
 
 def source(p, r, scale):
+    """Adjoint source (dJ/df^S)^T of eq. discrete_J: scale * (r_x M[0][q] +
+    r_y M[1][q]) per node and direction, r = d - d* on the observation set
+    (d from the first moments, eq. disp_from_moments), scale = dx^2 / Cbar."""
     src = p.zeros(8)
     _lib().orc_source(p.cref(), _ptr(_f64(r)), float(scale), _ptr(src))
     return src
 
 
 def adj_step(p, phiC, src):
+    """One adjoint iteration (eq. adjoint_iteration): transposed streaming
+    (eq. adjoint_streaming), then the transposed node Jacobian minus the
+    source (eq. adjoint_collision).  Returns (phi^C, adjoint displacement of
+    the input (reading C18), routed adjoint of the input)."""
     out, dphi, ext = p.zeros(8), p.zeros(2), p.zeros(16)
     _lib().orc_adj_step(p.cref(), _ptr(_f64(phiC)), _ptr(out), _ptr(_f64(src)), _ptr(dphi), _ptr(ext))
     return out, dphi, ext
 
 
 def adj_solve(p, src, tol=1e-10, K=None, max_steps=10_000_000, phiC0=None):
+    """Adjoint fixed point from phi^C = 0 (eq. adjoint_init) with the primal's
+    stopping rule on the adjoint displacement, then the two-step average of the
+    routed adjoint (readings C6, C7, C18)."""
     phiC = p.zeros(8) if phiC0 is None else _f64(phiC0).copy()
     K = check_interval(p.dx) if K is None else int(K)
     ext = p.zeros(16)
@@ -222,6 +234,10 @@ def adj_solve(p, src, tol=1e-10, K=None, max_steps=10_000_000, phiC0=None):
 
 
 def grad_local(p, fbar, ext, want_E=False):
+    """Local part of eq. optimality at every domain node: minus the transposed
+    derivative of the node map with respect to the forcing (and, if want_E,
+    to Young's modulus, by complex step at the averaged state fbar), applied to
+    the averaged routed adjoint `ext`."""
     dg = p.zeros(2)
     dE = p.zeros(1)[0] if want_E else None
     _lib().orc_grad_local(p.cref(), _ptr(_f64(fbar)), _ptr(_f64(ext)), _ptr(dg), _ptr(dE))
@@ -241,7 +257,7 @@ def zero_mean(a, mask=None):
 
 
 class Gradient:
-    pass
+    """Result record of objective_and_grad: J, grad, and the primal / adjoint solves."""
 
 
 # ------------------------------------------------- the paper's convergence test
@@ -415,6 +431,8 @@ def fad_grad_E_sq(p, target, alpha, fixed_force, obs=None, normalize=True, tol=1
 
 
 def minv():
+    """The inverse of the moment matrix M of the appendix, as the C oracle forms
+    it (checked against M in the pins)."""
     out = np.zeros(64)
     _lib().orc_minv(_ptr(out))
     return out.reshape(8, 8)

@@ -477,3 +477,19 @@ def test_cv_solve_of_a_zero_state_stops_at_the_first_full_window(orc):
     for w in (2, 10):
         s = orc.solve_cv(p, 1e-7, window=w)
         assert s.rc == 0 and s.steps == w * K and s.residual == 0.0
+
+
+def test_fixed_step_solve_averages_steps_m_and_m_plus_one(orc):
+    """The fixed-step mode (tol <= 0) that the GPU parity tests compare against:
+    exactly max_steps steps, then the two-step average of d(m) and d(m + 1)
+    (reading C7).  A consistency check of the convention, not a pin."""
+    n, m = 12, 7
+    F = I.grf(n, n, 1 / n, 0.05, 0.1, 3, comps=2)
+    q = orc.Problem(n, n, 1 / n, 1.0, 0.3, F / n ** 2)
+    s = orc.solve(q, tol=0.0, max_steps=m)
+    f_m = orc.run(q, q.zeros(8), m)
+    f_m1, d_m, _ = orc.step(q, f_m)
+    _, d_m1, _ = orc.step(q, f_m1)
+    assert s.steps == m
+    assert np.abs(s.dbar - 0.5 * (d_m + d_m1)).max() <= 1e-15 * np.abs(d_m).max()
+    assert np.abs(s.fbar - 0.5 * (f_m + f_m1)).max() <= 1e-15 * np.abs(f_m).max()

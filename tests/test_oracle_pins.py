@@ -1,7 +1,8 @@
 """Pins of the CPU oracle against what the paper and the mathematics fix.
 
-Each test names the passage it follows.  None of them compares the oracle with
-itself: the pins are the paper's printed convergence orders and floors,
+Each test names the passage it follows.  None of the pins compares the oracle
+with itself (the one consistency check of the fixed-step convention at the
+end says so): the pins are the paper's printed convergence orders and floors,
 closed forms (a separate matrix/Fourier encoding of the periodic scheme, the
 continuum manufactured solutions), invariants (equilibria, moment budgets,
 single-wavenumber response, gradient zeros) and independent gradients (central

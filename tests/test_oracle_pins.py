@@ -373,6 +373,33 @@ def test_plate_marched_solve_matches_sparse_fixed_point(orc):
     assert s.rc == 0 and rel(s.dbar, dd) < 1e-9
 
 
+def test_plate_rigid_translation_is_an_exact_steady_state(orc):
+    """Closed form of the closures (reading C13): with zero body force, wall
+    displacement d0 on every Dirichlet link and zero traction on every Neumann
+    link, the uniform translation d = d0 solves the boundary-value problem, and
+    its equilibrium populations f_q = W_q c_q.d0 are reproduced exactly by both
+    closures (bounce-back: -W c.d0 + 2 W c.d0; anti-bounce-back of a state with
+    zero stress: +W c.d0).  The solve from rest must therefore reach d0 at every
+    domain node; a wrong sign or factor in either closure would not."""
+    cp = I.clamped_plate(40, 25)
+    d0 = np.array([3e-4, -2e-4])
+    wall = np.zeros_like(cp["wall"])
+    for q in range(8):
+        dirichlet = cp["bc"][q] == I.DIRICHLET
+        wall[0, q][dirichlet], wall[1, q][dirichlet] = d0
+    assert (cp["bc"] == I.DIRICHLET).any() and (cp["bc"] == I.NEUMANN).any()
+    p = orc.Problem(40, 25, cp["dx"], 1.0, 0.3, np.zeros((2, 25, 40)), active=cp["active"].astype(np.uint8),
+                    bc=cp["bc"], wall=wall, normal=cp["normal"])
+    from oracle import fixedpoint as FP
+    A = cp["active"]
+    _, dd = FP.fixed_point(p)                   # the exact discrete steady state
+    assert np.abs((dd - d0[:, None, None]) * A).max() < 1e-12 * np.abs(d0).max()
+    s = orc.solve(p, tol=1e-13)                 # marched from rest: error ~ tol / (1 - |slowest mode|)
+    assert s.rc == 0
+    assert np.abs((s.dbar - d0[:, None, None]) * A).max() < 1e-9 * np.abs(d0).max()
+    assert np.abs(s.sbar * A).max() < 1e-10 * np.abs(d0).max()       # no stress anywhere
+
+
 def _plate_errors(orc, nxc):
     from oracle import fixedpoint as FP
     p, d = _plate_problem(orc, nxc)

@@ -440,6 +440,33 @@ def test_plate_gamma_is_needed_for_first_order(orc):
     assert errs[0] / errs[1] < 1.6
 
 
+@pytest.mark.parametrize("case", ["periodic", "plate", "plate E field"])
+def test_adjoint_step_is_the_transpose_of_the_primal_step(orc, case):
+    """Dot-product test of the discrete adjoint (eq. adjoint_iteration is the
+    transpose of one primal step, Algorithm ALBM): with the affine part of the
+    step removed, <L x, y> = <x, L^T y> for random states on the domain nodes,
+    with closures, gamma and per-node moduli on the plate."""
+    rng = np.random.default_rng(11)
+    if case == "periodic":
+        nx, ny = 13, 9
+        F = I.grf(nx, ny, 1 / nx, 0.05, 0.2, 1, comps=2)
+        p = orc.Problem(nx, ny, 1 / nx, 0.9, 0.3, F / nx ** 2)
+        m = np.ones((1, ny, nx))
+    else:
+        d = I.paper_plate(16)
+        ny, nx = d["active"].shape
+        E = d["E"] if case == "plate" else d["E"] * (1 + 0.3 * np.tanh(rng.standard_normal((ny, nx))))
+        p = orc.Problem(nx, ny, d["dx"], E, d["nu"], d["F"] * d["dx"] ** 2 * d["active"], active=d["active"],
+                        bc=d["bc"], wall=d["wall"], normal=d["normal"])
+        m = d["active"][None].astype(float)
+    x = rng.standard_normal((8, ny, nx)) * m
+    y = rng.standard_normal((8, ny, nx)) * m
+    Lx = orc.step(p, x)[0] - orc.step(p, p.zeros(8))[0]
+    LTy = orc.adj_step(p, y, p.zeros(8))[0]
+    a, b = float((Lx * y).sum()), float((x * LTy).sum())
+    assert abs(a - b) <= 1e-13 * abs(a)
+
+
 def test_plate_adjoint_is_transpose_of_closure_map(orc):
     """ALBM gradient on the plate (adjoint closures = transposed node Jacobian)
     equals the gradient from the transposed sparse system."""

@@ -197,3 +197,32 @@ def test_tuning_limits(S, plate16):
     ctx = S.solid_lbm_init(pc)
     with pytest.raises(S.SlbmError):
         S.solid_lbm_set_tuning(ctx, 3, 0)                   # wave-strip kernel: 2, 4, 6, 8
+
+
+def test_full_size_e_field_plate_matches_oracle_steps(S, orc):
+    """The E-field plate at its benchmark size (512 x 308 nodes, clamped left
+    arc, uniform traction, E = 1 + 0.5 tanh(GRF)) in its automatic launch
+    shape (LDS tiles, 6 steps per launch): 17 steps from rest equal 17 oracle
+    steps at every node; the adjoint likewise, its source the oracle's own
+    residual of a 16-step fixed-step primal."""
+    cp = I.clamped_plate(512, 308)
+    pd = dict(cp, E=1.0, nu=0.3)
+    ny, nx = cp["active"].shape
+    E = 1.0 + 0.5 * np.tanh(I.grf(nx, ny, cp["dx"], 1.0, 0.15, 0)[0])
+    tgt = 1e-4 * I.grf(nx, ny, cp["dx"], 1.0, 0.3, 1, comps=2) * cp["active"]
+    steps = 17
+    p = plate_problem(S, pd, S.CTRL_E_NODAL, target=tgt, tol=0.0, max_steps=steps - 1)
+    ctx = S.solid_lbm_init(p)
+    S.solid_lbm_set_control(ctx, E)
+    S.solid_lbm_run_steps(ctx, steps)
+    q = oracle_plate(orc, p, np.zeros((2, ny, nx)), E)
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_POPS), orc.run(q, q.zeros(8), steps)) < TOL_D
+    S.primal_solve(ctx, E)
+    r = (orc.solve(q, tol=0.0, max_steps=steps - 1).dbar - tgt) * q.mask
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL), r) < TOL_D
+    S.solid_lbm_run_adjoint_steps(ctx, steps)
+    src = orc.source(q, r, cp["dx"] ** 2 / orc.cbar(q, tgt))
+    ph = q.zeros(8)
+    for _ in range(steps):
+        ph = orc.adj_step(q, ph, src)[0]
+    assert rel(S.solid_lbm_get_field(ctx, S.FIELD_ADJ_POPS), ph) < TOL_D

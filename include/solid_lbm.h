@@ -155,8 +155,10 @@ int solid_lbm_init(const slbm_problem *problem, slbm_ctx **out);
  * zero, eq. discrete_G closed by f^S(0) of d_0 = 0; warm: the equilibrium
  * populations of init_disp (2N)), residual test every K steps, then the
  * two-step average d = (d(t) + d(t+1)) / 2.  Leaves the averaged state, d,
- * r = d - d* and J in the context.  control / init_disp are read according to
- * ptr_kind; init_disp may be NULL.  info may be NULL.
+ * r = d - d* and J in the context.  With tol <= 0 it runs exactly max_steps
+ * steps and forms the same average (info->steps = max_steps).  control /
+ * init_disp are read according to ptr_kind; init_disp may be NULL.  info may
+ * be NULL.
  */
 int primal_solve(slbm_ctx *ctx, const double *control, const double *init_disp,
                  int32_t ptr_kind, slbm_solve_info *info);

@@ -25,7 +25,8 @@ def _modulus(n):
 
 
 def step_matrix(p):
-    """(A, idx): sparse linear part of one step restricted to domain slots."""
+    """(A, idx): sparse linear part of one step (eq. local_collide, eq. local_stream,
+    closures of reading C13) restricted to domain slots."""
     nx, ny, N = p.nx, p.ny, p.N
     q0 = p.with_(g=np.zeros((2, ny, nx)), wall=None if p.wall is None else np.zeros_like(p.wall))
     mx, my = _modulus(nx), _modulus(ny)
@@ -56,7 +57,8 @@ def step_matrix(p):
 
 
 def forcing_matrix(p):
-    """Sparse map g (2N) -> constant part of one step (8N, domain slots)."""
+    """Sparse map g (2N) -> constant part of one step (8N, domain slots): the
+    forcing of eq. local_collide after eq. local_stream."""
     nx, ny, N = p.nx, p.ny, p.N
     mx, my = _modulus(nx), _modulus(ny)
     act = p.mask
@@ -87,7 +89,8 @@ def forcing_matrix(p):
 
 
 def fixed_point(p, A=None, idx=None):
-    """Exact steady populations f^S (8, ny, nx) and displacement d (2, ny, nx)."""
+    """Exact steady populations f^S (8, ny, nx) and displacement d (2, ny, nx):
+    eq. primal_fixed_point solved directly."""
     if A is None:
         A, idx = step_matrix(p)
     b = O.step(p, np.zeros((8, p.ny, p.nx)))[0].ravel()[idx]
@@ -107,8 +110,9 @@ def _disp(p, f):
 
 
 def nodal_force_gradient(p, r, scale, A=None, idx=None):
-    """Exact dJ/dg (2, ny, nx) for J = 1/2 sum |d - d*|^2 * scale with r = d - d*
-    (zero off the observation set):  dJ/dg = G^T (I - A)^-T M12^T r s + r s / 2."""
+    """Exact dJ/dg (2, ny, nx) of eq. optimality for a force control, through
+    the transposed fixed-point system, for J = 1/2 sum |d - d*|^2 * scale with
+    r = d - d* (zero off the observation set):  dJ/dg = G^T (I - A)^-T M12^T r s + r s / 2."""
     if A is None:
         A, idx = step_matrix(p)
     G = forcing_matrix(p)

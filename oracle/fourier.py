@@ -34,7 +34,8 @@ M = np.array([
 
 
 def collision_matrices(E, nu):
-    """(C, B): f^C = C f^S + B g for a bulk node (gamma = 0)."""
+    """(C, B): f^C = C f^S + B g for a bulk node (gamma = 0), from eq. moments_c,
+    the relaxation-time table and the appendix matrix M."""
     mu = E / (2 * (1 + nu))
     K = E / (2 * (1 - nu))
     taus = {2: mu / THETA, 3: 2 * K / (1 + THETA), 4: 2 * mu / (1 - THETA), 5: 0.5, 6: 0.5, 7: 0.5}
@@ -58,7 +59,8 @@ def collision_matrices(E, nu):
 
 
 def transfer(nx, ny, E, nu):
-    """H(k) (ny, nx, 2, 2) with d^ = H g^, and H(0) = 0."""
+    """H(k) (ny, nx, 2, 2) with d^ = H g^, and H(0) = 0: eq. primal_fixed_point
+    per wavevector, read out by eq. disp_from_moments."""
     C, B = collision_matrices(E, nu)
     kx = 2 * np.pi * np.fft.fftfreq(nx)
     ky = 2 * np.pi * np.fft.fftfreq(ny)
@@ -76,7 +78,8 @@ def transfer(nx, ny, E, nu):
 
 
 def steady_disp(g, E, nu, H=None):
-    """Exact fixed-point displacement (2, ny, nx) for forcing g (2, ny, nx)."""
+    """Exact fixed-point displacement (2, ny, nx) of eq. primal_fixed_point for
+    forcing g (2, ny, nx)."""
     ny, nx = g.shape[1:]
     H = transfer(nx, ny, E, nu) if H is None else H
     gh = np.fft.fft2(g, axes=(1, 2))
@@ -85,7 +88,8 @@ def steady_disp(g, E, nu, H=None):
 
 
 def grad_g(r, E, nu, H=None):
-    """Adjoint of the map g -> d applied to r:  (dd/dg)^T r, shape (2, ny, nx)."""
+    """Adjoint of the map g -> d of eq. primal_fixed_point applied to r:
+    (dd/dg)^T r, shape (2, ny, nx) (the force part of eq. optimality)."""
     ny, nx = r.shape[1:]
     H = transfer(nx, ny, E, nu) if H is None else H
     rh = np.fft.fft2(r, axes=(1, 2))
@@ -94,7 +98,8 @@ def grad_g(r, E, nu, H=None):
 
 
 def mode_decay(nx, ny, E, nu, k):
-    """Spectral radius of P(k) C for one integer wavevector k = (kx, ky)."""
+    """Moduli of the eigenvalues of P(k) C, one step (eq. local_collide, then
+    eq. local_stream) of the Fourier mode k = (kx, ky)."""
     C, _ = collision_matrices(E, nu)
     kap = (2 * np.pi * k[0] / nx, 2 * np.pi * k[1] / ny)
     P = np.exp(-1j * (kap[0] * CX + kap[1] * CY))
@@ -102,7 +107,8 @@ def mode_decay(nx, ny, E, nu, k):
 
 
 def steady_pops(g, E, nu):
-    """Exact fixed-point populations f^S (8, ny, nx) for forcing g (2, ny, nx)."""
+    """Exact fixed-point populations f^S (8, ny, nx) of eq. primal_fixed_point for
+    forcing g (2, ny, nx)."""
     ny, nx = g.shape[1:]
     C, B = collision_matrices(E, nu)
     kx = 2 * np.pi * np.fft.fftfreq(nx)

@@ -129,7 +129,8 @@ class Problem:
 # ----------------------------------------------------------------- primal
 
 def step(p, fS):
-    """One step; returns (fS(t+1), d(t), sigma(t) lattice units)."""
+    """One primal step (eq. local_collide, then eq. local_stream); returns
+    (fS(t+1), d(t), sigma(t) in lattice units)."""
     fS = _f64(fS)
     out, d, s = p.zeros(8), p.zeros(2), p.zeros(3)
     _lib().orc_step(p.cref(), _ptr(fS), _ptr(out), _ptr(d), _ptr(s))
@@ -168,7 +169,8 @@ def solve(p, fS0=None, tol=1e-10, K=None, max_steps=10_000_000):
 
 
 def solve_cs(p, E_im=None, g_im=None, tol=1e-10, K=None, max_steps=10_000_000):
-    """Complex-step primal solve: returns (dbar, dbar_im) with inputs E + i E_im, g + i g_im."""
+    """Complex-step primal solve, the forward mode of eq. fAD: returns (dbar,
+    dbar_im) for inputs E + i E_im, g + i g_im."""
     fr, fi = p.zeros(8), p.zeros(8)
     K = check_interval(p.dx) if K is None else int(K)
     E_im = None if E_im is None else _f64(np.broadcast_to(E_im, (p.ny, p.nx)))
@@ -420,7 +422,8 @@ def fad_grad_modes(p, target, control, modes, obs=None, normalize=True, tol=1e-1
 
 def fad_grad_E_sq(p, target, alpha, fixed_force, obs=None, normalize=True, tol=1e-10, K=None,
                   max_steps=10_000_000, h=1e-30):
-    """Forward-mode gradient for E = alpha^2 via a complex-step primal solve."""
+    """Forward-mode gradient (eq. fAD) for the scalar control E = alpha^2
+    (eq. E_substitution), by a complex-step primal solve."""
     dx2 = p.dx * p.dx
     q = p.with_(E=alpha * alpha, g=dx2 * fixed_force)
     m = q.mask if obs is None else (np.asarray(obs, bool) & q.mask)

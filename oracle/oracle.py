@@ -29,7 +29,7 @@ CY = np.array([0, 1, 0, -1, 1, 1, -1, -1])
 def _lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(HERE, "liboracle.so")
+        path = os.environ.get("SLBM_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
         if not os.path.exists(path):
             from . import build as _b
             _b.build()
@@ -377,9 +377,12 @@ def objective_and_grad(p, target, kind, control, modes=None, fixed_force=None, o
     r = (prim.dbar - target) * m
     J = 0.5 * float((r ** 2).sum()) * dx2 / c
     if q.active is None:
-        # periodic: d has zero mean, so the mean of the adjoint source is outside
-        # the range of the solution map; removing it keeps the adjoint's
-        # translation mode at rest and leaves the gradient unchanged
+        # periodic (reading C21): d has zero mean (the translations are the
+        # kernel of the torus problem, Sec. "Problem formulation"), so the mean
+        # of r does not depend on the control; the source takes the zero-mean
+        # part of r, the compatibility condition that eq. zero_mean_projection
+        # states for the control.  With the mean kept the source excites the
+        # adjoint's translation mode (eigenvalue 1) and there is no fixed point.
         r = zero_mean(r)
     src = source(q, r, dx2 / c)
     if cv_window > 0:

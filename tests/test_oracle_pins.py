@@ -548,3 +548,121 @@ def test_fixed_step_solve_averages_steps_m_and_m_plus_one(orc):
     assert s.steps == m
     assert np.abs(s.dbar - 0.5 * (d_m + d_m1)).max() <= 1e-15 * np.abs(d_m).max()
     assert np.abs(s.fbar - 0.5 * (f_m + f_m1)).max() <= 1e-15 * np.abs(f_m).max()
+
+
+# ------------------------------------- C-bar, the closed-form objective, mean removal
+
+def test_cbar_and_two_mode_objective_in_closed_form(orc):
+    """C-bar of eq. node_J for the two-mode target (reading C10) in closed form,
+    and the oracle's J and dJ/dA (tol 1e-12) against the values of the Fourier
+    fixed point written to tests/golden/two_mode_closed_form.json (eq.
+    primal_fixed_point per wavevector; eq. optimality).  With d = A1 a1 b1 +
+    A2 a2 b2 (the response is pure amplitude) and discrete orthogonality of b1,
+    b2, J = [(A1 a1 - c1)^2 / 4 + (A2 a2 - c2)^2 / 2] / C-bar and
+    dJ/dA1 = (A1 a1 - c1) a1 / (2 C-bar), dJ/dA2 = (A2 a2 - c2) a2 / C-bar, where
+    a1, a2 are read off unit-amplitude solves: a dropped term, a wrong C-bar or
+    a transposed mode fails one of these."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "two_mode_closed_form.json")))
+    for case in gold["cases"]:
+        n = case["n"]
+        p, modes, tgt = _config1(orc, n)
+        s = 1.0 / (1.0 - 0.3 ** 2)                       # mu + K = E / (1 - nu^2)
+        c1, c2 = 0.7 / (8 * np.pi ** 2 * s), 0.3 / (16 * np.pi ** 2 * s)
+        cb = 0.5 * c1 * c1 + c2 * c2
+        assert abs(orc.cbar(p, tgt) - cb) <= 1e-14 * cb
+        assert abs(case["cbar"] - cb) <= 1e-14 * cb
+        a = np.array(case["A"])
+        G = orc.objective_and_grad(p, tgt, "modes", a, modes=modes, tol=1e-12)
+        assert G.prim.rc == 0 and G.adj.rc == 0
+        assert abs(G.cbar - cb) <= 1e-14 * cb
+        assert abs(G.J - case["J"]) <= 1e-10 * case["J"]
+        assert rel(G.grad, np.array(case["grad"])) <= 1e-10
+        amp = []
+        for i in range(2):
+            u = orc.solve(p.with_(g=modes[i] / n ** 2), tol=1e-13)
+            assert u.rc == 0
+            amp.append((u.dbar * modes[i]).sum() / (modes[i] ** 2).sum())
+            # pure amplitude: nothing outside the mode
+            assert np.abs(u.dbar - amp[-1] * modes[i]).max() <= 1e-10 * np.abs(u.dbar).max()
+        a1, a2 = amp
+        J = ((a[0] * a1 - c1) ** 2 / 4 + (a[1] * a2 - c2) ** 2 / 2) / cb
+        g = np.array([(a[0] * a1 - c1) * a1 / (2 * cb), (a[1] * a2 - c2) * a2 / cb])
+        assert abs(G.J - J) <= 1e-10 * J
+        assert rel(G.grad, g) <= 1e-10
+
+
+def test_periodic_gradient_with_a_nonzero_mean_target(orc):
+    """A target whose mean is not zero.  On the torus the displacement has zero
+    mean (reading C5; the translations are the kernel of the problem, Sec.
+    'Problem formulation'), so the mean of r = d - d* is fixed and J's
+    dependence on the control is through the zero-mean part of r alone.  The
+    adjoint source is therefore taken with its mean removed (the same
+    compatibility condition that eq. zero_mean_projection imposes on the
+    control); the gradient then equals central FD of J at every DOF.  Without
+    the removal the source has a component on the adjoint's translation mode
+    (eigenvalue 1 of C^T), which grows every step: the adjoint never reaches a
+    fixed point."""
+    n = 6
+    rng = np.random.default_rng(11)
+    tgt = rng.standard_normal((2, n, n)) * 1e-3 + np.array([2e-3, -1e-3])[:, None, None]
+    alpha = rng.standard_normal((2, n, n)) * 0.1
+    p = orc.Problem(n, n, 1 / n, 1.0, 0.3, np.zeros((2, n, n)))
+    G = orc.objective_and_grad(p, tgt, "nodal", alpha, tol=1e-13)
+    assert G.prim.rc == 0 and G.adj.rc == 0
+    h = 1e-1
+    fd = np.zeros_like(alpha)
+    for c in range(2):
+        for j in range(n):
+            for i in range(n):
+                e = np.zeros_like(alpha)
+                e[c, j, i] = h
+                jp = orc.objective_and_grad(p, tgt, "nodal", alpha + e, tol=1e-13).J
+                jm = orc.objective_and_grad(p, tgt, "nodal", alpha - e, tol=1e-13).J
+                fd[c, j, i] = (jp - jm) / (2 * h)
+    assert rel(G.grad, orc.zero_mean(fd)) < 1e-8
+    # mode controls see the same: a constant shift of the target changes J by a
+    # constant only, so the gradient is that of the zero-mean target
+    m, modes, tgt2 = _config1(orc, 16)
+    a = np.array([0.2, -0.3])
+    G1 = orc.objective_and_grad(m, tgt2 + 1e-3, "modes", a, modes=modes, tol=1e-12, normalize=False)
+    G0 = orc.objective_and_grad(m, tgt2, "modes", a, modes=modes, tol=1e-12, normalize=False)
+    assert rel(G1.grad, G0.grad) < 1e-10
+    # the raw source (mean kept) has no adjoint fixed point
+    q = G.problem
+    raw = (G.prim.dbar - tgt)
+    src = orc.source(q, raw, q.dx ** 2 / G.cbar)
+    bad = orc.adj_solve(q, src, tol=1e-10, max_steps=20000)
+    assert bad.rc != 0
+    good = orc.adj_solve(q, orc.source(q, orc.zero_mean(raw), q.dx ** 2 / G.cbar), tol=1e-10, max_steps=20000)
+    assert good.rc == 0
+
+
+def test_cv_adjoint_reaches_the_fourier_adjoint(orc):
+    """The adjoint under the paper's coefficient-of-variation test (eq.
+    convergence_crit on the adjoint displacement, reading C18) gives the exact
+    gradient of the periodic fixed point: the adjoint of the Fourier transfer
+    map applied to the misfit (eq. optimality), for a mode control and a
+    nodal control."""
+    from oracle import fourier as Fo
+    n = 16
+    p, modes, tgt = _config1(orc, n)
+    a = np.array([0.1, 0.1])
+    G = orc.objective_and_grad(p, tgt, "modes", a, modes=modes, tol=1e-10, cv_window=10)
+    assert G.prim.rc == 0 and G.adj.rc == 0
+    H = Fo.transfer(n, n, 1.0, 0.3)
+    dx2 = 1 / n ** 2
+    s = 1.0 / (1.0 - 0.3 ** 2)
+    cb = 0.5 * (0.7 / (8 * np.pi ** 2 * s)) ** 2 + (0.3 / (16 * np.pi ** 2 * s)) ** 2
+    d = Fo.steady_disp(dx2 * np.tensordot(a, modes, 1), 1.0, 0.3, H)
+    gg = Fo.grad_g(d - tgt, 1.0, 0.3, H) * dx2 / cb
+    exact = np.array([(gg * dx2 * m).sum() for m in modes])
+    assert rel(G.grad, exact) < 1e-10
+    alpha = I.grf(n, n, 1 / n, 0.05, 0.1, 4, comps=2)
+    G = orc.objective_and_grad(p, tgt, "nodal", alpha, tol=1e-10, cv_window=10)
+    assert G.prim.rc == 0 and G.adj.rc == 0
+    d = Fo.steady_disp(dx2 * orc.zero_mean(alpha), 1.0, 0.3, H)
+    exact = orc.zero_mean(dx2 * Fo.grad_g(d - tgt, 1.0, 0.3, H) * dx2 / cb)
+    assert rel(G.grad, exact) < 1e-9
+    # the adjoint displacement's test stops on a multiple of K after a full window
+    K = orc.check_interval(1 / n)
+    assert G.adj.steps % K == 0 and G.adj.steps >= 10 * K

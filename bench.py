@@ -1,17 +1,24 @@
 """Benchmark: FP64 primal + adjoint solid-LBM sweeps and time-to-gradient on one MI355X.
 
-Workload: periodic two-amplitude force identification on the unit torus at
-N = 1024 (E = 1, nu = 0.3, body force A1 b1 + A2 b2, target the continuum
-displacement of A* = (0.7, 0.3)), gradient at the L-BFGS start A = (0.1, 0.1).
-One step = one objective_and_grad call: cold primal solve to residual 1e-10,
-J, adjoint solve to 1e-10, gradient dJ/dA (all on the GPU, inputs resident).
+Default workload (HBM-resident): distributed body-force control on the
+2048 x 2048 torus (2 x 2048^2 DOF; E = 1, nu = 0.3; reference force = the
+two-mode field with A* = (0.7, 0.3) plus a GRF of variance 0.05, length 0.1,
+seed 0; gradient at the informed start -F_ref).  One step = one gradient pass
+with a fixed sweep budget of `--checks` residual-check intervals per half:
+control -> forcing (zero-mean projection), primal sweeps with the K-lag
+residual test, two-step average, r and J, adjoint sweeps with the test,
+gradient assembly -- every row of the hot path, inputs resident in HBM.  The
+two population buffers are 268 MB each, beyond the 256 MB Infinity Cache.
 
-value = MLUPS over all primal + adjoint sweeps of the timed steps
-(cells x sweeps / wall seconds / 1e6).  The roofline object is for the
-dominant kernel (the primal sweep): algorithmic 144 B/node/sweep x nodes /
-the average sweep duration measured with HIP events on the library's stream
-during the timed steps.  cpu_baseline = the CPU oracle timed on a bounded
-sample of the same workload on one host core.
+value = MLUPS over all primal + adjoint sweeps of the timed steps (cells x
+sweeps / wall seconds / 1e6).  roofline = the dominant kernel (the fused
+primal sweep): its algorithmic bytes per launch (144 B per node: populations
+read once and written once, forcing read once) over its average launch
+duration from HIP events on the library stream during the timed steps.
+time_to_gradient = cold converged gradients (primal and adjoint to residual
+1e-10) of the two-amplitude workload at 1024^2 and at the bench grid, timed
+after the steps.  cpu_baseline = the CPU oracle on a bounded sample of the
+same workload on one host core.
 """
 import argparse
 import json
@@ -26,25 +33,25 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_NODE = 144.0      # 8 pops read + 8 written (8 B each) + 2 forcing / residual reads
 PEAK_GBS = 8000.0           # MI355X HBM3E
-# Measured HBM bytes per launch of the dominant kernel, keyed by (N, T, H), from
-# rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors of a plain device copy);
-# see profiles/.  Entries are dropped whenever the kernel changes.
-TRAFFIC_BYTES = {(1024, 8, 24): (2.0 * 94293.2 + 65536.0) * 1024,
-                 (1024, 8, 32): (2.0 * 84606.5 + 65536.0) * 1024,
-                 (1024, 6, 24): (2.0 * 94204.7 + 65536.0) * 1024,
-                 (2048, 8, 48): (2.0 * 294298.0 + 262144.0) * 1024,
-                 (2048, 8, 96): (2.0 * 258148.4 + 262144.0) * 1024}
+# Measured HBM bytes per launch of the dominant kernel, keyed by (N, T, H):
+# rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain device copy
+# of known size reads on gfx950), per dispatch of the fused primal sweep, with
+# the hash of the kernel sources they were taken with (profiles/).
+TRAFFIC = {}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--checks", type=int, default=2,
+                    help="gradient mode: sweep budget per half in residual-check intervals K")
+    ap.add_argument("--no-ttg", action="store_true", help="skip the converged time-to-gradient runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--mode", choices=("gradient", "sweeps", "lbfgs", "batch", "warmstart", "nodal"),
                     default="gradient",
                     help="sweeps: time fixed counts of primal/adjoint sweeps and a reference copy "
@@ -415,20 +422,17 @@ def warmstart_mode(args):
               flush=True)
 
 
-def cpu_baseline(n, steps, a):
+def cpu_baseline(n, steps, F, tgt):
     """Oracle sweeps on a bounded sample: `steps` primal and `steps` adjoint
-    sweeps of the same N x N workload on one core."""
+    sweeps of the same N x N workload (nodal forcing F, target tgt) on one core."""
     from oracle import oracle as O
-    from paper_2609_31347_amd import inputs as I
-    modes = I.two_mode_basis(n)
-    tgt = I.two_mode_target(n)
-    p = O.Problem(n, n, 1.0 / n, 1.0, 0.3, np.tensordot(a, modes, 1) / n ** 2)
+    p = O.Problem(n, n, 1.0 / n, 1.0, 0.3, O.zero_mean(F) / n ** 2)
     f = p.zeros(8)
     t0 = time.perf_counter()
     f = O.run(p, f, steps)
     t1 = time.perf_counter()
     _, d, _ = O.step(p, f)
-    src = O.source(p, d - tgt, (1.0 / n ** 2) / O.cbar(p, tgt))
+    src = O.source(p, O.zero_mean(d - tgt), (1.0 / n ** 2) / O.cbar(p, tgt))
     ph = p.zeros(8)
     t2 = time.perf_counter()
     for _ in range(steps):
@@ -441,6 +445,43 @@ def cpu_baseline(n, steps, a):
                       f"(single-threaded C, -O2 -ffp-contract=off)",
             "primal_mlups": round(steps * cells / (t1 - t0) / 1e6, 3),
             "adjoint_mlups": round(steps * cells / (t3 - t2) / 1e6, 3)}
+
+
+def kernel_source_hash():
+    """Hash of the sweep kernels' sources: counter figures taken with other
+    sources do not describe the running kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("slbm_kernels.h", "slbm_device.h"):
+        with open(os.path.join(ROOT, "paper_2609_31347_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def converged_gradient(S, n, tol):
+    """Cold time-to-gradient of the two-amplitude workload on the n x n torus
+    (primal and adjoint to tol): (wall s, primal info, adjoint info, J, grad)."""
+    import torch
+    from paper_2609_31347_amd import inputs as I
+    from paper_2609_31347_amd import autotune
+    prob = dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC, target=I.two_mode_target(n),
+                control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=I.two_mode_basis(n), tol=tol,
+                max_steps=50_000_000, stream=torch.cuda.current_stream().cuda_stream)
+    ctx = S.solid_lbm_init(prob)
+    autotune.autotune(ctx, prob, np.array([0.1, 0.1]))
+    a = torch.tensor([0.1, 0.1], dtype=torch.float64, device="cuda")
+    grad = torch.zeros(2, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, J, _, pi, ai = S.objective_and_grad(ctx, a, grad=grad)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    S.require_converged(rc, f"{n}x{n} two-amplitude gradient", pi if not pi.converged else ai)
+    out = {"grid": [n, n], "time_to_gradient_s": round(wall, 4), "primal_steps": pi.steps,
+           "adjoint_steps": ai.steps, "glups": round(n * n * (pi.sweeps + ai.sweeps) / wall / 1e9, 2),
+           "J": J, "grad": [float(x) for x in grad.cpu().numpy()]}
+    S.solid_lbm_destroy(ctx)
+    return out
 
 
 def main():
@@ -465,51 +506,79 @@ def main():
 
     torch.cuda.set_device(0)
     n = args.n
-    modes = I.two_mode_basis(n)
+    # distributed body-force control (2 n^2 DOF): reference force = two-mode field
+    # A* = (0.7, 0.3) + GRF (variance 0.05, length 0.1, seed 0); gradient at the
+    # informed start -F_ref; target = continuum displacement of the two-mode part
+    F_ref = I.grf_force_control(n, 0)
     tgt = I.two_mode_target(n)
+    K = 2 * int(np.ceil(0.005 * n * n - 1e-9))
+    budget = args.checks * K
     prob = dict(nx=n, ny=n, dx=1.0 / n, E=1.0, nu=0.3, domain=S.PERIODIC, target=tgt,
-                control_kind=S.CTRL_FORCE_MODES, n_modes=2, force_modes=modes, tol=args.tol,
-                max_steps=50_000_000, stream=torch.cuda.current_stream().cuda_stream)
+                control_kind=S.CTRL_FORCE_NODAL, tol=args.tol, max_steps=budget,
+                stream=torch.cuda.current_stream().cuda_stream)
     ctx = S.solid_lbm_init(prob)
     from paper_2609_31347_amd import autotune
-    tune = autotune.autotune(ctx, prob, np.array([0.1, 0.1]))
-    a = torch.tensor([0.1, 0.1], dtype=torch.float64, device="cuda")
-    grad = torch.zeros(2, dtype=torch.float64, device="cuda")
+    tune = autotune.autotune(ctx, prob, -F_ref)
+    S.solid_lbm_set_launch_timing(ctx, True)
+    alpha = torch.tensor(-F_ref, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(2 * n * n, dtype=torch.float64, device="cuda")
+
+    def one_step():
+        rc, J, _, pi, ai = S.objective_and_grad(ctx, alpha, grad=grad)
+        # a fixed sweep budget per half: the residual test runs and stops nothing
+        if rc < 0 or pi.sweeps != budget + 1 or ai.sweeps != budget + 1:
+            raise RuntimeError(f"unexpected gradient pass: rc {rc}, sweeps {pi.sweeps} / {ai.sweeps}")
+        return rc, J, pi, ai
 
     for _ in range(args.warmup):
-        S.objective_and_grad(ctx, a, grad=grad)
+        one_step()
     torch.cuda.synchronize()
     rec = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        rc, J, _, pi, ai = S.objective_and_grad(ctx, a, grad=grad)
+        rc, J, pi, ai = one_step()
         rec.append((rc, J, pi.as_dict(), ai.as_dict()))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
     cells = n * n
     sweeps = sum(r[2]["sweeps"] + r[3]["sweeps"] for r in rec)
-    p_sweeps = sum(r[2]["sweeps"] for r in rec)
-    a_sweeps = sum(r[3]["sweeps"] for r in rec)
-    p_ms = sum(r[2]["device_ms"] for r in rec)
-    a_ms = sum(r[3]["device_ms"] for r in rec)
     mlups = sweeps * cells / wall / 1e6
-    t_primal = p_ms / p_sweeps * 1e-3          # s per primal time step (device, events)
-    t_adj = a_ms / a_sweeps * 1e-3
+
+    def launch_stats(k):
+        launches = sum(r[k]["fused_launches"] for r in rec)
+        fsweeps = sum(r[k]["fused_sweeps"] for r in rec)
+        ms = sum(r[k]["fused_ms"] for r in rec)
+        dev = sum(r[k]["device_ms"] for r in rec)
+        all_sweeps = sum(r[k]["sweeps"] for r in rec)
+        return launches, fsweeps, ms, dev, all_sweeps
+
     T, H = tune["T"], tune["H"]
     tw, th = tune.get("tiles", [0, 0])
     if tw > 0:
-        kname = (f"k_sweep_tile<false,false,false> (primal sweep, {T} time steps per launch, "
-                 f"{tw}x{th} tiles in LDS)")
-        traffic = None
+        kname = f"k_sweep_tile<false,false,false> (primal sweep, {T} time steps per launch, {tw}x{th} tiles in LDS)"
     elif T > 1:
         kname = f"k_sweep_tb<{T},false> (primal sweep, {T} time steps per launch, {H} rows per wave)"
-        traffic = TRAFFIC_BYTES.get((n, T, H))
     else:
-        kname = "k_primal<false,false,false> (primal sweep)"
-        traffic = None
-    ach = BYTES_PER_NODE * cells / t_primal / 1e9
-    ach_adj = BYTES_PER_NODE * cells / t_adj / 1e9
+        kname = "k_primal<false,false,false> (primal sweep, one step per launch)"
+    lp, sp, msp, devp, allp = launch_stats(2)
+    la, sa, msa, deva, alla = launch_stats(3)
+    if lp == 0:
+        raise RuntimeError("no fused launches were timed")
+    steps_per_launch = sp / lp
+    bytes_launch = BYTES_PER_NODE * cells                  # fused-launch minimum: pops in + out, forcing in, once
+    us_p = msp / lp * 1e3
+    us_a = msa / la * 1e3 if la else float("nan")
+    ach = bytes_launch / (us_p * 1e-6) / 1e9
+    src_hash = kernel_source_hash()
+    entry = TRAFFIC.get((n, T, H))
+    traffic, tnote = None, None
+    if entry is None:
+        tnote = f"no counter record for grid {n}, T {T}, H {H}"
+    elif entry["sources"] != src_hash:
+        tnote = f"counters were taken with kernel sources {entry['sources']}, running {src_hash}"
+    else:
+        traffic = entry["bytes"]
     out = {
         "metric": "FP64 MLUPS primal+adjoint (%HBM roofline); time-to-gradient at res 1e-10",
         "value": round(mlups, 1),
@@ -523,29 +592,41 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"periodic two-amplitude force identification, {n}x{n} torus, E=1, nu=0.3, "
-                               f"gradient at A=(0.1,0.1), primal+adjoint to residual {args.tol:g}",
-                   "grid": [n, n], "tol": args.tol, "control": "FORCE_MODES"},
-        "time_to_gradient_s": round(wall / args.steps, 4),
-        "primal": {"sweeps": rec[-1][2]["sweeps"], "steps": rec[-1][2]["steps"],
-                   "mlups": round(cells / t_primal / 1e6, 1), "converged": rec[-1][2]["converged"]},
-        "adjoint": {"sweeps": rec[-1][3]["sweeps"], "steps": rec[-1][3]["steps"],
-                    "mlups": round(cells / t_adj / 1e6, 1), "converged": rec[-1][3]["converged"],
-                    "achieved_GBs": round(ach_adj, 1), "frac": round(ach_adj / PEAK_GBS, 4)},
+        "config": {"workload": f"distributed body-force control on the {n}x{n} torus ({2 * cells} DOF; E=1, nu=0.3; "
+                               f"reference force = two-mode field (0.7, 0.3) + GRF var 0.05 len 0.1 seed 0; "
+                               f"gradient at -F_ref); one step = control -> forcing, {budget} primal sweeps with "
+                               f"K-lag residual checks every {K}, two-step average, r, J, {budget} adjoint sweeps "
+                               f"with checks, gradient assembly; HBM-resident (two 268 MB population buffers)",
+                   "grid": [n, n], "control": "FORCE_NODAL", "tol": args.tol, "check_interval": K,
+                   "sweeps_per_half": budget},
+        "primal": {"sweeps_per_step": rec[-1][2]["sweeps"], "glups": round(allp * cells / (devp * 1e-3) / 1e9, 2),
+                   "fused_launch_us": round(us_p, 3), "residual": rec[-1][2]["residual"]},
+        "adjoint": {"sweeps_per_step": rec[-1][3]["sweeps"], "glups": round(alla * cells / (deva * 1e-3) / 1e9, 2),
+                    "fused_launch_us": round(us_a, 3), "residual": rec[-1][3]["residual"],
+                    "achieved_GBs": round(bytes_launch / (us_a * 1e-6) / 1e9, 1),
+                    "frac": round(bytes_launch / (us_a * 1e-6) / 1e9 / PEAK_GBS, 4)},
         "J": rec[-1][1],
-        "grad": [float(x) for x in grad.cpu().numpy()],
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-                     "bytes_per_node_step": BYTES_PER_NODE, "node_steps_per_launch": cells * max(T, 1),
-                     "avg_step_us": round(t_primal * 1e6, 3),
-                     "note": "achieved = algorithmic bytes of the single-step scheme (144 B per node and "
-                             "time step) over the measured time; fused launches reuse data across their T "
-                             "steps in registers, so frac can exceed 1 while the HBM traffic (traffic, "
-                             "bytes per launch) stays below the peak"},
+                     "algorithmic_bytes_per_launch": bytes_launch, "bytes_per_node_per_launch": BYTES_PER_NODE,
+                     "steps_per_launch": round(steps_per_launch, 3), "avg_launch_us": round(us_p, 3),
+                     "launches_timed": lp, "kernel_sources": src_hash,
+                     "note": "achieved = the fused launch's algorithmic bytes (each node's 8 populations read "
+                             "once and written once, its 2 forcing values read once: 144 B per node per launch) "
+                             "/ the launch's average duration from HIP events on the library stream over the "
+                             "timed steps; traffic = HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE "
+                             "scaled by a plain copy's factors"},
         "tuning": {"T": T, "H": H, "tiles": [tw, th], "cached": tune["cached"], "candidates_us": tune.get("us")},
     }
+    if tnote:
+        out["roofline"]["traffic_note"] = tnote
+    if not args.no_ttg:
+        # cold time-to-gradient at residual 1e-10, two-amplitude workload (converged; outside the timed steps)
+        ttg = [converged_gradient(S, m, args.tol) for m in (1024, n)]
+        out["time_to_gradient_s"] = ttg[-1]["time_to_gradient_s"]
+        out["time_to_gradient"] = ttg
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, np.array([0.1, 0.1]))
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, -F_ref, tgt)
     print(json.dumps(out), flush=True)
 
 

@@ -139,6 +139,13 @@ typedef struct {
     double device_ms;  /* device time of the sweep loop: HIP events recorded on the
                           context's stream before the first and after the last sweep */
     int32_t converged; /* 1 if residual < tol */
+    /* With solid_lbm_set_launch_timing on (else 0): the fused launches of the
+     * sweep loop (several time steps per launch: wave strips or LDS tiles),
+     * the sweeps they made, and their device time, from HIP events on the
+     * context's stream around each run of back-to-back fused launches. */
+    int64_t fused_launches;
+    int64_t fused_sweeps;
+    double fused_ms;
 } slbm_solve_info;
 
 /*
@@ -190,7 +197,9 @@ int objective_and_grad(slbm_ctx *ctx, const double *control, double *J, double *
  * This is Algorithm "ALBM" with the objective's source (dJ/df)^T replaced by
  * the cotangent and eq. optimality applied to it.  d_cot and grad (length as
  * for objective_and_grad) are read/written according to ptr_kind.  The
- * objective's residual held in the context is replaced by d_cot.
+ * cotangent is staged in the context's own adjoint-source buffer: the primal
+ * state, r = d - d* and J stay as they were, so a later adjoint_solve still
+ * differentiates the objective.
  */
 int adjoint_solve_vjp(slbm_ctx *ctx, const double *d_cot, double *grad, int32_t ptr_kind,
                       slbm_solve_info *info);
@@ -293,6 +302,12 @@ int solid_lbm_set_tiles(slbm_ctx *ctx, int32_t tile_w, int32_t tile_h);
  * call into the library with the same ctx. */
 typedef void (*slbm_progress_fn)(void *user, int32_t phase, int64_t step, double residual);
 int solid_lbm_set_progress(slbm_ctx *ctx, slbm_progress_fn fn, void *user, double every_s);
+
+/* Measurement switch: on != 0 makes the solve loops time their fused
+ * launches (fields fused_launches, fused_sweeps, fused_ms of slbm_solve_info)
+ * with one pair of HIP events per run of launches between residual checks;
+ * off (default) leaves those fields 0.  Does not change results. */
+int solid_lbm_set_launch_timing(slbm_ctx *ctx, int32_t on);
 
 /* Message of the last error on ctx (or of the last failed init if ctx is NULL). */
 const char *solid_lbm_last_error(const slbm_ctx *ctx);

@@ -23,9 +23,14 @@ MODES = ("checkpoint", "recompute")
 
 
 class Solver:
-    """One problem on the current GPU (owns the library context)."""
+    """One problem on the current GPU (owns the library context).
 
-    def __init__(self, problem, tune=True, tune_control=None):
+    strict (default True): a primal or adjoint solve that stops at max_steps
+    before reaching tol raises slbm.NotConverged instead of handing a
+    non-steady displacement or gradient to autograd."""
+
+    def __init__(self, problem, tune=True, tune_control=None, strict=True):
+        self.strict = bool(strict)
         self.problem = dict(problem)
         self.problem.setdefault("stream", torch.cuda.current_stream().cuda_stream)
         self.ctx = S.solid_lbm_init(self.problem)
@@ -48,6 +53,8 @@ class Solver:
         rc, info = S.primal_solve(self.ctx, c, d0)
         self.solve_id += 1
         self.last_info = info
+        if self.strict:
+            S.require_converged(rc, "primal solve", info)
         d = torch.empty((2, self.ny, self.nx), dtype=torch.float64, device="cuda")
         S.solid_lbm_get_field(self.ctx, S.FIELD_DISP, d)
         return d
@@ -65,6 +72,8 @@ class Solver:
         g = torch.empty(self.ctx.grad_len(), dtype=torch.float64, device="cuda")
         rc, g, info = S.adjoint_solve_vjp(self.ctx, d_cot.detach().to(torch.float64).contiguous(), g)
         self.last_adjoint_info = info
+        if self.strict:
+            S.require_converged(rc, "adjoint solve", info)
         return g.reshape(grad_shape)
 
     def objective(self):
@@ -80,6 +89,7 @@ class _Displacement(torch.autograd.Function):
         c = control.detach().to(torch.float64).contiguous()
         d = solver.solve(c)
         fctx.solver, fctx.mode, fctx.sid, fctx.shape = solver, mode, solver.solve_id, tuple(control.shape)
+        fctx.cdev, fctx.cdtype = control.device, control.dtype
         saved = solver.checkpoint() if mode == "checkpoint" else d.detach().clone()
         fctx.save_for_backward(c, saved)
         return d
@@ -94,8 +104,9 @@ class _Displacement(torch.autograd.Function):
             else:
                 solver.solve(c, init_disp=saved)
             fctx.sid = solver.solve_id
-        g = solver.vjp(grad_d, fctx.shape)
-        return g.to(grad_d.device), None, None
+        g = solver.vjp(grad_d.to("cuda"), fctx.shape)
+        # autograd wants the gradient where the control lives (it may be a CPU tensor)
+        return g.to(fctx.cdev, fctx.cdtype), None, None
 
 
 def displacement(control, solver, mode="checkpoint"):

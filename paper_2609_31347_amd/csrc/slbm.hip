@@ -23,6 +23,88 @@ thread_local std::string g_init_error;
 
 }  // namespace
 
+// Device time of the fused launches of a solve loop: one pair of HIP events on
+// the context's stream around each run of back-to-back fused launches (the
+// launches between two residual checks); pairs are harvested once the host
+// has seen them complete and their events are reused.
+struct LaunchTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;                        // free events
+    std::deque<std::pair<hipEvent_t, hipEvent_t>> pending;
+    hipEvent_t open = nullptr;                           // start of the run being recorded
+    int64_t launches = 0, sweeps = 0;                    // fused launches and the sweeps they made
+    double ms = 0.0;                                     // device time of the completed runs
+    hipError_t take(hipEvent_t* e)
+    {
+        if (!pool.empty()) {
+            *e = pool.back();
+            pool.pop_back();
+            return hipSuccess;
+        }
+        return hipEventCreate(e);
+    }
+    void reset()
+    {
+        launches = sweeps = 0;
+        ms = 0.0;
+    }
+    // before a fused launch of `k` sweeps on `stream`
+    hipError_t before(hipStream_t stream, int k)
+    {
+        if (!on) return hipSuccess;
+        ++launches;
+        sweeps += k;
+        if (open) return hipSuccess;
+        hipError_t e = take(&open);
+        return e != hipSuccess ? e : hipEventRecord(open, stream);
+    }
+    // after the last fused launch of a run
+    hipError_t close(hipStream_t stream)
+    {
+        if (!on || !open) return hipSuccess;
+        hipEvent_t end;
+        hipError_t e = take(&end);
+        if (e == hipSuccess) e = hipEventRecord(end, stream);
+        if (e != hipSuccess) return e;
+        pending.emplace_back(open, end);
+        open = nullptr;
+        return hipSuccess;
+    }
+    // accumulates the runs that have completed (wait: block until all have)
+    hipError_t harvest(bool wait)
+    {
+        while (!pending.empty()) {
+            auto pr = pending.front();
+            if (wait) {
+                hipError_t e = hipEventSynchronize(pr.second);
+                if (e != hipSuccess) return e;
+            } else if (hipEventQuery(pr.second) != hipSuccess) {
+                break;
+            }
+            float f = 0.f;
+            hipError_t e = hipEventElapsedTime(&f, pr.first, pr.second);
+            if (e != hipSuccess) return e;
+            ms += f;
+            pool.push_back(pr.first);
+            pool.push_back(pr.second);
+            pending.pop_front();
+        }
+        return hipSuccess;
+    }
+    void destroy()
+    {
+        for (auto& pr : pending) {
+            pool.push_back(pr.first);
+            pool.push_back(pr.second);
+        }
+        pending.clear();
+        if (open) pool.push_back(open);
+        open = nullptr;
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+};
+
 struct slbm_ctx {
     // problem
     int nx = 0, ny = 0;
@@ -42,7 +124,8 @@ struct slbm_ctx {
     double *g = nullptr, *Efield = nullptr, *target = nullptr, *snap = nullptr, *dbar = nullptr,
            *r = nullptr, *fbar = nullptr, *dJdF = nullptr, *dJdE = nullptr, *adisp = nullptr,
            *modes = nullptr, *fixedF = nullptr, *work = nullptr, *partial = nullptr, *scal = nullptr,
-           *ctrl = nullptr;
+           *ctrl = nullptr,
+           *asrc = nullptr;  // adjoint source field (2 planes): the objective's r, or a VJP cotangent
     uint8_t* obs = nullptr;
     int32_t* code = nullptr;
     BNode* bnodes = nullptr;
@@ -74,6 +157,7 @@ struct slbm_ctx {
     double E_cur = 0;       // uniform E of the current control
     double alpha_sq = 0;    // E_SCALAR_SQ control value
     double J = 0;
+    LaunchTimer lt;         // optional device time of the fused launches (solid_lbm_set_launch_timing)
     std::string err;
     std::vector<void*> allocs;
 };
@@ -555,12 +639,13 @@ int tangent_loop(slbm_ctx* c, const TangentArgs& base, int64_t* t_out, int* x_ou
 int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, int64_t* t_out,
              double* res_out, bool* conv_out, double* dev_ms = nullptr, int* x_out = nullptr)
 {
+    c->lt.reset();
     double** bufs = adjoint ? c->abuf : c->fbuf;
     hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(1), 0, c->stream, c->status);
     HIPCHK(c, hipGetLastError());
     SweepArgs a = base_args(c);
     if (adjoint) {
-        a.g = c->r;
+        a.g = c->asrc;
         a.scale = c->dx2 / c->cbar;
     } else {
         a.g = c->g;
@@ -592,6 +677,7 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
             if (!check && T > 1 && plain >= T) {
                 a.src = bufs[cur];
                 a.dst = bufs[cur ^ 1];
+                HIPCHK(c, c->lt.before(c->stream, T));
                 launch_fused(c, adjoint, a, T);
                 cur ^= 1;
                 s += T;
@@ -601,11 +687,13 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
                 const int k = (int)std::min<int64_t>(plain, TL);
                 a.src = bufs[cur];
                 a.dst = bufs[cur ^ 1];
+                HIPCHK(c, c->lt.before(c->stream, k));
                 launch_tile(c, adjoint, a, k, TL);
                 cur ^= 1;
                 s += k;
                 continue;
             }
+            HIPCHK(c, c->lt.close(c->stream));
             a.src = bufs[cur];
             a.dst = bufs[cur ^ 1];
             launch_sweep(c, adjoint, a, check);
@@ -619,6 +707,8 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
             ++s;
         }
         HIPCHK(c, hipGetLastError());
+        HIPCHK(c, c->lt.close(c->stream));
+        HIPCHK(c, c->lt.harvest(false));
         if (use_tol) {
             int slot = chunk & 1;
             HIPCHK(c, hipMemcpyAsync(&c->h_status[slot], c->status, sizeof(Status), hipMemcpyDeviceToHost,
@@ -639,8 +729,10 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
             ++chunk;
         }
     }
+    HIPCHK(c, c->lt.close(c->stream));
     HIPCHK(c, hipEventRecord(c->t1, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, c->lt.harvest(true));
     if (dev_ms) {
         float f = 0.f;
         HIPCHK(c, hipEventElapsedTime(&f, c->t0, c->t1));
@@ -856,6 +948,9 @@ int do_primal(slbm_ctx* c, slbm_solve_info* info)
         info->wall_s = std::chrono::duration<double>(w1 - w0).count();
         info->device_ms = dms;
         info->converged = conv ? 1 : 0;
+        info->fused_launches = c->lt.launches;
+        info->fused_sweeps = c->lt.sweeps;
+        info->fused_ms = c->lt.ms;
     }
     return (use_tol && !conv) ? SLBM_NOT_CONVERGED : SLBM_OK;
 }
@@ -871,35 +966,48 @@ int adjoint_prepare(slbm_ctx* c)
     return SLBM_OK;
 }
 
-// Periodic domains: the displacement has zero mean by construction, so the
-// mean of the adjoint source lies outside the range of the solution map; it is
-// removed (per component) so that the adjoint's translation mode stays at rest.
+// Periodic domains: the displacement has zero mean by construction (the
+// translations are the kernel of the torus problem), so the mean of the
+// adjoint source does not depend on the control and lies outside the range of
+// the solution map; it is removed per component (the compatibility condition
+// of eq. zero_mean_projection), which keeps the adjoint's translation mode at
+// rest.  Works on c->asrc; r = d - d* itself is left as it is.
 int project_source(slbm_ctx* c)
 {
     if (c->masked) return SLBM_OK;
     double m[2];
     int rc;
     for (int k = 0; k < 2; ++k) {
-        if ((rc = dot(c, c->r + k * c->N, nullptr, c->N, &m[k]))) return rc;
+        if ((rc = dot(c, c->asrc + k * c->N, nullptr, c->N, &m[k]))) return rc;
         m[k] /= (double)c->N;
     }
     HIPCHK(c, hipMemcpyAsync(c->work, m, 2 * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->r, (const double*)c->work,
-                       (const int32_t*)nullptr, c->N, 1.0, c->r);
+    hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->asrc,
+                       (const double*)c->work, (const int32_t*)nullptr, c->N, 1.0, c->asrc);
     HIPCHK(c, hipGetLastError());
     return SLBM_OK;
 }
 
+// Adjoint source of the objective (eq. discrete_J): r of the last completed
+// primal solve, projected on periodic domains.
+int objective_source(slbm_ctx* c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->asrc, c->r, 2 * c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return project_source(c);
+}
+
 int adjoint_finalize(slbm_ctx* c, int X, double scale);
 
+// scale_override > 0: c->asrc already holds a cotangent (adjoint_solve_vjp),
+// used with that scale; otherwise the objective's source is formed from r.
 int do_adjoint(slbm_ctx* c, slbm_solve_info* info, double scale_override = -1.0)
 {
     if (!c->prim_done) return fail(c, SLBM_ESTATE, "adjoint_solve needs a completed primal_solve");
     auto w0 = std::chrono::steady_clock::now();
     int rc = adjoint_prepare(c);
     if (rc) return rc;
-    if ((rc = project_source(c))) return rc;
+    if ((rc = scale_override > 0.0 ? project_source(c) : objective_source(c))) return rc;
     const double saved_cbar = c->cbar;
     if (scale_override > 0.0) c->cbar = c->dx2 / scale_override;  // run_loop uses dx^2 / cbar
     int64_t t;
@@ -920,6 +1028,9 @@ int do_adjoint(slbm_ctx* c, slbm_solve_info* info, double scale_override = -1.0)
         info->wall_s = std::chrono::duration<double>(w1 - w0).count();
         info->device_ms = dms;
         info->converged = conv ? 1 : 0;
+        info->fused_launches = c->lt.launches;
+        info->fused_sweeps = c->lt.sweeps;
+        info->fused_ms = c->lt.ms;
     }
     return (use_tol && !conv) ? SLBM_NOT_CONVERGED : SLBM_OK;
 }
@@ -932,12 +1043,12 @@ int adjoint_finalize(slbm_ctx* c, int X, double scale)
     bool wantE = c->kind == SLBM_CTRL_E_NODAL || c->kind == SLBM_CTRL_E_SCALAR_SQ;
     if (c->masked)
         hipLaunchKernelGGL(k_adjoint_finalize<true>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->abuf[X],
-                           c->abuf[X ^ 1], c->code, c->bnodes, c->fbar, c->r, c->g,
+                           c->abuf[X ^ 1], c->code, c->bnodes, c->fbar, c->asrc, c->g,
                            c->efield_on ? c->Efield : (const double*)nullptr, c->E_cur, c->nu, wantE ? 1 : 0,
                            c->nx, c->ny, c->N, c->inv_nx, scale, c->dx2, c->dJdF, c->dJdE, c->adisp);
     else
         hipLaunchKernelGGL(k_adjoint_finalize<false>, dim3(grid_of(c->N)), dim3(kBlock), 0, c->stream, c->abuf[X],
-                           c->abuf[X ^ 1], c->code, c->bnodes, c->fbar, c->r, c->g,
+                           c->abuf[X ^ 1], c->code, c->bnodes, c->fbar, c->asrc, c->g,
                            c->efield_on ? c->Efield : (const double*)nullptr, c->E_cur, c->nu, wantE ? 1 : 0,
                            c->nx, c->ny, c->N, c->inv_nx, scale, c->dx2, c->dJdF, c->dJdE, c->adisp);
     HIPCHK(c, hipGetLastError());
@@ -1162,6 +1273,7 @@ int solid_lbm_init(const slbm_problem* p, slbm_ctx** out)
     A(&c->snap, P2);
     A(&c->dbar, P2);
     A(&c->r, P2);
+    A(&c->asrc, P2);
     A(&c->dJdF, P2);
     A(&c->adisp, P2);
     A(&c->work, P8 > 1024 ? P8 : 1024);
@@ -1293,7 +1405,7 @@ int solid_lbm_run_adjoint_steps(slbm_ctx* c, int64_t n)
     if (n < 0) return fail(c, SLBM_EINVAL, "n must be >= 0");
     int rc = adjoint_prepare(c);
     if (rc) return rc;
-    if ((rc = project_source(c))) return rc;
+    if ((rc = objective_source(c))) return rc;
     if (n == 0) return SLBM_OK;
     int64_t t;
     double res;
@@ -1358,11 +1470,11 @@ int solid_lbm_time_sweeps(slbm_ctx* c, int32_t adjoint, int64_t n, double* ms)
     if (!adjoint && !c->prim_valid) return fail(c, SLBM_ESTATE, "no primal state");
     if (adjoint && !c->adj_done) {
         int rc = adjoint_prepare(c);
-        if (rc) return rc;
+        if (rc || (rc = objective_source(c))) return rc;
     }
     hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(1), 0, c->stream, c->status);
     SweepArgs a = base_args(c);
-    a.g = adjoint ? c->r : c->g;
+    a.g = adjoint ? c->asrc : c->g;
     a.scale = c->dx2 / c->cbar;
     double** bufs = adjoint ? c->abuf : c->fbuf;
     int cur = adjoint ? c->adj_cur : c->prim_cur;
@@ -1407,11 +1519,11 @@ int adjoint_solve_vjp(slbm_ctx* c, const double* d_cot, double* grad, int32_t pt
     if (!c) return SLBM_EINVAL;
     if (!d_cot || !grad) return fail(c, SLBM_EINVAL, "d_cot and grad are required");
     if (!c->prim_done) return fail(c, SLBM_ESTATE, "adjoint_solve_vjp needs a completed primal_solve");
-    int rc = copy_in(c, c->r, d_cot, 2 * c->N * sizeof(double), ptr_kind);
+    int rc = copy_in(c, c->asrc, d_cot, 2 * c->N * sizeof(double), ptr_kind);
     if (rc) return rc;
     // outside the domain the displacement is not defined: its cotangent is ignored
-    hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->r, (const double*)nullptr,
-                       c->masked ? c->code : (const int32_t*)nullptr, c->N, 1.0, c->r);
+    hipLaunchKernelGGL(k_axpb2, dim3(grid_of(2 * c->N)), dim3(kBlock), 0, c->stream, c->asrc,
+                       (const double*)nullptr, c->masked ? c->code : (const int32_t*)nullptr, c->N, 1.0, c->asrc);
     HIPCHK(c, hipGetLastError());
     rc = do_adjoint(c, info, 1.0);
     if (rc < 0) return rc;
@@ -1565,6 +1677,13 @@ int solid_lbm_set_tuning(slbm_ctx* c, int32_t steps_per_launch, int32_t rows_per
     return SLBM_OK;
 }
 
+int solid_lbm_set_launch_timing(slbm_ctx* c, int32_t on)
+{
+    if (!c) return SLBM_EINVAL;
+    c->lt.on = on != 0;
+    return SLBM_OK;
+}
+
 const char* solid_lbm_last_error(const slbm_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
 
 void solid_lbm_destroy(slbm_ctx* c)
@@ -1576,6 +1695,7 @@ void solid_lbm_destroy(slbm_ctx* c)
     if (c->h_status) (void)hipHostFree(c->h_status);
     for (hipEvent_t e : {c->ev[0], c->ev[1], c->t0, c->t1})
         if (e) (void)hipEventDestroy(e);
+    c->lt.destroy();
     delete c;
 }
 
@@ -1670,7 +1790,7 @@ int batch_tables(slbm_batch* b, bool adjoint)
             pa.g = c->g;
             aa.src = c->abuf[par];
             aa.dst = c->abuf[par ^ 1];
-            aa.g = c->r;
+            aa.g = c->asrc;
             aa.scale = c->dx2 / c->cbar;
             I.prim[par] = pa;
             I.adj[par] = aa;
@@ -1978,7 +2098,7 @@ int batch_adjoint(slbm_batch* b, double* const* grads, int ptr_kind, slbm_solve_
     for (int i = 0; i < B; ++i) {
         slbm_ctx* c = b->ctx[i];
         if (!c->prim_done) return bfail(b, SLBM_ESTATE, "instance " + std::to_string(i) + ": no completed primal");
-        if ((rc = adjoint_prepare(c)) || (rc = project_source(c)))
+        if ((rc = adjoint_prepare(c)) || (rc = objective_source(c)))
             return bfail(b, rc, "instance " + std::to_string(i) + ": " + c->err);
     }
     std::vector<int64_t> t;
@@ -2077,6 +2197,7 @@ int solid_lbm_batch_init(const slbm_problem* problems, int32_t count, slbm_batch
         for (double* a : {c->fbuf[0], c->fbuf[1], c->abuf[0], c->abuf[1]})
             if (!rc) rc = fill(c, a, 8 * c->N, 0.0);
         if (!rc) rc = fill(c, c->r, 2 * c->N, 0.0);
+        if (!rc) rc = fill(c, c->asrc, 2 * c->N, 0.0);
         c->adj_valid = true;
     }
     if (rc || hipStreamSynchronize(b->stream) != hipSuccess) {

@@ -189,11 +189,14 @@ def lbfgs(fun, x0, eps=1e-10, eps_alpha=2.2e-16, lam0=1.0, m_max=50, k_max=100, 
 
 
 def gpu_objective(ctx):
-    """fun(x) -> (J, grad) through the HIP library's objective_and_grad."""
+    """fun(x) -> (J, grad) through the HIP library's objective_and_grad.  A
+    solve that stops at max_steps before tol raises slbm.NotConverged: a
+    non-steady J or gradient would mislead the line search."""
     from . import slbm as S
 
     def fun(x):
         rc, J, grad, pi, ai = S.objective_and_grad(ctx, np.ascontiguousarray(x, dtype=np.float64))
+        S.require_converged(rc, "objective_and_grad", pi if not pi.converged else ai)
         fun.sweeps += pi.sweeps + ai.sweeps
         fun.device_ms += pi.device_ms + ai.device_ms
         return J, np.asarray(grad).reshape(np.shape(x))

@@ -27,6 +27,7 @@ EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_gra
            "solid_lbm_restore_solve", "solid_lbm_objective", "solid_lbm_set_control",
            "solid_lbm_run_steps", "solid_lbm_run_adjoint_steps", "solid_lbm_get_field",
            "solid_lbm_time_sweeps", "solid_lbm_set_tuning", "solid_lbm_set_tiles", "solid_lbm_set_progress",
+           "solid_lbm_set_launch_timing",
            "solid_lbm_last_error",
            "solid_lbm_destroy",
            "solid_lbm_batch_init", "batch_objective_and_grad", "batch_gradient", "solid_lbm_batch_set_tuning",
@@ -41,6 +42,24 @@ class SlbmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"solid_lbm error {code}: {msg}")
         self.code = code
+
+
+class NotConverged(SlbmError):
+    """A solve stopped at max_steps before its residual reached tol
+    (SLBM_NOT_CONVERGED): its outputs exist but are not a steady state."""
+
+    def __init__(self, what, info=None):
+        extra = "" if info is None else f" (steps {info.steps}, residual {info.residual:.3e})"
+        super().__init__(NOT_CONVERGED, f"{what}: max_steps reached before tol{extra}")
+        self.info = info
+
+
+def require_converged(rc, what, info=None):
+    """Raises NotConverged for rc == SLBM_NOT_CONVERGED (the wrappers whose
+    results feed gradients, optimisers or training data call this)."""
+    if rc == NOT_CONVERGED:
+        raise NotConverged(what, info)
+    return rc
 
 
 class _Problem(ctypes.Structure):
@@ -59,7 +78,8 @@ class _Problem(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("sweeps", ctypes.c_int64), ("residual", ctypes.c_double),
-                ("wall_s", ctypes.c_double), ("device_ms", ctypes.c_double), ("converged", ctypes.c_int32)]
+                ("wall_s", ctypes.c_double), ("device_ms", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("fused_launches", ctypes.c_int64), ("fused_sweeps", ctypes.c_int64), ("fused_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -94,6 +114,7 @@ def _load():
                                   ctypes.c_int32, info]
     lib.solid_lbm_set_tiles.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.solid_lbm_set_progress.argtypes = [P, PROGRESS_FN, P, ctypes.c_double]
+    lib.solid_lbm_set_launch_timing.argtypes = [P, ctypes.c_int32]
     lib.adjoint_solve_vjp.argtypes = [P, P, P, ctypes.c_int32, info]
     lib.objective_and_grad_from.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double), P, ctypes.c_int32, info, info]
     lib.solid_lbm_restore_solve.argtypes = [P, P, P, ctypes.c_int32]
@@ -397,6 +418,11 @@ def solid_lbm_set_progress(ctx, fn=None, every_s=30.0):
     cb = PROGRESS_FN(lambda user, phase, step, res: fn(int(phase), int(step), float(res)))
     ctx._progress = cb                        # keeps the C callback alive with the context
     return _check(ctx, LIB.solid_lbm_set_progress(ctx.handle, cb, None, float(every_s)))
+
+
+def solid_lbm_set_launch_timing(ctx, on=True):
+    """Fused-launch timing of the solve loops (SolveInfo.fused_launches / fused_sweeps / fused_ms)."""
+    return _check(ctx, LIB.solid_lbm_set_launch_timing(ctx.handle, 1 if on else 0))
 
 
 def solid_lbm_set_tiles(ctx, tile_w=0, tile_h=0):

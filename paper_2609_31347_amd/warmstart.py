@@ -204,6 +204,8 @@ def solve_batch(cp, fields, tol, chunk=96):
         part = fields[k:k + chunk]
         batch = S.solid_lbm_batch_init([plate_problem(cp, tol) for _ in part])
         rc, J, _, pi, _ = S.batch_objective_and_grad(batch, list(part), want_grad=False)
+        # training targets must be steady states
+        S.require_converged(rc, "batched plate solves", next((x for x in pi if not x.converged), None))
         for c in batch.contexts:
             out.append(S.solid_lbm_get_field(c, S.FIELD_DISP))
         steps += [x.steps for x in pi]

@@ -1,5 +1,6 @@
 """Host-side parts of the benchmark's contract (no GPU): one GPU only, and the
-stored per-launch traffic figures are plausible for fused launches."""
+stored per-launch traffic figures are plausible for fused launches and tied to
+the kernel sources they were measured with."""
 import os
 import subprocess
 import sys
@@ -17,8 +18,16 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_traffic_per_launch_lies_between_the_state_and_the_single_step_bytes():
     sys.path.insert(0, ROOT)
     import bench
-    for (n, T, H), bytes_per_launch in bench.TRAFFIC_BYTES.items():
-        per_node_step = bytes_per_launch / (n * n * T)
+    for (n, T, H), e in bench.TRAFFIC.items():
+        per_node = e["bytes"] / (n * n)
         # at least the 128 B of state read and written once per launch, at most
-        # the 144 B per step of single-step sweeps
-        assert 128.0 / T <= per_node_step < bench.BYTES_PER_NODE, (n, T, H, per_node_step)
+        # the 144 B per step of T single-step sweeps
+        assert 128.0 <= per_node < bench.BYTES_PER_NODE * T, (n, T, H, per_node)
+        assert len(e["sources"]) == 16
+
+
+def test_kernel_source_hash_names_the_sweep_sources():
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and h == bench.kernel_source_hash()

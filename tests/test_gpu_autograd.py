@@ -124,5 +124,7 @@ def test_autograd_full_size_nodal_gradient(env):
     d = Fo.steady_disp(-F_ref * dx2, 1.0, 0.3, H)
     cb = (tgt ** 2).sum() * dx2
     exact = Fo.grad_g(d - tgt, 1.0, 0.3, H) * dx2 / cb * dx2
-    assert rel(alpha.grad.cpu().numpy(), exact - exact.mean((1, 2), keepdims=True)) < 1e-6
+    # the slowest transverse modes decay by about 0.86 per check interval at
+    # N = 1024, so the K-lag test at 1e-10 leaves ~1e-9 (reading C6)
+    assert rel(alpha.grad.cpu().numpy(), exact - exact.mean((1, 2), keepdims=True)) < 1e-8
     assert solver.last_info.converged and solver.last_adjoint_info.converged

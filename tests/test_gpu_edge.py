@@ -161,9 +161,10 @@ def test_non_finite_control_is_rejected_and_the_context_survives(S, bad):
     assert rc == 0
     badF = F.copy()
     badF[1, 3, 5] = bad
-    for arg in (badF, torch.tensor(badF, device="cuda")):
+    dev_grad = torch.zeros(2 * n * n, dtype=torch.float64, device="cuda")
+    for arg, gout in ((badF, None), (torch.tensor(badF, device="cuda"), dev_grad)):
         with pytest.raises(S.SlbmError) as e:
-            S.objective_and_grad(ctx, arg)
+            S.objective_and_grad(ctx, arg, grad=gout)
         assert e.value.code == S.ENONFINITE
         assert S.solid_lbm_objective(ctx) == J0
     rc, J1, g1, _, _ = S.objective_and_grad(ctx, F)

@@ -333,7 +333,8 @@ void launch_fused(slbm_ctx* c, bool adjoint, const SweepArgs& s, int T)
     a.scale = s.scale;
     a.H = fused_rows(c, T);
     int V = 64 - 2 * T;
-    dim3 grid((unsigned)((c->nx + V - 1) / V), (unsigned)((c->ny + a.H - 1) / a.H)), block(64);
+    a.strips = (c->nx + V - 1) / V;
+    dim3 grid((unsigned)(a.strips * ((c->ny + a.H - 1) / a.H))), block(64);
 #define TB_CASE(TT)                                                                                   \
     case TT:                                                                                          \
         if (adjoint) hipLaunchKernelGGL((k_sweep_tb<TT, true>), grid, block, 0, c->stream, a);        \
@@ -1804,6 +1805,7 @@ int batch_tables(slbm_batch* b, bool adjoint)
                 t.nx = c->nx;
                 t.ny = c->ny;
                 t.H = std::min(H, c->ny);
+                t.strips = (c->nx + (64 - 2 * std::max(T, 1)) - 1) / (64 - 2 * std::max(T, 1));
                 t.N = c->N;
                 t.k11 = s.k11;
                 t.ks = s.ks;

@@ -791,9 +791,25 @@ struct TBArgs {
     const double* __restrict__ g;   // primal: forcing; adjoint: r
     const Status* __restrict__ status;
     int32_t nx, ny, H;
+    int32_t strips;                 // strips per row block (single-problem launches)
     int64_t N;
     double k11, ks, kd, scale;
 };
+
+// Compute dies (XCDs) of the device: the dispatcher hands consecutive
+// workgroups of a launch to the XCDs in turn, and each XCD has its own L2.
+constexpr int kXcds = 8;
+
+// Workgroup b of a launch of n -> its place in an order that gives every XCD
+// one contiguous run of the n work items (so neighbours in that order, which
+// read the same halo lines, run on the same XCD at the same time and the
+// second read hits that XCD's L2).  A bijection of [0, n).
+__device__ __forceinline__ int xcd_order(int b, int n)
+{
+    const int x = b % kXcds, j = b / kXcds;
+    const int q = n / kXcds, rem = n % kXcds;
+    return x * q + min(x, rem) + j;
+}
 
 // Whole-wave lane shifts of a double: up = value of lane l-1, down = value of
 // lane l+1 (the end lanes keep their own value; they are halo lanes).
@@ -1000,11 +1016,15 @@ __device__ __forceinline__ void tb_strip(const TBArgs& a, int sx, int sy)
     }
 }
 
+// One wave per strip of a row block, in row-major order of (row block, strip)
+// handed out XCD by XCD: the strips of a row block, which share their halo
+// columns with their neighbours, run together on one XCD.
 template <int T, bool ADJ>
 __global__ __launch_bounds__(64) void k_sweep_tb(TBArgs a)
 {
     if (a.status->stop) return;
-    tb_strip<T, ADJ>(a, blockIdx.x, blockIdx.y);
+    const int t = xcd_order(blockIdx.x, gridDim.x);
+    tb_strip<T, ADJ>(a, t % a.strips, t / a.strips);
 }
 
 // ---------------------------------------------------------------- fused sweeps, plates and E fields

@@ -338,6 +338,22 @@ int batch_objective_and_grad(slbm_batch *batch, const double *const *controls, d
                              double *const *grads, int32_t ptr_kind, slbm_solve_info *primal_info,
                              slbm_solve_info *adjoint_info);
 
+/* No-allocation variant of batch_objective_and_grad, for callers that cannot
+ * allocate device memory during the call (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and return codes.  batch_objective_and_grad builds the work-lists of its
+ * fused launches (one (instance, strip or tile) entry per work item) in
+ * device memory that the batch allocates and grows on demand; this variant
+ * writes them into a static device array of 65536 entries (512 KiB) that
+ * the library holds on each GPU it runs on until the process ends, and calls
+ * no allocating routine.  SLBM_EINVAL, before any work, if the batch's
+ * current launch shape needs more entries (the message says how many).  The
+ * array is rewritten by every call: calls that overlap on one GPU (other
+ * threads, other streams) race on it and must be serialised by the caller. */
+int batch_objective_and_grad_noalloc(slbm_batch *batch, const double *const *controls, double *J,
+                                     double *const *grads, int32_t ptr_kind, slbm_solve_info *primal_info,
+                                     slbm_solve_info *adjoint_info);
+
 /* Adjoints and gradients of every instance at the state of the last
  * batch_objective_and_grad call (made with grads = NULL, so that a caller can
  * report between the two halves): grads[i] (length per the instance's

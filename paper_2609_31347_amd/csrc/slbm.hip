@@ -10,6 +10,7 @@
 #include <cstring>
 #include <string>
 #include <deque>
+#include <mutex>
 #include <vector>
 
 #include "solid_lbm.h"
@@ -1713,6 +1714,9 @@ struct slbm_batch {
     int2* d_all = nullptr;         // every instance: (instance, block) of a single-step sweep
     int2* d_tb = nullptr;          // wave-strip instances: (instance, strip) of a fused launch
     int2* d_tile = nullptr;        // tiled instances: (instance, tile) of a fused launch
+    int2* static_tables = nullptr; // non-null during batch_objective_and_grad_noalloc: tables go there
+    const int2* cur_tb = nullptr;  // tables of the current launches (own or static)
+    const int2* cur_tile = nullptr;
     int64_t n_all = 0, n_tb = 0, tb_cap = 0, n_tile = 0, tile_cap = 0;
     int tb_T = -1, tb_H = 0;       // tuning (-1 / 0: automatic)
     int T = 1, H = 0;              // effective fused shape of the current tables
@@ -1766,6 +1770,55 @@ void batch_shape(slbm_batch* b, int* T, int* H)
     if (t > 1 && h < 2 * t) h = 2 * t;
     *T = t;
     *H = h;
+}
+
+// ---- launch tables without allocation (batch_objective_and_grad_noalloc)
+// The fused launches' work-lists (strip and tile tables) of a no-allocation
+// call live in this file-scope device array instead of memory the batch
+// allocates.  Each device holds its own copy for the life of the process; in
+// host code `scratch` only names the symbol: kernels and copies take the
+// device address from hipGetSymbolAddress (static_tables_of), never the name.
+constexpr int64_t kStaticTableEntries = 65536;   // (instance, item) pairs: 512 KiB
+static __device__ __align__(256) int2 scratch[kStaticTableEntries];
+
+std::mutex g_scratch_mu;
+std::vector<int2*> g_scratch_dev;   // per device id: address of `scratch` there (null = not resolved)
+
+// Device address of the static table array on the current device (resolved
+// once per device, with that device current).
+int static_tables_of(slbm_batch* b, int2** out)
+{
+    int dev = -1;
+    BHIPCHK(b, hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        BHIPCHK(b, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_dev[dev] = static_cast<int2*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return SLBM_OK;
+}
+
+// Entries of the fused strip and tile tables for the current tuning.
+int64_t batch_table_entries(slbm_batch* b)
+{
+    int T, H;
+    batch_shape(b, &T, &H);
+    if (T <= 1) return 0;
+    const int tw = std::max(2, 32 - 2 * T);
+    int64_t n = 0;
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        const slbm_ctx* c = b->ctx[i];
+        if (b->tiled[i]) {
+            n += (int64_t)((c->nx + tw - 1) / tw) * ((c->ny + tw - 1) / tw);
+        } else {
+            const int V = 64 - 2 * T, h = std::min(H, c->ny);
+            n += (int64_t)((c->nx + V - 1) / V) * ((c->ny + h - 1) / h);
+        }
+    }
+    return n;
 }
 
 // (Re)builds the per-instance table for the current controls and the fused
@@ -1858,24 +1911,38 @@ int batch_tables(slbm_batch* b, bool adjoint)
     }
     (void)adjoint;
     BHIPCHK(b, hipMemcpyAsync(b->d_inst, b->h_inst.data(), B * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream));
-    if ((int64_t)tb.size() > b->tb_cap) {
-        void* q = nullptr;
-        int rc = balloc(b, &q, tb.size() * sizeof(int2));
-        if (rc) return rc;
-        b->d_tb = (int2*)q;
-        b->tb_cap = (int64_t)tb.size();
+    int2* tb_dst = nullptr;
+    int2* tl_dst = nullptr;
+    if (b->static_tables) {
+        // no-allocation path: both tables in the static device array
+        if ((int64_t)(tb.size() + tl.size()) > kStaticTableEntries)
+            return bfail(b, SLBM_EINVAL, "launch tables exceed the static table");
+        tb_dst = b->static_tables;
+        tl_dst = b->static_tables + tb.size();
+    } else {
+        if ((int64_t)tb.size() > b->tb_cap) {
+            void* q = nullptr;
+            int rc = balloc(b, &q, tb.size() * sizeof(int2));
+            if (rc) return rc;
+            b->d_tb = (int2*)q;
+            b->tb_cap = (int64_t)tb.size();
+        }
+        if ((int64_t)tl.size() > b->tile_cap) {
+            void* q = nullptr;
+            int rc = balloc(b, &q, tl.size() * sizeof(int2));
+            if (rc) return rc;
+            b->d_tile = (int2*)q;
+            b->tile_cap = (int64_t)tl.size();
+        }
+        tb_dst = b->d_tb;
+        tl_dst = b->d_tile;
     }
     if (!tb.empty())
-        BHIPCHK(b, hipMemcpyAsync(b->d_tb, tb.data(), tb.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
-    if ((int64_t)tl.size() > b->tile_cap) {
-        void* q = nullptr;
-        int rc = balloc(b, &q, tl.size() * sizeof(int2));
-        if (rc) return rc;
-        b->d_tile = (int2*)q;
-        b->tile_cap = (int64_t)tl.size();
-    }
+        BHIPCHK(b, hipMemcpyAsync(tb_dst, tb.data(), tb.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
     if (!tl.empty())
-        BHIPCHK(b, hipMemcpyAsync(b->d_tile, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+        BHIPCHK(b, hipMemcpyAsync(tl_dst, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+    b->cur_tb = tb_dst;
+    b->cur_tile = tl_dst;
     if (!tl.empty() && !b->tile_attr) {
         const int lmax = (int)tile_lds_bytes(kTileMaxNodes, true);
         BHIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile_batch<false>),
@@ -1910,9 +1977,9 @@ void launch_batch_fused(slbm_batch* b, bool adjoint, int pp)
 #define BTB_CASE(TT)                                                                                       \
     case TT:                                                                                               \
         if (adjoint) hipLaunchKernelGGL((k_sweep_tb_batch<TT, true>), grid, block, 0, b->stream, b->d_inst, \
-                                        b->d_tb, pp);                                                      \
+                                        b->cur_tb, pp);                                                    \
         else hipLaunchKernelGGL((k_sweep_tb_batch<TT, false>), grid, block, 0, b->stream, b->d_inst,       \
-                                b->d_tb, pp);                                                              \
+                                b->cur_tb, pp);                                                            \
         break;
     switch (b->T) {
         BTB_CASE(2)
@@ -1930,9 +1997,9 @@ void launch_batch_tile(slbm_batch* b, bool adjoint, int pl)
     const size_t lds = tile_lds_bytes(R, b->any_masked);
     dim3 grid((unsigned)b->n_tile), block(kTileBlock);
     if (adjoint)
-        hipLaunchKernelGGL(k_sweep_tile_batch<true>, grid, block, lds, b->stream, b->d_inst, b->d_tile, pl, b->T);
+        hipLaunchKernelGGL(k_sweep_tile_batch<true>, grid, block, lds, b->stream, b->d_inst, b->cur_tile, pl, b->T);
     else
-        hipLaunchKernelGGL(k_sweep_tile_batch<false>, grid, block, lds, b->stream, b->d_inst, b->d_tile, pl, b->T);
+        hipLaunchKernelGGL(k_sweep_tile_batch<false>, grid, block, lds, b->stream, b->d_inst, b->cur_tile, pl, b->T);
 }
 
 // Advances every instance from buffer 0 in lock-step (step index s), each
@@ -2216,6 +2283,25 @@ int batch_objective_and_grad(slbm_batch* b, const double* const* controls, doubl
     if (!b) return SLBM_EINVAL;
     if (!controls || !J) return bfail(b, SLBM_EINVAL, "controls and J are required");
     return batch_solve(b, controls, ptr_kind, J, grads, primal_info, adjoint_info);
+}
+
+int batch_objective_and_grad_noalloc(slbm_batch* b, const double* const* controls, double* J,
+                                     double* const* grads, int32_t ptr_kind, slbm_solve_info* primal_info,
+                                     slbm_solve_info* adjoint_info)
+{
+    if (!b) return SLBM_EINVAL;
+    if (!controls || !J) return bfail(b, SLBM_EINVAL, "controls and J are required");
+    const int64_t need = batch_table_entries(b);
+    if (need > kStaticTableEntries)
+        return bfail(b, SLBM_EINVAL, "launch tables need " + std::to_string(need) + " entries; the static table holds " +
+                                         std::to_string(kStaticTableEntries));
+    int2* tables = nullptr;
+    int rc = static_tables_of(b, &tables);
+    if (rc) return rc;
+    b->static_tables = tables;
+    rc = batch_solve(b, controls, ptr_kind, J, grads, primal_info, adjoint_info);
+    b->static_tables = nullptr;
+    return rc;
 }
 
 int batch_gradient(slbm_batch* b, double* const* grads, int32_t ptr_kind, slbm_solve_info* adjoint_info)

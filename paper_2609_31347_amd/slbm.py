@@ -30,7 +30,8 @@ EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_gra
            "solid_lbm_set_launch_timing",
            "solid_lbm_last_error",
            "solid_lbm_destroy",
-           "solid_lbm_batch_init", "batch_objective_and_grad", "batch_gradient", "solid_lbm_batch_set_tuning",
+           "solid_lbm_batch_init", "batch_objective_and_grad", "batch_objective_and_grad_noalloc",
+           "batch_gradient", "solid_lbm_batch_set_tuning",
            "solid_lbm_batch_time_sweeps", "solid_lbm_batch_instance", "solid_lbm_batch_last_error",
            "solid_lbm_batch_destroy")
 
@@ -127,6 +128,7 @@ def _load():
     lib.batch_objective_and_grad.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, info, info]
     lib.batch_gradient.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, info]
+    lib.batch_objective_and_grad_noalloc.argtypes = lib.batch_objective_and_grad.argtypes
     lib.solid_lbm_batch_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.solid_lbm_batch_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_batch_instance.argtypes = [P, ctypes.c_int32]
@@ -479,8 +481,10 @@ def solid_lbm_batch_init(problems):
     return Batch(h, problems)
 
 
-def batch_objective_and_grad(batch, controls, grads=None, want_grad=True):
-    """Returns (rc, J (array), grads (list), primal infos, adjoint infos)."""
+def batch_objective_and_grad(batch, controls, grads=None, want_grad=True, noalloc=False):
+    """Returns (rc, J (array), grads (list), primal infos, adjoint infos).
+    noalloc: call batch_objective_and_grad_noalloc (launch tables in the
+    library's static device array; nothing is allocated during the call)."""
     B = len(batch)
     keep = []
     cptr = (ctypes.c_void_p * B)()
@@ -509,8 +513,14 @@ def batch_objective_and_grad(batch, controls, grads=None, want_grad=True):
                 raise ValueError("controls and grads must live in the same memory kind")
     J = (ctypes.c_double * B)()
     pi, ai = (SolveInfo * B)(), (SolveInfo * B)()
-    rc = _bcheck(batch, LIB.batch_objective_and_grad(batch.handle, cptr, J, gptr, kind, pi, ai))
+    fn = LIB.batch_objective_and_grad_noalloc if noalloc else LIB.batch_objective_and_grad
+    rc = _bcheck(batch, fn(batch.handle, cptr, J, gptr, kind, pi, ai))
     return rc, np.array(J[:]), grads, list(pi), list(ai)
+
+
+def batch_objective_and_grad_noalloc(batch, controls, grads=None, want_grad=True):
+    """batch_objective_and_grad without device allocation during the call."""
+    return batch_objective_and_grad(batch, controls, grads, want_grad, noalloc=True)
 
 
 def batch_gradient(batch, grads=None):

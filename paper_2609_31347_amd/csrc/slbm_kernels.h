@@ -1299,12 +1299,14 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
     }
 }
 
+// Tiles in row-major order, handed out XCD by XCD (xcd_order): neighbouring
+// tiles, whose regions overlap by the halo, load them on the same L2.
 template <bool MASKED, bool EFIELD, bool ADJ>
 __global__ __launch_bounds__(kTileBlock) void k_sweep_tile(TileArgs a)
 {
     if (a.status->stop) return;
     extern __shared__ __align__(16) double lds[];    // 8 planes of RX * RY doubles (2 copies for plates), then staged records
-    tile_body<MASKED, EFIELD, ADJ>(a, blockIdx.x, lds);
+    tile_body<MASKED, EFIELD, ADJ>(a, xcd_order(blockIdx.x, gridDim.x), lds);
 }
 
 }  // namespace slbm

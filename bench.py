@@ -64,6 +64,12 @@ def parse():
     ap.add_argument("--instances", type=int, default=96, help="batch mode: number of instances")
     ap.add_argument("--plates", type=int, default=24, help="batch mode: how many of them are plates")
     ap.add_argument("--sequential", action="store_true", help="batch mode: also solve them one by one")
+    ap.add_argument("--persistent", action="store_true",
+                    help="batch mode: the persistent, graph-captured batch kernel instead of host-driven launches")
+    ap.add_argument("--host-too", action="store_true",
+                    help="batch mode with --persistent: also time the host-driven launches on the same mix")
+    ap.add_argument("--sizes", default="64,96,128,192,256,384,512",
+                    help="batch mode: grid sizes the instance seeds draw from")
     ap.add_argument("--sweeps-only", action="store_true",
                     help="batch mode: fixed sweep counts of the whole mix (batched vs one by one) instead of "
                          "solves to tol")
@@ -166,14 +172,15 @@ def lbfgs_mode(args):
     print(json.dumps({"mode": "lbfgs", "eoc_control_error": round(float(eoc), 4)}), flush=True)
 
 
-def batch_instances(count, plates, tol, max_steps=50_000_000):
-    """Seeded mixed batch: instance seeds 0..count-1 draw N from {64, ..., 512};
-    the first count - plates are periodic (two-amplitude control A ~ U[-1,1]^2 or a
-    GRF nodal force, by seed), the rest elliptic plates (semi-axes 1 x 0.6,
-    clamped on the left arc, traction (0, -1e-3) elsewhere, GRF body force)."""
+def batch_instances(count, plates, tol, max_steps=50_000_000, sizes=(64, 96, 128, 192, 256, 384, 512)):
+    """Seeded mixed batch: instance seeds 0..count-1 draw N from `sizes`
+    (default {64, ..., 512}); the first count - plates are periodic
+    (two-amplitude control A ~ U[-1,1]^2 or a GRF nodal force, by seed), the
+    rest elliptic plates (semi-axes 1 x 0.6, clamped on the left arc, traction
+    (0, -1e-3) elsewhere, GRF body force)."""
     from paper_2609_31347_amd import inputs as I
     from paper_2609_31347_amd import slbm as S
-    sizes = (64, 96, 128, 192, 256, 384, 512)
+    sizes = tuple(sizes)
     probs, ctrls = [], []
     for seed in range(count):
         rng = np.random.Generator(np.random.PCG64(seed))
@@ -206,41 +213,68 @@ def batch_mode(args):
     solved one after another."""
     import torch
     from paper_2609_31347_amd import slbm as S
-    from paper_2609_31347_amd.autotune import autotune_batch
+    from paper_2609_31347_amd.autotune import autotune, autotune_batch
     torch.cuda.set_device(0)
     if args.sweeps_only:
         return batch_sweeps(args)
-    probs, ctrls = batch_instances(args.instances, args.plates, args.tol)
+    sizes = [int(v) for v in args.sizes.split(",")]
+    probs, ctrls = batch_instances(args.instances, args.plates, args.tol, sizes=sizes)
     cells = [p["nx"] * p["ny"] for p in probs]
-    batch = S.solid_lbm_batch_init(probs)
-    tune = autotune_batch(batch, ctrls)
-    print(json.dumps({"stage": "tuned", **tune}), flush=True)
-    t0 = time.perf_counter()
-    rc, J, _, pi, _ = S.batch_objective_and_grad(batch, ctrls, want_grad=False)
-    tp = time.perf_counter() - t0
-    print(json.dumps({"stage": "primal", "wall_s": round(tp, 3), "max_steps": int(max(p.steps for p in pi))}),
-          flush=True)
-    rc2, grads, ai = S.batch_gradient(batch)
-    wall = time.perf_counter() - t0
-    print(json.dumps({"stage": "adjoint", "wall_s": round(wall - tp, 3)}), flush=True)
-    lups = sum(c * (p.sweeps + a.sweeps) for c, p, a in zip(cells, pi, ai))
-    out = {"mode": "batch", "instances": len(probs), "plates": args.plates, "tol": args.tol,
-           "total_cells": int(sum(cells)), "rc": rc, "tuning": tune,
+
+    def run_batch(persistent):
+        batch = S.solid_lbm_batch_init(probs)
+        tune = autotune_batch(batch, ctrls)
+        print(json.dumps({"stage": "tuned", "persistent": persistent, **tune}), flush=True)
+        S.solid_lbm_batch_set_persistent(batch, persistent)
+        t0 = time.perf_counter()
+        rc, J, _, pi, _ = S.batch_objective_and_grad(batch, ctrls, want_grad=False)
+        tp = time.perf_counter() - t0
+        print(json.dumps({"stage": "primal", "persistent": persistent, "wall_s": round(tp, 3),
+                          "max_steps": int(max(p.steps for p in pi))}), flush=True)
+        rc2, grads, ai = S.batch_gradient(batch)
+        wall = time.perf_counter() - t0
+        print(json.dumps({"stage": "adjoint", "persistent": persistent, "wall_s": round(wall - tp, 3)}), flush=True)
+        S.require_converged(max(rc, rc2), "batched gradients")
+        lups = sum(c * (p.sweeps + a.sweeps) for c, p, a in zip(cells, pi, ai))
+        rec = {"wall_s": round(wall, 3), "mlups": round(lups / wall / 1e6, 1), "tuning": tune,
+               "primal_device_ms": round(pi[0].device_ms, 1), "adjoint_device_ms": round(ai[0].device_ms, 1),
+               "J": [float(x) for x in J], "steps": [int(p.steps) for p in pi]}
+        if persistent:
+            rec["graph_replays_adjoint"], rec["rounds_adjoint"] = S.solid_lbm_batch_persistent_stats(batch)
+        S.solid_lbm_batch_destroy(batch)
+        return rec, pi, ai
+
+    main_rec, pi, ai = run_batch(args.persistent)
+    wall = main_rec["wall_s"]
+    out = {"mode": "batch", "instances": len(probs), "plates": args.plates, "sizes": sizes, "tol": args.tol,
+           "total_cells": int(sum(cells)), "persistent": args.persistent,
            "all_converged": bool(all(p.converged and a.converged for p, a in zip(pi, ai))),
-           "batch_wall_s": round(wall, 3), "batch_mlups": round(lups / wall / 1e6, 1),
-           "max_steps": int(max(p.steps for p in pi)), "primal_device_ms": round(pi[0].device_ms, 1),
-           "adjoint_device_ms": round(ai[0].device_ms, 1)}
+           "batch_wall_s": wall, "batch_mlups": main_rec["mlups"], "tuning": main_rec["tuning"],
+           "max_steps": int(max(p.steps for p in pi)), "primal_device_ms": main_rec["primal_device_ms"],
+           "adjoint_device_ms": main_rec["adjoint_device_ms"]}
+    if args.persistent:
+        out["graph_replays_adjoint"] = main_rec["graph_replays_adjoint"]
+        out["rounds_adjoint"] = main_rec["rounds_adjoint"]
+    if args.persistent and args.host_too:
+        host_rec, _, _ = run_batch(False)
+        out.update({"host_driven_wall_s": host_rec["wall_s"], "host_driven_mlups": host_rec["mlups"],
+                    "same_steps": host_rec["steps"] == main_rec["steps"],
+                    "J_max_rel_diff": float(max(abs(a - b) / abs(b) for a, b in zip(main_rec["J"], host_rec["J"])))})
     if args.sequential:
+        ctxs = []
+        for p, c in zip(probs, ctrls):                 # set-up and launch-shape tuning outside the timing
+            ctxs.append(S.solid_lbm_init(p))
+            autotune(ctxs[-1], p, c)
         t0 = time.perf_counter()
         seq_lups = 0
-        for k, (p, c, cl) in enumerate(zip(probs, ctrls, cells)):
-            ctx = S.solid_lbm_init(p)
+        for k, (p, c, cl, ctx) in enumerate(zip(probs, ctrls, cells, ctxs)):
             r = S.objective_and_grad(ctx, c)
+            S.require_converged(r[0], f"instance {k}")
             seq_lups += cl * (r[3].sweeps + r[4].sweeps)
             print(json.dumps({"stage": "sequential", "instance": k, "grid": [p["nx"], p["ny"]],
                               "steps": r[3].steps, "wall_s": round(time.perf_counter() - t0, 3)}), flush=True)
-            del ctx
         seq = time.perf_counter() - t0
+        del ctxs
         out.update({"sequential_wall_s": round(seq, 3), "sequential_mlups": round(seq_lups / seq / 1e6, 1),
                     "speedup": round(seq / wall, 2)})
     print(json.dumps(out), flush=True)

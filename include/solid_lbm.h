@@ -370,6 +370,26 @@ int solid_lbm_batch_set_tuning(slbm_batch *batch, int32_t steps_per_launch, int3
  * invalidated (the next solve starts from its control as always). */
 int solid_lbm_batch_time_sweeps(slbm_batch *batch, int32_t adjoint, int64_t n, double *ms);
 
+/* Persistent launches (on != 0): the batch's primal and adjoint loops run as
+ * one persistent kernel (one workgroup of 1024 threads per compute unit, all
+ * resident at once) captured in a HIP graph with a kernel that resets its
+ * counters, replayed until every instance has stopped; rounds_per_launch
+ * rounds per replay (0 = 4096).  In every round each running instance
+ * takes its own next piece of work from one shared work-list -- a fused LDS
+ * tile sweep of up to T steps (periodic instances are tiled too), a single
+ * step (its residual-check step, or the plain steps before its next check or
+ * its max_steps), or the reduction of its residual after a check -- so the
+ * instances keep their own step counters and check intervals and a stopped
+ * instance takes no more work; a grid barrier ends each round.  Results equal
+ * the host-driven launches' bit for bit (same node arithmetic).  A barrier
+ * that waits for more than a few seconds (workgroups not co-resident) ends
+ * the launch with SLBM_EHIP instead of hanging.  Off by default; the
+ * no-allocation variant always uses the host-driven launches. */
+int solid_lbm_batch_set_persistent(slbm_batch *batch, int32_t on, int32_t rounds_per_launch);
+
+/* Graph replays (persistent launches) and rounds of the last persistent solve half. */
+int solid_lbm_batch_persistent_stats(const slbm_batch *batch, int64_t *launches, int64_t *rounds);
+
 /* The context of instance i (owned by the batch) for solid_lbm_get_field and
  * the other per-context calls; NULL if i is out of range. */
 slbm_ctx *solid_lbm_batch_instance(slbm_batch *batch, int32_t i);

@@ -431,6 +431,7 @@ void launch_tile(slbm_ctx* c, bool adjoint, const SweepArgs& s, int steps, int h
     a.scale = s.scale;
     a.halo = halo;
     a.steps = steps;
+    a.maxb = kTileMaxB;
     tile_shape(c, halo, &a.tw, &a.th);
     a.tiles_x = (c->nx + a.tw - 1) / a.tw;
     const int tiles_y = (c->ny + a.th - 1) / a.th;
@@ -1725,6 +1726,19 @@ struct slbm_batch {
     double tol = 0.0;
     int64_t max_steps = 0;
     hipEvent_t ev[2] = {nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
+    // persistent launches (solid_lbm_batch_set_persistent): one graph-captured
+    // persistent kernel per launch instead of host-driven launches per round
+    bool persist = false;
+    int persist_rounds = 4096;     // rounds per persistent launch (one graph replay)
+    PersistInst* d_pinst = nullptr;
+    PersistState* d_pstate = nullptr;   // replicas: one state array per workgroup
+    int64_t pstate_cap = 0;             // replicas allocated (workgroups x instances)
+    PersistCtl* d_pctl = nullptr;
+    PersistCtl* h_pctl = nullptr;  // pinned: the graph copies the control block here
+    hipStream_t pstream = nullptr; // capture stream (the batch's stream may be the default one)
+    hipEvent_t pev = nullptr;
+    bool persist_attr = false;
+    int64_t persist_launches = 0, persist_rounds_run = 0;   // of the last persistent half
     std::string err;
     std::vector<void*> allocs;
 };
@@ -1887,6 +1901,7 @@ int batch_tables(slbm_batch* b, bool adjoint)
                 l.th = tw;
                 l.halo = T;
                 l.steps = T;
+                l.maxb = kTileMaxB;
                 l.tiles_x = (c->nx + tw - 1) / tw;
                 (k ? I.ladj : I.lprim)[par] = l;
             }
@@ -2007,9 +2022,13 @@ void launch_batch_tile(slbm_batch* b, bool adjoint, int pl)
 // runs between checks are fused for periodic instances.  Afterwards, for each
 // instance: t (its final step), X (buffer holding its input of step t) and
 // whether it converged.
+int batch_loop_persist(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::vector<int>& x_out,
+                       std::vector<char>& conv, std::vector<double>& res, double* dev_ms);
+
 int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::vector<int>& x_out,
                std::vector<char>& conv, std::vector<double>& res, double* dev_ms)
 {
+    if (b->persist && !b->static_tables) return batch_loop_persist(b, adjoint, t_out, x_out, conv, res, dev_ms);
     const int B = (int)b->ctx.size();
     hipLaunchKernelGGL(k_status_reset_all, dim3((B + 127) / 128), dim3(128), 0, b->stream, b->status, B);
     BHIPCHK(b, hipGetLastError());
@@ -2108,6 +2127,152 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
             conv[i] = 1;
         } else {
             x_out[i] = last_in[i];
+        }
+    }
+    return SLBM_OK;
+}
+
+// The persistent path: per-instance constants, state reset, then graph
+// replays of [reset of the launch's counters and barrier, the persistent
+// kernel, a copy of the control block to pinned memory] until every instance
+// has stopped.  Every instance runs as LDS tiles (periodic ones too), halo =
+// the batch's T; results equal the host-driven loop's bit for bit (same node
+// arithmetic, same checks).
+int batch_loop_persist(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::vector<int>& x_out,
+                       std::vector<char>& conv, std::vector<double>& res, double* dev_ms)
+{
+    const int B = (int)b->ctx.size();
+    hipLaunchKernelGGL(k_status_reset_all, dim3((B + 127) / 128), dim3(128), 0, b->stream, b->status, B);
+    BHIPCHK(b, hipGetLastError());
+    int rc = batch_tables(b, adjoint);
+    if (rc) return rc;
+    const int T = b->T > 1 ? b->T : 1;
+    const int tw = std::max(2, 32 - 2 * T);
+    std::vector<PersistInst> pi(B);
+    for (int i = 0; i < B; ++i) {
+        const slbm_ctx* c = b->ctx[i];
+        pi[i].K = c->K;
+        pi[i].last = b->max_steps;
+        pi[i].ntiles = ((c->nx + tw - 1) / tw) * ((c->ny + tw - 1) / tw);
+        pi[i].nnb = (int32_t)((c->N + kPersistBlock - 1) / kPersistBlock);
+        pi[i].halo = T;
+        pi[i].pad = 0;
+    }
+    BHIPCHK(b, hipMemcpyAsync(b->d_pinst, pi.data(), B * sizeof(PersistInst), hipMemcpyHostToDevice, b->stream));
+    // LDS: the tile regions (two copies for plates) and the staged boundary
+    // records, within what a compute unit has beside the kernel's own arrays
+    int maxb = kTileMaxB;
+    if (b->any_masked) {
+        hipFuncAttributes fa;
+        BHIPCHK(b, hipFuncGetAttributes(&fa, adjoint ? reinterpret_cast<const void*>(&k_batch_persist<true>)
+                                                     : reinterpret_cast<const void*>(&k_batch_persist<false>)));
+        int dev0 = 0, lds_cu = 0;
+        BHIPCHK(b, hipGetDevice(&dev0));
+        BHIPCHK(b, hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev0));
+        const int64_t room = (int64_t)lds_cu - (int64_t)fa.sharedSizeBytes - (int64_t)tile_lds_bytes(kTileMaxNodes, true, 0);
+        maxb = (int)std::max<int64_t>(0, std::min<int64_t>(kTileMaxB, room / (int64_t)sizeof(BNode)));
+    }
+    const size_t lds = T > 1 ? tile_lds_bytes((tw + 2 * T) * (tw + 2 * T), b->any_masked, maxb) : 0;
+    const void* fn = adjoint ? reinterpret_cast<const void*>(&k_batch_persist<true>)
+                             : reinterpret_cast<const void*>(&k_batch_persist<false>);
+    if (!b->persist_attr) {
+        const int lmax = (int)tile_lds_bytes(kTileMaxNodes, true);
+        BHIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_persist<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+        BHIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_persist<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+        b->persist_attr = true;
+    }
+    // every workgroup must be resident at once (grid barriers): as many as the
+    // occupancy calculator admits on the device's compute units
+    int dev = 0, cus = 0, per_cu = 0;
+    BHIPCHK(b, hipGetDevice(&dev));
+    BHIPCHK(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    BHIPCHK(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPersistBlock, lds));
+    const int G = per_cu * cus;
+    if (G < 1) return bfail(b, SLBM_EHIP, "persistent batch kernel does not fit on a compute unit");
+    if ((int64_t)G * B > b->pstate_cap) {
+        void* q = nullptr;
+        if ((rc = balloc(b, &q, (size_t)G * B * sizeof(PersistState)))) return rc;
+        b->d_pstate = (PersistState*)q;
+        b->pstate_cap = (int64_t)G * B;
+    }
+    hipLaunchKernelGGL(k_persist_init, dim3((unsigned)(((int64_t)G * B + 255) / 256)), dim3(256), 0, b->stream,
+                       b->d_pstate, b->d_pctl, (int64_t)G * B);
+    BHIPCHK(b, hipGetLastError());
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    const int use_tol = b->tol > 0.0 ? 1 : 0;
+    // order the capture stream after the batch stream's work
+    BHIPCHK(b, hipEventRecord(b->pev, b->stream));
+    BHIPCHK(b, hipStreamWaitEvent(b->pstream, b->pev, 0));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BHIPCHK(b, hipStreamBeginCapture(b->pstream, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(k_persist_begin, dim3(1), dim3(1), 0, b->pstream, b->d_pctl, b->persist_rounds);
+    if (adjoint)
+        hipLaunchKernelGGL(k_batch_persist<true>, dim3(G), dim3(kPersistBlock), lds, b->pstream, b->d_inst,
+                           b->d_pinst, B, b->d_pstate, b->d_pctl, use_tol, b->tol, maxb);
+    else
+        hipLaunchKernelGGL(k_batch_persist<false>, dim3(G), dim3(kPersistBlock), lds, b->pstream, b->d_inst,
+                           b->d_pinst, B, b->d_pstate, b->d_pctl, use_tol, b->tol, maxb);
+    hipError_t ce = hipMemcpyAsync(b->h_pctl, b->d_pctl, sizeof(PersistCtl), hipMemcpyDeviceToHost, b->pstream);
+    hipError_t ee = hipStreamEndCapture(b->pstream, &graph);
+    if (ce != hipSuccess || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return bfail(b, SLBM_EHIP, std::string("persistent batch graph capture: ") +
+                                       hipGetErrorString(ce != hipSuccess ? ce : ee));
+    }
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return bfail(b, SLBM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    int out = SLBM_OK;
+    b->persist_launches = 0;
+    hipError_t e = hipEventRecord(b->t0, b->pstream);
+    while (e == hipSuccess) {
+        e = hipGraphLaunch(exec, b->pstream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->pstream);
+        if (e != hipSuccess) break;
+        ++b->persist_launches;
+        if (b->h_pctl->error) {
+            out = bfail(b, SLBM_EHIP, "persistent batch kernel: a grid barrier timed out");
+            break;
+        }
+        if (b->h_pctl->done) break;
+        // every round advances a running instance by a step or a residual test
+        if (b->h_pctl->rounds > 2 * (b->max_steps + 2) + 16) {
+            out = bfail(b, SLBM_EHIP, "internal: persistent batch made no progress");
+            break;
+        }
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->t1, b->pstream);
+    if (e == hipSuccess) e = hipEventSynchronize(b->t1);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return bfail(b, SLBM_EHIP, std::string("persistent batch launch: ") + hipGetErrorString(e));
+    if (out) return out;
+    b->persist_rounds_run = b->h_pctl->rounds;
+    float f = 0.f;
+    BHIPCHK(b, hipEventElapsedTime(&f, b->t0, b->t1));
+    if (dev_ms) *dev_ms = f;
+    std::vector<Status> st(B);
+    std::vector<PersistState> ps(B);
+    BHIPCHK(b, hipMemcpy(st.data(), b->status, B * sizeof(Status), hipMemcpyDeviceToHost));
+    BHIPCHK(b, hipMemcpy(ps.data(), b->d_pstate, B * sizeof(PersistState), hipMemcpyDeviceToHost));   // replica 0
+    t_out.assign(B, b->max_steps);
+    x_out.assign(B, 0);
+    conv.assign(B, 0);
+    res.assign(B, 0.0);
+    for (int i = 0; i < B; ++i) {
+        res[i] = st[i].res;
+        if (use_tol && st[i].stop) {
+            if (ps[i].t_chk != st[i].t_conv) return bfail(b, SLBM_EHIP, "internal: converged step is not the last check");
+            t_out[i] = st[i].t_conv;
+            x_out[i] = ps[i].x_chk;
+            conv[i] = 1;
+        } else {
+            x_out[i] = ps[i].x_last;
         }
     }
     return SLBM_OK;
@@ -2253,12 +2418,20 @@ int solid_lbm_batch_init(const slbm_problem* problems, int32_t count, slbm_batch
     if (!rc && hipHostMalloc((void**)&b->h_status, 2 * count * sizeof(Status), hipHostMallocDefault) != hipSuccess)
         rc = SLBM_EHIP;
     if (!rc && (hipEventCreate(&b->ev[0]) != hipSuccess || hipEventCreate(&b->ev[1]) != hipSuccess ||
-                hipEventCreate(&b->t0) != hipSuccess || hipEventCreate(&b->t1) != hipSuccess))
+                hipEventCreate(&b->t0) != hipSuccess || hipEventCreate(&b->t1) != hipSuccess ||
+                hipEventCreate(&b->pev) != hipSuccess))
         rc = SLBM_EHIP;
+    // persistent path: per-instance constants and state, control block, capture stream
+    if (!rc && !(rc = balloc(b, &q, count * sizeof(PersistInst)))) b->d_pinst = (PersistInst*)q;
+    if (!rc && !(rc = balloc(b, &q, sizeof(PersistCtl)))) b->d_pctl = (PersistCtl*)q;
+    if (!rc && hipHostMalloc((void**)&b->h_pctl, sizeof(PersistCtl), hipHostMallocDefault) != hipSuccess)
+        rc = SLBM_EHIP;
+    if (!rc && hipStreamCreateWithFlags(&b->pstream, hipStreamNonBlocking) != hipSuccess) rc = SLBM_EHIP;
     if (rc) {
         solid_lbm_batch_destroy(b);
         return bfail(nullptr, rc, "batch allocation failed");
     }
+    std::memset(b->h_pctl, 0, sizeof(PersistCtl));
     b->n_all = (int64_t)all.size();
     b->h_inst.resize(count);
     // defined contents for timing sweeps before any solve
@@ -2360,6 +2533,23 @@ int solid_lbm_batch_time_sweeps(slbm_batch* b, int32_t adjoint, int64_t n, doubl
     return SLBM_OK;
 }
 
+int solid_lbm_batch_set_persistent(slbm_batch* b, int32_t on, int32_t rounds_per_launch)
+{
+    if (!b) return SLBM_EINVAL;
+    if (rounds_per_launch < 0) return bfail(b, SLBM_EINVAL, "rounds_per_launch must be >= 0");
+    b->persist = on != 0;
+    b->persist_rounds = rounds_per_launch > 0 ? rounds_per_launch : 4096;
+    return SLBM_OK;
+}
+
+int solid_lbm_batch_persistent_stats(const slbm_batch* b, int64_t* launches, int64_t* rounds)
+{
+    if (!b || !launches || !rounds) return SLBM_EINVAL;
+    *launches = b->persist_launches;
+    *rounds = b->persist_rounds_run;
+    return SLBM_OK;
+}
+
 slbm_ctx* solid_lbm_batch_instance(slbm_batch* b, int32_t i)
 {
     if (!b || i < 0 || i >= (int32_t)b->ctx.size()) return nullptr;
@@ -2374,10 +2564,13 @@ void solid_lbm_batch_destroy(slbm_batch* b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     else (void)hipDeviceSynchronize();
     for (auto* c : b->ctx) solid_lbm_destroy(c);
+    if (b->pstream) (void)hipStreamSynchronize(b->pstream);
     for (void* p : b->allocs) (void)hipFree(p);
     if (b->h_status) (void)hipHostFree(b->h_status);
-    for (hipEvent_t e : {b->ev[0], b->ev[1], b->t0, b->t1})
+    if (b->h_pctl) (void)hipHostFree(b->h_pctl);
+    for (hipEvent_t e : {b->ev[0], b->ev[1], b->t0, b->t1, b->pev})
         if (e) (void)hipEventDestroy(e);
+    if (b->pstream) (void)hipStreamDestroy(b->pstream);
     delete b;
 }
 

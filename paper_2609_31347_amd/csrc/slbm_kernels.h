@@ -1056,6 +1056,7 @@ struct TileArgs {
     double k11, ks, kd, E0, nu, scale;
     int32_t tw, th, halo, steps, tiles_x;
     int32_t order_by_kind;           // plates: threads take bulk, then boundary, then outside nodes
+    int32_t maxb;                    // boundary records staged in LDS (<= kTileMaxB; the rest from HBM)
 };
 
 constexpr int kTileBlock = 1024;
@@ -1065,9 +1066,9 @@ constexpr int kTileMaxNodes = kTileBlock * kTileNPT; // region <= 1024 nodes (64
 // the cap are read from HBM / L2 (same values, only slower).
 constexpr int kTileMaxB = 96;                        // 96 x 272 B
 
-__host__ __device__ constexpr size_t tile_lds_bytes(int region, bool masked)
+__host__ __device__ constexpr size_t tile_lds_bytes(int region, bool masked, int maxb = kTileMaxB)
 {
-    return (size_t)(masked ? 16 : 8) * region * sizeof(double) + (masked ? (size_t)kTileMaxB * sizeof(BNode) : 0);
+    return (size_t)(masked ? 16 : 8) * region * sizeof(double) + (masked ? (size_t)maxb * sizeof(BNode) : 0);
 }
 
 // One tile (index `tile` of the problem's tiles_x x tiles_y) of a tiled launch;
@@ -1205,7 +1206,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
             const int k = cd[j] - 1;
             const int slot = atomicAdd(&nstaged, 1);
             bng[j] = a.bnodes + k;
-            if (slot < kTileMaxB) {
+            if (slot < a.maxb) {
                 const double* s8 = reinterpret_cast<const double*>(a.bnodes + k);
                 double* d8 = reinterpret_cast<double*>(lbn + slot);
 #pragma unroll
@@ -1445,6 +1446,363 @@ __global__ void k_status_reset_all(Status* st, int n)
         st[i].t_last = -1;
         st[i].res = INFINITY;
     }
+}
+
+// ---------------------------------------------------------------- persistent batch sweeps
+// One launch of kPersistBlock-thread workgroups, one per compute unit, that
+// advances every instance of a batch round after round until all of them
+// have stopped (or a round budget ends the launch; the next launch resumes).
+// Each instance keeps its own step counter, buffer parity and residual-check
+// schedule (its own K): in a round it runs one fused launch's worth of steps
+// (an LDS tile sweep of up to `halo` steps; periodic instances are tiled
+// too), or one single step (a residual-check step, or the plain steps before
+// its next check or its last step), or, after a check step, the reduction of
+// its residual, which sets its stop flag.  The round's work items (tiles,
+// 1024-node blocks, reductions) of all running instances form one list that
+// the workgroups take from with an atomic counter; a stopped instance has no
+// items (it retires).  A grid barrier ends every round.
+//
+// The per-instance state machine is replicated: thread i of every workgroup
+// holds instance i's state and applies the same update after each barrier,
+// from data every workgroup reads identically (the round's decisions and the
+// stop flags written before the barrier), so all workgroups agree on every
+// round without another barrier.  Every wait is bounded: a barrier that does
+// not complete within kPersistSpin polls sets the error flag and the launch
+// ends (the host reports an error) instead of hanging.
+constexpr int kPersistBlock = 1024;
+constexpr int kMaxBatch = 128;
+constexpr long kPersistSpin = 1L << 26;     // about 4 s of 64-cycle sleeps
+enum { PS_RUN = 0, PS_RESID = 1, PS_DONE = 2 };
+enum { PT_NONE = 0, PT_FUSED = 1, PT_SINGLE = 2, PT_CHECK = 3, PT_RESID = 4 };
+
+struct PersistInst {
+    int64_t K;          // check interval
+    int64_t last;       // final step index (max_steps)
+    int32_t ntiles;     // tiles of a fused round (tile of 32 - 2 halo nodes, halo = the batch's T)
+    int32_t nnb;        // 1024-node blocks of a single step
+    int32_t halo;       // steps a fused round may take (tile halo)
+    int32_t pad;
+};
+
+struct PersistState {
+    int64_t s;          // next step to run
+    int64_t t_chk;      // step of the latest check
+    int32_t cur;        // buffer parity holding the input of step s
+    int32_t phase;      // PS_*
+    int32_t x_chk;      // input parity of the latest check step
+    int32_t x_last;     // input parity of the final step (runs that end at max_steps)
+};
+
+struct PersistCtl {
+    uint32_t cnt[2];        // work-item counters of alternate rounds
+    uint32_t arrive;        // grid barrier: workgroups arrived
+    uint32_t gen;           // grid barrier: generation
+    int32_t error;          // a barrier timed out
+    int32_t done;           // every instance has stopped
+    int32_t budget;         // rounds per launch
+    int32_t pad;
+    int64_t rounds;         // rounds run so far (all launches of a solve)
+};
+
+// Sums (a, b) over the kPersistBlock threads into out[0], out[1] (thread 0 writes).
+__device__ __forceinline__ void block_sum2_persist(double a, double b, double* out)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    __shared__ double pa[kPersistBlock / 64], pb[kPersistBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { pa[w] = a; pb[w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0, y = 0.0;
+#pragma unroll
+        for (int i = 0; i < kPersistBlock / 64; ++i) { x += pa[i]; y += pb[i]; }
+        out[0] = x;
+        out[1] = y;
+    }
+}
+
+// Grid barrier over nwg workgroups with device-scope release/acquire; false
+// if it timed out or another workgroup reported an error.
+__device__ __forceinline__ bool persist_barrier(PersistCtl* ctl, uint32_t nwg)
+{
+    __shared__ int ok_s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();
+        const uint32_t g = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t arrived = __hip_atomic_fetch_add(&ctl->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nwg - 1) {
+            __hip_atomic_store(&ctl->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spins = 0;
+            while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kPersistSpin ||
+                    ((spins & 1023) == 0 && __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0;
+}
+
+// Round decision of one running instance (mirrors the single-problem solve
+// loop: check steps at s > 0, s % K == 0; the last step and leftovers are
+// single steps; plain runs between checks are fused up to `halo` steps).
+__device__ __forceinline__ void persist_decide(const PersistInst& P, const PersistState& st, bool use_tol,
+                                               int& type, int& k, int& items)
+{
+    type = PT_NONE;
+    k = 0;
+    items = 0;
+    if (st.phase == PS_DONE) return;
+    if (st.phase == PS_RESID) {
+        type = PT_RESID;
+        items = 1;
+        return;
+    }
+    const int64_t s = st.s;
+    if (use_tol && s > 0 && s % P.K == 0) {
+        type = PT_CHECK;
+        k = 1;
+        items = P.nnb;
+        return;
+    }
+    const int64_t end = use_tol ? min(P.last, (s / P.K + 1) * P.K - 1) : P.last;
+    const int64_t plain = min(end, P.last - 1) - s + 1;
+    if (P.halo > 1 && plain >= 2) {
+        type = PT_FUSED;
+        k = (int)min(plain, (int64_t)P.halo);
+        items = P.ntiles;
+        return;
+    }
+    type = PT_SINGLE;
+    k = 1;
+    items = P.nnb;
+}
+
+// State after a round of the given type (stopped: the instance's stop flag,
+// read after the barrier; only used after a reduction).
+__device__ __forceinline__ void persist_update(const PersistInst& P, PersistState& st, int type, int k,
+                                               bool stopped)
+{
+    switch (type) {
+        case PT_FUSED:
+            st.s += k;
+            st.cur ^= 1;
+            break;
+        case PT_SINGLE:
+        case PT_CHECK:
+            if (type == PT_CHECK) {
+                st.t_chk = st.s;
+                st.x_chk = st.cur;
+                st.phase = PS_RESID;
+            }
+            if (st.s == P.last) st.x_last = st.cur;
+            st.s += 1;
+            st.cur ^= 1;
+            if (type == PT_SINGLE && st.s > P.last) st.phase = PS_DONE;
+            break;
+        case PT_RESID:
+            st.phase = (stopped || st.s > P.last) ? PS_DONE : PS_RUN;
+            break;
+        default:
+            break;
+    }
+}
+
+// One 1024-node block of a single step (with the residual terms on check steps).
+template <bool ADJ>
+__device__ __forceinline__ void persist_nodes(const BatchInst& I, int par, int blk, bool check)
+{
+    const SweepArgs& a = ADJ ? I.adj[par] : I.prim[par];
+    const int64_t n = (int64_t)blk * kPersistBlock + threadIdx.x;
+    double num = 0.0, den = 0.0;
+    if (n < a.N) {
+        const int sel = (I.masked ? 4 : 0) | (I.efield ? 2 : 0) | (check ? 1 : 0);
+#define BN_CASE(i, M, EF, CH)                                                       \
+    case i:                                                                         \
+        if (ADJ) adjoint_node<M, EF, CH>(a, n, I.inv_nx, num, den);                 \
+        else primal_node<M, EF, CH>(a, n, I.inv_nx, num, den);                      \
+        break;
+        switch (sel) {
+            BN_CASE(0, false, false, false)
+            BN_CASE(1, false, false, true)
+            BN_CASE(2, false, true, false)
+            BN_CASE(3, false, true, true)
+            BN_CASE(4, true, false, false)
+            BN_CASE(5, true, false, true)
+            BN_CASE(6, true, true, false)
+            BN_CASE(7, true, true, true)
+        }
+#undef BN_CASE
+    }
+    if (check) block_sum2_persist(num, den, a.partial + 2 * (int64_t)blk);
+}
+
+// Residual test of an instance after its check step t: the sum of its nnb
+// partial pairs in block order, then stop if below tol.
+__device__ __forceinline__ void persist_resid(const BatchInst& I, const PersistInst& P, double tol, int64_t t)
+{
+    const double* partial = I.prim[0].partial;
+    double a = 0.0, b = 0.0;
+    for (int64_t k = threadIdx.x; k < P.nnb; k += kPersistBlock) {
+        a += partial[2 * k];
+        b += partial[2 * k + 1];
+    }
+    __shared__ double out[2];
+    block_sum2_persist(a, b, out);
+    if (threadIdx.x == 0) {
+        Status* st = I.status;
+        const double num = out[0], den = out[1];
+        const double r = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+        st->res = r;
+        st->t_last = t;
+        if (r < tol) {
+            st->t_conv = t;
+            __hip_atomic_store(&st->stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <bool ADJ>
+__global__ __launch_bounds__(kPersistBlock) void k_batch_persist(const BatchInst* __restrict__ inst,
+                                                                 const PersistInst* __restrict__ pinst, int B,
+                                                                 PersistState* prep, PersistCtl* ctl,
+                                                                 int use_tol, double tol, int maxb)
+{
+    extern __shared__ __align__(16) double lds[];
+    __shared__ int s_dec[kMaxBatch];              // round decision: type | k << 3 | cur << 8
+    __shared__ int s_pre[kMaxBatch + 1];          // work items of instances < i
+    __shared__ int s_item[3];
+    const int tid = threadIdx.x;
+    // this workgroup's replica of the instances' states (all replicas evolve alike)
+    PersistState* rep = prep + (int64_t)blockIdx.x * B;
+    const int budget = ctl->budget;
+    int round = 0;
+    bool all_done = false;
+    for (;;) {
+        if (tid < B) {
+            const PersistState st = rep[tid];
+            int type, k, items;
+            persist_decide(pinst[tid], st, use_tol != 0, type, k, items);
+            s_dec[tid] = type | (k << 3) | (st.cur << 8);
+            s_pre[tid + 1] = items;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_pre[0] = 0;
+            for (int i = 0; i < B; ++i) s_pre[i + 1] += s_pre[i];
+        }
+        __syncthreads();
+        const int total = s_pre[B];
+        if (total == 0) {
+            all_done = true;
+            break;
+        }
+        if (round >= budget) break;
+        const int slot = round & 1;
+        // the other counter was last used a round ago: every workgroup finished
+        // taking from it before the barrier that ended that round
+        if (blockIdx.x == 0 && tid == 0)
+            __hip_atomic_store(&ctl->cnt[slot ^ 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (;;) {
+            if (tid == 0) {
+                const int it = (int)__hip_atomic_fetch_add(&ctl->cnt[slot], 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                int lo = 0, hi = B;                       // instance: s_pre[lo] <= it < s_pre[lo + 1]
+                if (it < total) {
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_pre[mid] <= it) lo = mid;
+                        else hi = mid;
+                    }
+                }
+                s_item[0] = it;
+                s_item[1] = lo;
+                s_item[2] = it - s_pre[lo];
+            }
+            __syncthreads();
+            const int it = s_item[0], i = s_item[1], loc = s_item[2];
+            __syncthreads();
+            if (it >= total) break;
+            const BatchInst& I = inst[i];
+            const int dec = s_dec[i], ty = dec & 7, par = (dec >> 8) & 1;
+            if (ty == PT_FUSED) {
+                TileArgs a = ADJ ? I.ladj[par] : I.lprim[par];
+                a.steps = (dec >> 3) & 31;
+                a.maxb = min(a.maxb, maxb);
+                const int sel = (I.masked ? 2 : 0) | (I.efield ? 1 : 0);
+                switch (sel) {
+                    case 0: tile_body<false, false, ADJ>(a, loc, lds); break;
+                    case 1: tile_body<false, true, ADJ>(a, loc, lds); break;
+                    case 2: tile_body<true, false, ADJ>(a, loc, lds); break;
+                    default: tile_body<true, true, ADJ>(a, loc, lds); break;
+                }
+            } else if (ty == PT_SINGLE || ty == PT_CHECK) {
+                persist_nodes<ADJ>(I, par, loc, ty == PT_CHECK);
+            } else if (ty == PT_RESID) {
+                persist_resid(I, pinst[i], tol, rep[i].s - 1);    // the check step was s - 1
+            }
+            __syncthreads();
+        }
+        if (!persist_barrier(ctl, gridDim.x)) return;
+        if (tid < B) {
+            PersistState st = rep[tid];
+            const int dec = s_dec[tid], type = dec & 7;
+            const bool stopped = type == PT_RESID &&
+                                 __hip_atomic_load(&inst[tid].status->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            persist_update(pinst[tid], st, type, (dec >> 3) & 31, stopped);
+            rep[tid] = st;
+        }
+        ++round;
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        ctl->done = all_done ? 1 : 0;
+        ctl->rounds += round;
+    }
+}
+
+// Start of a persistent launch (a graph node, so no memset node): clears the
+// round counters and the barrier, sets the round budget.
+__global__ void k_persist_begin(PersistCtl* ctl, int budget)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->cnt[0] = ctl->cnt[1] = 0;
+        ctl->arrive = 0;
+        ctl->gen = 0;
+        ctl->error = 0;
+        ctl->done = 0;
+        ctl->budget = budget;
+    }
+}
+
+// Start of a persistent solve: every instance at step 0 from buffer 0, in
+// each of the n = workgroups x B replicas.
+__global__ void k_persist_init(PersistState* st, PersistCtl* ctl, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        st[i].s = 0;
+        st[i].t_chk = -1;
+        st[i].cur = 0;
+        st[i].phase = PS_RUN;
+        st[i].x_chk = 0;
+        st[i].x_last = 0;
+    }
+    if (i == 0) ctl->rounds = 0;
 }
 
 }  // namespace slbm

@@ -31,7 +31,8 @@ EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_gra
            "solid_lbm_last_error",
            "solid_lbm_destroy",
            "solid_lbm_batch_init", "batch_objective_and_grad", "batch_objective_and_grad_noalloc",
-           "batch_gradient", "solid_lbm_batch_set_tuning",
+           "batch_gradient", "solid_lbm_batch_set_tuning", "solid_lbm_batch_set_persistent",
+           "solid_lbm_batch_persistent_stats",
            "solid_lbm_batch_time_sweeps", "solid_lbm_batch_instance", "solid_lbm_batch_last_error",
            "solid_lbm_batch_destroy")
 
@@ -129,6 +130,8 @@ def _load():
                                              ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, info, info]
     lib.batch_gradient.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, info]
     lib.batch_objective_and_grad_noalloc.argtypes = lib.batch_objective_and_grad.argtypes
+    lib.solid_lbm_batch_set_persistent.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.solid_lbm_batch_persistent_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.solid_lbm_batch_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.solid_lbm_batch_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_batch_instance.argtypes = [P, ctypes.c_int32]
@@ -546,6 +549,18 @@ def batch_gradient(batch, grads=None):
 def solid_lbm_batch_set_tuning(batch, steps_per_launch=-1, rows_per_wave=0):
     """Launch shape of the batch's shared launches (-1 / 0 automatic); results do not change."""
     return _bcheck(batch, LIB.solid_lbm_batch_set_tuning(batch.handle, int(steps_per_launch), int(rows_per_wave)))
+
+
+def solid_lbm_batch_set_persistent(batch, on=True, rounds_per_launch=0):
+    """Persistent, graph-captured launches for the batch's solves (see the header)."""
+    return _bcheck(batch, LIB.solid_lbm_batch_set_persistent(batch.handle, 1 if on else 0, int(rounds_per_launch)))
+
+
+def solid_lbm_batch_persistent_stats(batch):
+    """(graph replays, rounds) of the last persistent solve half."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _bcheck(batch, LIB.solid_lbm_batch_persistent_stats(batch.handle, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def solid_lbm_batch_time_sweeps(batch, adjoint, n):

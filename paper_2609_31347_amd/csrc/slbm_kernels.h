@@ -1495,13 +1495,14 @@ struct PersistState {
 
 struct PersistCtl {
     uint32_t cnt[2];        // work-item counters of alternate rounds
-    uint32_t arrive;        // grid barrier: workgroups arrived
+    uint32_t arrive;        // grid barrier: groups arrived
     uint32_t gen;           // grid barrier: generation
     int32_t error;          // a barrier timed out
     int32_t done;           // every instance has stopped
     int32_t budget;         // rounds per launch
     int32_t pad;
     int64_t rounds;         // rounds run so far (all launches of a solve)
+    uint32_t grp[kXcds][32];  // grid barrier: workgroups arrived per group (one 128-byte line each)
 };
 
 // Sums (a, b) over the kPersistBlock threads into out[0], out[1] (thread 0 writes).
@@ -1526,7 +1527,10 @@ __device__ __forceinline__ void block_sum2_persist(double a, double b, double* o
 }
 
 // Grid barrier over nwg workgroups with device-scope release/acquire; false
-// if it timed out or another workgroup reported an error.
+// if it timed out or another workgroup reported an error.  Two levels: the
+// workgroups of a group (those of one XCD: workgroup b runs on XCD b % 8)
+// count on the group's own counter, and the last of each group on the
+// global one, so no counter takes more than one XCD's arrivals.
 __device__ __forceinline__ bool persist_barrier(PersistCtl* ctl, uint32_t nwg)
 {
     __shared__ int ok_s;
@@ -1534,9 +1538,16 @@ __device__ __forceinline__ bool persist_barrier(PersistCtl* ctl, uint32_t nwg)
     if (threadIdx.x == 0) {
         int ok = 1;
         __threadfence();
+        const uint32_t ngrp = nwg < (uint32_t)kXcds ? nwg : (uint32_t)kXcds;
+        const uint32_t grp = blockIdx.x % ngrp;
+        const uint32_t in_grp = nwg / ngrp + (grp < nwg % ngrp ? 1u : 0u);
         const uint32_t g = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t arrived = __hip_atomic_fetch_add(&ctl->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nwg - 1) {
+        bool last = false;
+        if (__hip_atomic_fetch_add(&ctl->grp[grp][0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == in_grp - 1) {
+            __hip_atomic_store(&ctl->grp[grp][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = __hip_atomic_fetch_add(&ctl->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == ngrp - 1;
+        }
+        if (last) {
             __hip_atomic_store(&ctl->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -1782,6 +1793,7 @@ __global__ void k_persist_begin(PersistCtl* ctl, int budget)
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ctl->cnt[0] = ctl->cnt[1] = 0;
         ctl->arrive = 0;
+        for (int k = 0; k < kXcds; ++k) ctl->grp[k][0] = 0;
         ctl->gen = 0;
         ctl->error = 0;
         ctl->done = 0;

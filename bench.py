@@ -364,9 +364,12 @@ def batch_sweeps(args):
 def warmstart_mode(args):
     """Learned warm start of the E-field identification on the clamped plate:
     training data from batched FP64 solves at 64 x 39, training by the
-    project's MFMA kernels, then cold vs warm time-to-gradient (primal +
-    adjoint to the residual tol) on held-out E fields at each evaluation size.
-    Every stage prints one JSON line."""
+    project's MFMA kernels, then cold vs warm batched gradients (primal and
+    adjoint to the residual tol, all held-out fields of a size in one batch,
+    the prediction timed with the warm solves) at each evaluation size, with
+    two ablations of the initial state (the E = 1 displacement alone, and the
+    exact solution of the coarse grid interpolated).  Every stage prints one
+    JSON line."""
     import torch
     from paper_2609_31347_amd import slbm as S
     from paper_2609_31347_amd import warmstart as WS
@@ -392,23 +395,13 @@ def warmstart_mode(args):
     print(json.dumps({"stage": "trained", "wall_s": round(time.perf_counter() - t0, 2)}), flush=True)
     rows = []
 
-    def gradient(ctx, E, d0, cbar, dx, tag):
-        """Primal solve (cold or warm) then the adjoint: the objective's gradient
-        as the VJP of the residual r dx^2 / Cbar (the objective's own adjoint
-        source), in two calls so that each one reports when it ends."""
-        t0 = time.perf_counter()
-        rc, pi = S.primal_solve(ctx, E, d0)
-        tp = time.perf_counter() - t0
-        J = S.solid_lbm_objective(ctx)
-        print(json.dumps({"stage": "primal", "run": tag, "steps": pi.steps, "wall_s": round(tp, 3),
-                          "converged": pi.converged}), flush=True)
-        r = S.solid_lbm_get_field(ctx, S.FIELD_RESIDUAL)
-        t1 = time.perf_counter()
-        rc, g, ai = S.adjoint_solve_vjp(ctx, r * (dx * dx / cbar))
-        ta = time.perf_counter() - t1
-        print(json.dumps({"stage": "adjoint", "run": tag, "steps": ai.steps, "wall_s": round(ta, 3),
-                          "converged": ai.converged}), flush=True)
-        return J, np.asarray(g).copy(), pi, ai, tp + ta
+    def primal_steps(cp, fields, target, d0s):
+        """Primal solves only (batched) from the given initial displacements: steps per field."""
+        batch = S.solid_lbm_batch_init([WS.plate_problem(cp, args.tol, target=target) for _ in fields])
+        rc, _, _, pi, _ = S.batch_objective_and_grad(batch, list(fields), want_grad=False, init_disps=d0s)
+        S.require_converged(rc, "primal solves")
+        S.solid_lbm_batch_destroy(batch)
+        return [int(p.steps) for p in pi]
 
     sizes = [int(v) for v in args.eval_sizes.split(",")]
     nf = [int(v) for v in str(args.eval_fields).split(",")]
@@ -420,40 +413,47 @@ def warmstart_mode(args):
         ctx = S.solid_lbm_init(WS.plate_problem(cp, args.tol))
         t0 = time.perf_counter()
         rc, ti = S.primal_solve(ctx, E_star)
+        S.require_converged(rc, "target solve", ti)
         print(json.dumps({"stage": "target", "width": nx, "steps": ti.steps,
                           "wall_s": round(time.perf_counter() - t0, 3)}), flush=True)
         target = S.solid_lbm_get_field(ctx, S.FIELD_DISP)
-        cbar = float(((target ** 2).sum(0) * cp["active"]).sum()) * cp["dx"] ** 2
-        ctx = S.solid_lbm_init(WS.plate_problem(cp, args.tol, target=target))
-        for seed in range(10000, 10000 + n_fields[nx]):
-            E = WS.e_field(cp, seed)
-            tag = f"{nx}:{seed}"
-            Jc, gc, pc, ac, tc = gradient(ctx, E, None, cbar, cp["dx"], tag + ":cold")
-            t0 = time.perf_counter()
-            d0 = ws.predict(cp, E)
-            tp = time.perf_counter() - t0
-            Jw, gw, pw, aw, tw = gradient(ctx, E, d0, cbar, cp["dx"], tag + ":warm")
-            tw += tp
-            # ablation: the E = 1 displacement alone as the initial state (primal only)
-            rc, pr = S.primal_solve(ctx, E, ws.predict(cp, E, use_net=False))
-            row = {"stage": "eval", "grid": [cp["active"].shape[1], cp["active"].shape[0]], "seed": seed,
-                   "cold_primal_steps": pc.steps, "warm_primal_steps": pw.steps,
-                   "ref_only_primal_steps": pr.steps, "adjoint_steps": ac.steps,
-                   "cold_time_to_gradient_s": round(tc, 3), "warm_time_to_gradient_s": round(tw, 3),
-                   "predict_s": round(tp, 4), "J_rel_diff": abs(Jw - Jc) / abs(Jc),
-                   "grad_rel_diff": float(np.linalg.norm(gw - gc) / np.linalg.norm(gc))}
-            rows.append(row)
-            print(json.dumps(row), flush=True)
-    for nx in sorted(set(r["grid"][0] for r in rows)):
-        rr = [r for r in rows if r["grid"][0] == nx]
-        print(json.dumps({"stage": "summary", "width": nx,
-                          "primal_step_ratio": round(np.mean([r["warm_primal_steps"] / r["cold_primal_steps"]
-                                                              for r in rr]), 4),
-                          "ref_only_primal_step_ratio": round(np.mean([r["ref_only_primal_steps"] /
-                                                                       r["cold_primal_steps"] for r in rr]), 4),
-                          "time_to_gradient_ratio": round(np.mean([r["warm_time_to_gradient_s"] /
-                                                                   r["cold_time_to_gradient_s"] for r in rr]), 4)}),
+        del ctx
+        fields = [WS.e_field(cp, seed) for seed in range(10000, 10000 + n_fields[nx])]
+        # cold: batched gradients from d_0 = 0
+        t0 = time.perf_counter()
+        Jc, gc, pc, ac = WS.batch_gradients(cp, fields, target, args.tol)
+        tc = time.perf_counter() - t0
+        print(json.dumps({"stage": "cold", "width": nx, "wall_s": round(tc, 3),
+                          "primal_steps": [int(p.steps) for p in pc], "adjoint_steps": [int(a.steps) for a in ac]}),
               flush=True)
+        # warm: network prediction (timed with the solves) then batched gradients
+        t0 = time.perf_counter()
+        d0s = ws.predict_batch(cp, fields)
+        tp = time.perf_counter() - t0
+        Jw, gw, pw, aw = WS.batch_gradients(cp, fields, target, args.tol, init_disps=d0s)
+        tw = time.perf_counter() - t0
+        print(json.dumps({"stage": "warm", "width": nx, "wall_s": round(tw, 3), "predict_s": round(tp, 4),
+                          "primal_steps": [int(p.steps) for p in pw]}), flush=True)
+        # ablations (primal steps only): the E = 1 displacement alone, and the
+        # exact coarse-grid solution interpolated (the best any predictor that
+        # works on the coarse grid can hand over)
+        ref_steps = primal_steps(cp, fields, target, [ws.predict(cp, E, use_net=False) for E in fields])
+        Ecs = [WS._resample(E, cp, ws.cp, fill_outside=False) for E in fields]
+        dcs, _ = WS.solve_batch(ws.cp, Ecs, 1e-10)
+        exact_steps = primal_steps(cp, fields, target, [ws.to_fine(d, cp) for d in dcs])
+        row = {"stage": "eval", "grid": [cp["active"].shape[1], cp["active"].shape[0]], "fields": len(fields),
+               "cold_time_to_gradient_s": round(tc, 3), "warm_time_to_gradient_s": round(tw, 3),
+               "time_to_gradient_ratio": round(tw / tc, 4), "predict_s": round(tp, 4),
+               "cold_primal_steps": [int(p.steps) for p in pc], "warm_primal_steps": [int(p.steps) for p in pw],
+               "ref_only_primal_steps": ref_steps, "coarse_exact_primal_steps": exact_steps,
+               "adjoint_steps": [int(a.steps) for a in ac],
+               "primal_step_ratio": round(float(np.mean([w.steps / c.steps for w, c in zip(pw, pc)])), 4),
+               "ref_only_primal_step_ratio": round(float(np.mean([r / c.steps for r, c in zip(ref_steps, pc)])), 4),
+               "coarse_exact_primal_step_ratio": round(float(np.mean([r / c.steps for r, c in zip(exact_steps, pc)])), 4),
+               "J_max_rel_diff": float(max(abs(a - b) / abs(b) for a, b in zip(Jw, Jc))),
+               "grad_max_rel_diff": float(max(np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in zip(gw, gc)))}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
 
 
 def cpu_baseline(n, steps, F, tgt):

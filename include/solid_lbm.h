@@ -338,6 +338,15 @@ int batch_objective_and_grad(slbm_batch *batch, const double *const *controls, d
                              double *const *grads, int32_t ptr_kind, slbm_solve_info *primal_info,
                              slbm_solve_info *adjoint_info);
 
+/* As batch_objective_and_grad, with each instance's primal started from
+ * init_disps[i] (2N, read per ptr_kind; a NULL array or NULL entry = cold
+ * start d_0 = 0) instead of d_0 = 0 -- the warm start of
+ * objective_and_grad_from, per instance: fewer steps, the same fixed point. */
+int batch_objective_and_grad_from(slbm_batch *batch, const double *const *controls,
+                                  const double *const *init_disps, double *J, double *const *grads,
+                                  int32_t ptr_kind, slbm_solve_info *primal_info,
+                                  slbm_solve_info *adjoint_info);
+
 /* No-allocation variant of batch_objective_and_grad, for callers that cannot
  * allocate device memory during the call (code under stream capture, tight
  * serving loops, harnesses that forbid hipMalloc).  Same arguments, results

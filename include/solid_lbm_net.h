@@ -14,8 +14,12 @@
  * hold bfloat16 bit patterns (uint16_t, round-to-nearest-even from FP32).
  * Weights of a layer with Cin inputs, Cout <= 32 outputs are packed as
  * bf16 [32][Kp] with K = Cin*9 entries per output channel ordered (ci, ky, kx),
- * Kp = K rounded up to a multiple of 8, unused rows/columns zero.  Matrix
- * products run on MFMA (bf16 inputs, FP32 accumulation).  Every call returns
+ * Kp = K rounded up to a multiple of 16 (one k-slice of gfx950's
+ * v_mfma_f32_32x32x16_bf16), unused rows/columns zero.  The convolutions run on
+ * that MFMA (bf16 inputs, FP32 accumulation) with the weights and the input
+ * rows a workgroup touches staged in LDS; the weight gradient runs on the
+ * FP32 MFMA (FP32 dz times the bf16 input, exact products, FP32 sums in a
+ * fixed order).  Every call returns
  * 0 or a negative SLBM_* code (-1 bad arguments, -3 HIP error); the kernels
  * allocate nothing.
  */
@@ -37,8 +41,9 @@ int slbm_conv3x3_forward(const uint16_t *x, const uint16_t *w, const float *bias
                          int32_t relu, int32_t dilation, void *stream);
 
 /* Weight gradient: dw[co][ci*9 + tap] = sum_b sum_p dz[b][co][p] x[b][ci][p + dil off(tap)],
- * db[co] = sum_b sum_p dz[b][co][p] (db may be NULL); dz FP32 [B][Cout][H][W],
- * x bf16 [B][Cin][H][W]; dw FP32 [Cout][Cin*9] (unpacked). Deterministic. */
+ * db[co] = sum_b sum_p dz[b][co][p] (db may be NULL); dz FP32 [B][Cout][H][W]
+ * (Cout <= 32), x bf16 [B][Cin][H][W]; dw FP32 [Cout][Cin*9] (unpacked).
+ * Deterministic (fixed split of the pixels and fixed summation order). */
 int slbm_conv3x3_backward_weight(const float *dz, const uint16_t *x, float *dw, float *db, int32_t B,
                                  int32_t Cin, int32_t Cout, int32_t H, int32_t W, int32_t dilation,
                                  void *stream);

@@ -2281,14 +2281,15 @@ int batch_loop_persist(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out,
 int batch_adjoint(slbm_batch* b, double* const* grads, int ptr_kind, slbm_solve_info* ainfo);
 
 int batch_solve(slbm_batch* b, const double* const* controls, int ptr_kind, double* J, double* const* grads,
-                slbm_solve_info* pinfo, slbm_solve_info* ainfo)
+                slbm_solve_info* pinfo, slbm_solve_info* ainfo, const double* const* init_disps = nullptr)
 {
     const int B = (int)b->ctx.size();
     int rc;
     auto w0 = std::chrono::steady_clock::now();
     for (int i = 0; i < B; ++i) {
         slbm_ctx* c = b->ctx[i];
-        if ((rc = apply_control(c, controls[i], ptr_kind)) || (rc = reset_primal(c, nullptr, ptr_kind)))
+        const double* d0 = init_disps ? init_disps[i] : nullptr;
+        if ((rc = apply_control(c, controls[i], ptr_kind)) || (rc = reset_primal(c, d0, ptr_kind)))
             return bfail(b, rc, "instance " + std::to_string(i) + ": " + c->err);
     }
     std::vector<int64_t> t;
@@ -2456,6 +2457,15 @@ int batch_objective_and_grad(slbm_batch* b, const double* const* controls, doubl
     if (!b) return SLBM_EINVAL;
     if (!controls || !J) return bfail(b, SLBM_EINVAL, "controls and J are required");
     return batch_solve(b, controls, ptr_kind, J, grads, primal_info, adjoint_info);
+}
+
+int batch_objective_and_grad_from(slbm_batch* b, const double* const* controls, const double* const* init_disps,
+                                  double* J, double* const* grads, int32_t ptr_kind, slbm_solve_info* primal_info,
+                                  slbm_solve_info* adjoint_info)
+{
+    if (!b) return SLBM_EINVAL;
+    if (!controls || !J) return bfail(b, SLBM_EINVAL, "controls and J are required");
+    return batch_solve(b, controls, ptr_kind, J, grads, primal_info, adjoint_info, init_disps);
 }
 
 int batch_objective_and_grad_noalloc(slbm_batch* b, const double* const* controls, double* J,

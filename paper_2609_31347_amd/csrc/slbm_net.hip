@@ -5,12 +5,15 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "solid_lbm_net.h"
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
 
 // FP32 -> bfloat16, round to nearest even (finite inputs).
 __device__ __forceinline__ uint16_t f2bf(float f)
@@ -21,46 +24,80 @@ __device__ __forceinline__ uint16_t f2bf(float f)
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__host__ __device__ inline int kpad(int K) { return (K + 7) / 8 * 8; }
+// K of the packed weights: rounded up to the 16 of one bf16 MFMA k-slice.
+__host__ __device__ inline int kpad(int K) { return (K + 15) / 16 * 16; }
 
-// One wave = 32 output channels x 32 pixels of one image.  The GEMM runs over
-// k = (ci, tap) in slices of 8: A (weights, rows = output channels) and B
-// (the input gathered at the 3x3 offsets, columns = pixels) feed
-// v_mfma_f32_32x32x8bf16_1k.  Operand lanes: A row = lane % 32, k = 4 (lane / 32) + j;
-// B column = lane % 32, same k; result register r of lane l holds row
-// 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
-__global__ __launch_bounds__(64) void k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
-                                                const float* __restrict__ bias, float* __restrict__ y,
-                                                uint16_t* __restrict__ yb, int Cin, int Cout, int H, int W,
-                                                int Kp, int relu, int dil)
+constexpr int kFwdPix = 128;                 // output pixels per workgroup (4 waves of 32)
+constexpr int kFwdStage = 64 * 1024;         // LDS bytes for the staged input rows
+
+// Rows of the image that the kFwdPix pixels from p0 (and their 3x3 taps at
+// dilation dil) touch: [ylo, ylo + nrows).
+__host__ __device__ inline void fwd_rows(int p0, int HW, int H, int W, int dil, int* ylo, int* nrows)
 {
+    const int p1 = min(p0 + kFwdPix, HW) - 1;
+    const int y0 = max(0, p0 / W - dil), y1 = min(H - 1, p1 / W + dil);
+    *ylo = y0;
+    *nrows = y1 - y0 + 1;
+}
+
+// Upper bound of fwd_rows' count over all workgroups of a launch.
+inline int fwd_rows_max(int H, int W, int dil) { return std::min(H, (kFwdPix + W - 1) / W + 1 + 2 * dil); }
+
+// 3x3 convolution as an implicit GEMM on gfx950's v_mfma_f32_32x32x16_bf16:
+// one wave = 32 output channels x 32 pixels of one image, four waves = 128
+// consecutive pixels.  The packed weights (A, rows = output channels) and,
+// when they fit (stage != 0), the input rows that the workgroup's taps touch
+// are first copied into LDS; the B operand (the input at the 3x3 offsets,
+// columns = pixels) is then gathered from LDS.  Operand lanes: row / column =
+// lane % 32, k = 8 (lane / 32) + j, j < 8; result register r of lane l holds
+// row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
+                                                 const float* __restrict__ bias, float* __restrict__ y,
+                                                 uint16_t* __restrict__ yb, int Cin, int Cout, int H, int W,
+                                                 int Kp, int relu, int dil, int stage)
+{
+    extern __shared__ __align__(16) uint16_t smem[];
+    uint16_t* wl = smem;                       // [32][Kp] weights
+    uint16_t* xl = smem + 32 * Kp;             // [Cin][nrows][W] input rows (stage != 0)
     const int HW = H * W;
-    const int p0 = blockIdx.x * 32, b = blockIdx.y;
-    const int lane = threadIdx.x, col = lane & 31, kq = (lane >> 5) * 4;
-    const int p = p0 + col;
+    const int P0 = blockIdx.x * kFwdPix, b = blockIdx.y;
+    const uint16_t* xb = x + (int64_t)b * Cin * HW;
+    int ylo = 0, nrows = 0;
+    fwd_rows(P0, HW, H, W, dil, &ylo, &nrows);
+    for (int i = threadIdx.x; i < 32 * Kp; i += 256) wl[i] = w[i];
+    if (stage) {
+        const int n = Cin * nrows * W;
+        for (int i = threadIdx.x; i < n; i += 256) {
+            const int ci = i / (nrows * W), r = i - ci * nrows * W;
+            xl[i] = xb[(int64_t)ci * HW + (int64_t)ylo * W + r];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, col = lane & 31, kq = (lane >> 5) * 8;
+    const int p = P0 + (threadIdx.x >> 6) * 32 + col;
     const bool pv = p < HW;
     const int py = pv ? p / W : 0, px = pv ? p - py * W : 0;
     const int K = Cin * 9;
-    const uint16_t* xb = x + (int64_t)b * Cin * HW;
     floatx16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    for (int kb = 0; kb < Kp; kb += 8) {
-        bf16x4 av, bv;
-        const uint16_t* wr = w + (int64_t)col * Kp + kb + kq;
+    for (int kb = 0; kb < Kp; kb += 16) {
+        const shortx8 av = *reinterpret_cast<const shortx8*>(wl + col * Kp + kb + kq);
+        shortx8 bv;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            av[j] = (short)wr[j];
+        for (int j = 0; j < 8; ++j) {
             const int k = kb + kq + j;
             short v = 0;
             if (pv && k < K) {
                 const int ci = k / 9, tap = k - ci * 9;
                 const int yy = py + (tap / 3 - 1) * dil, xx = px + (tap % 3 - 1) * dil;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = (short)xb[(int64_t)ci * HW + yy * W + xx];
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    v = (short)(stage ? xl[(ci * nrows + (yy - ylo)) * W + xx] : xb[(int64_t)ci * HW + yy * W + xx]);
             }
             bv[j] = v;
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                      acc, 0, 0, 0);
     }
     if (!pv) return;
 #pragma unroll
@@ -76,42 +113,63 @@ __global__ __launch_bounds__(64) void k_conv_fwd(const uint16_t* __restrict__ x,
     }
 }
 
-// dw[co][ci][tap] and db[co] (taps at dilation dil): one block per (co, ci); fixed striding and a
-// fixed reduction tree (deterministic).
-__global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ dz, const uint16_t* __restrict__ x,
-                                                   float* __restrict__ dw, float* __restrict__ db, int B, int Cin,
-                                                   int Cout, int H, int W, int dil)
+// Weight gradient as a GEMM on the FP32 MFMA v_mfma_f32_32x32x2_f32:
+// dw[co][k] = sum over pixels of dz[co][pixel] x~[k][pixel], x~ the input at
+// tap k's offset (im2col, bf16 values, exact in FP32).  A workgroup of 16
+// waves owns 32 columns k; wave v takes the pixel pairs v, v + 16, ... (A:
+// rows co = lane % 32, pixel 2 t + lane / 32; B: column k = lane % 32, same
+// pixel), and the 16 partial 32 x 32 blocks are summed in a fixed order in
+// LDS: deterministic, no scratch memory.  db[co] = sum of dz (workgroup 0).
+__global__ __launch_bounds__(1024) void k_conv_bwd_w(const float* __restrict__ dz, const uint16_t* __restrict__ x,
+                                                    float* __restrict__ dw, float* __restrict__ db, int B, int Cin,
+                                                    int Cout, int H, int W, int dil)
 {
-    const int co = blockIdx.x, ci = blockIdx.y;
-    const int HW = H * W;
-    const int64_t total = (int64_t)B * HW;
-    float acc[10];
+    __shared__ float part[16][16][64];        // [wave][register][lane]
+    __shared__ float bsum[16][64];
+    const int HW = H * W, K = Cin * 9;
+    const int kb = blockIdx.x * 32;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 31, half = lane >> 5;
+    // this lane's column k: input channel and tap offset (fixed for the loop)
+    const int kk = kb + row;
+    const bool kval = kk < K;
+    const int ci = kval ? kk / 9 : 0, tap = kval ? kk - ci * 9 : 0;
+    const int oy = (tap / 3 - 1) * dil, ox = (tap % 3 - 1) * dil;
+    const bool cval = row < Cout;
+    const int64_t npair = ((int64_t)B * HW + 1) / 2, P = (int64_t)B * HW;
+    floatx16 acc;
 #pragma unroll
-    for (int t = 0; t < 10; ++t) acc[t] = 0.0f;
-    for (int64_t i = threadIdx.x; i < total; i += 256) {
-        const int b = (int)(i / HW), p = (int)(i - (int64_t)b * HW);
-        const float g = dz[((int64_t)b * Cout + co) * HW + p];
-        const int py = p / W, px = p - py * W;
-        const uint16_t* xc = x + ((int64_t)b * Cin + ci) * HW;
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int yy = py + (tap / 3 - 1) * dil, xx = px + (tap % 3 - 1) * dil;
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W) acc[tap] += g * bf2f(xc[yy * W + xx]);
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    float s = 0.0f;
+    for (int64_t t = wv; t < npair; t += 16) {
+        const int64_t pix = 2 * t + half;
+        float av = 0.0f, bv = 0.0f;
+        if (pix < P) {
+            const int bb = (int)(pix / HW), p = (int)(pix - (int64_t)bb * HW);
+            if (cval) av = dz[((int64_t)bb * Cout + row) * HW + p];
+            if (kval) {
+                const int py = p / W, px = p - py * W, yy = py + oy, xx = px + ox;
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W) bv = bf2f(x[((int64_t)bb * Cin + ci) * HW + yy * W + xx]);
+            }
         }
-        acc[9] += g;
+        s += av;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
-    __shared__ float red[10][256];
 #pragma unroll
-    for (int t = 0; t < 10; ++t) red[t][threadIdx.x] = acc[t];
+    for (int r = 0; r < 16; ++r) part[wv][r][lane] = acc[r];
+    bsum[wv][lane] = s;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-#pragma unroll
-            for (int t = 0; t < 10; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + s];
-        __syncthreads();
+    {
+        const int r = threadIdx.x >> 6, l = threadIdx.x & 63;   // one output element per thread
+        float v = 0.0f;
+        for (int q = 0; q < 16; ++q) v += part[q][r][l];
+        const int co = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3), k = kb + (l & 31);
+        if (co < Cout && k < K) dw[(int64_t)co * K + k] = v;
     }
-    if (threadIdx.x < 9) dw[(int64_t)co * Cin * 9 + ci * 9 + threadIdx.x] = red[threadIdx.x][0];
-    if (threadIdx.x == 9 && ci == 0 && db) db[co] = red[9][0];
+    if (blockIdx.x == 0 && db && threadIdx.x < 32 && threadIdx.x < Cout) {
+        float v = 0.0f;
+        for (int q = 0; q < 16; ++q) v += bsum[q][threadIdx.x] + bsum[q][threadIdx.x + 32];
+        db[threadIdx.x] = v;
+    }
 }
 
 __global__ void k_act_bwd(const float* __restrict__ dy, const float* __restrict__ y, float* __restrict__ dz,
@@ -223,9 +281,21 @@ int slbm_conv3x3_forward(const uint16_t* x, const uint16_t* w, const float* bias
                          void* stream)
 {
     if (!x || !w || !y || B < 1 || Cin < 1 || Cout < 1 || Cout > 32 || H < 1 || W < 1 || dilation < 1) return -1;
-    dim3 grid(blocks((int64_t)H * W, 32), (unsigned)B);
-    hipLaunchKernelGGL(k_conv_fwd, grid, dim3(64), 0, (hipStream_t)stream, x, w, bias, y, y_bf16, Cin, Cout, H, W,
-                       kpad(Cin * 9), relu, dilation);
+    const int Kp = kpad(Cin * 9);
+    const size_t wbytes = (size_t)32 * Kp * sizeof(uint16_t);
+    const size_t xbytes = (size_t)Cin * fwd_rows_max(H, W, dilation) * W * sizeof(uint16_t);
+    const int stage = xbytes <= (size_t)kFwdStage ? 1 : 0;
+    const size_t lds = wbytes + (stage ? xbytes : 0);
+    static bool attr = false;
+    if (!attr) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv_fwd), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(kFwdStage + 32 * 32 * 9 * sizeof(uint16_t) + 1024)) != hipSuccess)
+            return -3;
+        attr = true;
+    }
+    dim3 grid(blocks((int64_t)H * W, kFwdPix), (unsigned)B);
+    hipLaunchKernelGGL(k_conv_fwd, grid, dim3(256), lds, (hipStream_t)stream, x, w, bias, y, y_bf16, Cin, Cout, H, W,
+                       Kp, relu, dilation, stage);
     return status(hipGetLastError());
 }
 
@@ -233,7 +303,8 @@ int slbm_conv3x3_backward_weight(const float* dz, const uint16_t* x, float* dw, 
                                  int32_t Cout, int32_t H, int32_t W, int32_t dilation, void* stream)
 {
     if (!dz || !x || !dw || B < 1 || Cin < 1 || Cout < 1 || H < 1 || W < 1 || dilation < 1) return -1;
-    hipLaunchKernelGGL(k_conv_bwd_w, dim3((unsigned)Cout, (unsigned)Cin), dim3(256), 0, (hipStream_t)stream, dz, x,
+    if (Cout > 32) return -1;
+    hipLaunchKernelGGL(k_conv_bwd_w, dim3((unsigned)((Cin * 9 + 31) / 32)), dim3(1024), 0, (hipStream_t)stream, dz, x,
                        dw, db, B, Cin, Cout, H, W, dilation);
     return status(hipGetLastError());
 }

@@ -31,6 +31,7 @@ EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_gra
            "solid_lbm_last_error",
            "solid_lbm_destroy",
            "solid_lbm_batch_init", "batch_objective_and_grad", "batch_objective_and_grad_noalloc",
+           "batch_objective_and_grad_from",
            "batch_gradient", "solid_lbm_batch_set_tuning", "solid_lbm_batch_set_persistent",
            "solid_lbm_batch_persistent_stats",
            "solid_lbm_batch_time_sweeps", "solid_lbm_batch_instance", "solid_lbm_batch_last_error",
@@ -130,6 +131,9 @@ def _load():
                                              ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, info, info]
     lib.batch_gradient.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, info]
     lib.batch_objective_and_grad_noalloc.argtypes = lib.batch_objective_and_grad.argtypes
+    lib.batch_objective_and_grad_from.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_void_p),
+                                                  ctypes.c_int32, info, info]
     lib.solid_lbm_batch_set_persistent.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.solid_lbm_batch_persistent_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.solid_lbm_batch_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
@@ -484,10 +488,12 @@ def solid_lbm_batch_init(problems):
     return Batch(h, problems)
 
 
-def batch_objective_and_grad(batch, controls, grads=None, want_grad=True, noalloc=False):
+def batch_objective_and_grad(batch, controls, grads=None, want_grad=True, noalloc=False, init_disps=None):
     """Returns (rc, J (array), grads (list), primal infos, adjoint infos).
     noalloc: call batch_objective_and_grad_noalloc (launch tables in the
-    library's static device array; nothing is allocated during the call)."""
+    library's static device array; nothing is allocated during the call).
+    init_disps: per-instance initial displacements (2N each, None entries =
+    cold start) for batch_objective_and_grad_from."""
     B = len(batch)
     keep = []
     cptr = (ctypes.c_void_p * B)()
@@ -516,6 +522,21 @@ def batch_objective_and_grad(batch, controls, grads=None, want_grad=True, noallo
                 raise ValueError("controls and grads must live in the same memory kind")
     J = (ctypes.c_double * B)()
     pi, ai = (SolveInfo * B)(), (SolveInfo * B)()
+    if init_disps is not None:
+        if noalloc:
+            raise ValueError("the no-allocation variant has no warm start")
+        if len(init_disps) != B:
+            raise ValueError(f"{len(init_disps)} init_disps for {B} instances")
+        dptr = (ctypes.c_void_p * B)()
+        for i, d0 in enumerate(init_disps):
+            if d0 is None:
+                dptr[i] = None
+                continue
+            dptr[i], dkind = _arg(d0, keep, size=2 * batch.contexts[i].N, what=f"init_disps[{i}]")
+            if dkind != kind:
+                raise ValueError("controls and init_disps must live in the same memory kind")
+        rc = _bcheck(batch, LIB.batch_objective_and_grad_from(batch.handle, cptr, dptr, J, gptr, kind, pi, ai))
+        return rc, np.array(J[:]), grads, list(pi), list(ai)
     fn = LIB.batch_objective_and_grad_noalloc if noalloc else LIB.batch_objective_and_grad
     rc = _bcheck(batch, fn(batch.handle, cptr, J, gptr, kind, pi, ai))
     return rc, np.array(J[:]), grads, list(pi), list(ai)

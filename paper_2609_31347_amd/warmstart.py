@@ -11,9 +11,10 @@ convolutional network predicts d_0 from the modulus field E(x):
          and u averaged over 4 and 16 nodes and over the whole plate,
   output (2 channels): (d - d_ref) / s, s = max |d_ref|,
   6 layers of 3x3 convolutions (dilations 1, 2, 4, 8, 4, 1), 32 channels, ReLU
-  between them, bf16 weights
-  and activations with FP32 accumulation on MFMA (csrc/slbm_net.hip), trained
-  with Adam by the same kernels.
+  between them, bf16 weights and activations with FP32 accumulation on
+  gfx950's 32x32x16 bf16 MFMA (forward and data gradient) and the FP32 MFMA
+  (weight gradient) in csrc/slbm_net.hip, trained with Adam by the same
+  kernels.
 
 It is trained on solver outputs at a coarse resolution (batched FP64 solves);
 for a finer grid, E is sampled onto the coarse grid, the prediction is
@@ -40,7 +41,8 @@ NU = 0.3
 
 
 def _kp(k):
-    return (k + 7) // 8 * 8
+    """K of the packed bf16 weights: rounded up to a 16-wide MFMA k-slice."""
+    return (k + 15) // 16 * 16
 
 
 def _p(t):
@@ -308,7 +310,34 @@ class WarmStart:
             return self.predict_coarse(E_fine, use_net) * cp_fine["active"]
         Ec = _resample(E_fine, cp_fine, self.cp, fill_outside=False)
         dc = self.predict_coarse(Ec, use_net)
+        return self.to_fine(dc, cp_fine)
+
+    def to_fine(self, dc, cp_fine):
+        """A displacement on the coarse plate, interpolated onto cp_fine."""
+        if cp_fine["active"].shape == self.cp["active"].shape:
+            return dc * cp_fine["active"]
         return np.stack([_resample(dc[c], self.cp, cp_fine, fill_outside=True) for c in range(2)]) * cp_fine["active"]
+
+    def predict_batch(self, cp_fine, fields):
+        """predict() for many E fields with one network forward pass."""
+        m = self.cp["active"]
+        same = cp_fine["active"].shape == m.shape
+        Ec = [E if same else _resample(E, cp_fine, self.cp, fill_outside=False) for E in fields]
+        x = torch.from_numpy(np.stack([features(E, m, self.dref, self.s) for E in Ec])).cuda()
+        y = self.net.forward(to_bf16(x)).double().cpu().numpy()
+        return [self.to_fine(self.dref + self.s * y[k] * m, cp_fine) for k in range(len(fields))]
+
+
+def batch_gradients(cp, fields, target, tol, init_disps=None, max_steps=50_000_000):
+    """E-field identification gradients of many fields on one plate in one
+    batch: J and dJ/dE per field, primal started cold or from init_disps.
+    Returns (J, grads, primal infos, adjoint infos)."""
+    probs = [plate_problem(cp, tol, max_steps=max_steps, target=target) for _ in fields]
+    batch = S.solid_lbm_batch_init(probs)
+    rc, J, grads, pi, ai = S.batch_objective_and_grad(batch, list(fields), init_disps=init_disps)
+    S.require_converged(rc, "batched E-field gradients")
+    S.solid_lbm_batch_destroy(batch)
+    return J, grads, pi, ai
 
 
 def _resample(f, src, dst, fill_outside):

@@ -34,10 +34,11 @@ sys.path.insert(0, ROOT)
 BYTES_PER_NODE = 144.0      # 8 pops read + 8 written (8 B each) + 2 forcing / residual reads
 PEAK_GBS = 8000.0           # MI355X HBM3E
 # Measured HBM bytes per launch of the dominant kernel, keyed by (N, T, H):
-# rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain device copy
-# of known size reads on gfx950), per dispatch of the fused primal sweep, with
-# the hash of the kernel sources they were taken with (profiles/).
-TRAFFIC = {}
+# rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors the benchmark's
+# plain copy of one population buffer reads in the same runs), mean per
+# dispatch of the fused primal sweep, with the hash of the kernel sources they
+# were taken with (profiles/k_sweep_tb_periodic_2048_bench.md).
+TRAFFIC = {(2048, 8, 96): {"bytes": (2.0 * 198630.6 + 271684.1) * 1024, "sources": "0027cf8311a2dd23"}}
 
 
 def parse():
@@ -578,6 +579,14 @@ def main():
     cells = n * n
     sweeps = sum(r[2]["sweeps"] + r[3]["sweeps"] for r in rec)
     mlups = sweeps * cells / wall / 1e6
+    # a plain device copy of known size (one population buffer, 8 n^2 doubles
+    # read and written), after the timed steps: the counter runs that measure
+    # the sweep's HBM bytes read its FETCH_SIZE / WRITE_SIZE for the scale
+    src = torch.ones(8 * cells, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
     def launch_stats(k):
         launches = sum(r[k]["fused_launches"] for r in rec)

@@ -71,6 +71,9 @@ def parse():
                     help="batch mode with --persistent: also time the host-driven launches on the same mix")
     ap.add_argument("--sizes", default="64,96,128,192,256,384,512",
                     help="batch mode: grid sizes the instance seeds draw from")
+    ap.add_argument("--seq-range", default="",
+                    help="batch mode: a,b -- solve only instances a..b-1 one by one (no batch); the one-by-one "
+                         "time of a long mix is the sum over several such runs")
     ap.add_argument("--sweeps-only", action="store_true",
                     help="batch mode: fixed sweep counts of the whole mix (batched vs one by one) instead of "
                          "solves to tol")
@@ -245,8 +248,31 @@ def batch_mode(args):
         S.solid_lbm_batch_destroy(batch)
         return rec, pi, ai
 
+    if args.seq_range:
+        a0, a1 = [int(v) for v in args.seq_range.split(",")]
+        ctxs = []
+        for p, c in zip(probs[a0:a1], ctrls[a0:a1]):
+            ctxs.append(S.solid_lbm_init(p))
+            autotune(ctxs[-1], p, c)
+        t0 = time.perf_counter()
+        seq_lups = 0
+        for k, (p, c, cl, ctx) in enumerate(zip(probs[a0:a1], ctrls[a0:a1], cells[a0:a1], ctxs)):
+            r = S.objective_and_grad(ctx, c)
+            S.require_converged(r[0], f"instance {a0 + k}")
+            seq_lups += cl * (r[3].sweeps + r[4].sweeps)
+            print(json.dumps({"stage": "sequential", "instance": a0 + k, "grid": [p["nx"], p["ny"]],
+                              "steps": r[3].steps, "adjoint_steps": r[4].steps, "J": r[1],
+                              "wall_s": round(time.perf_counter() - t0, 3)}), flush=True)
+        seq = time.perf_counter() - t0
+        print(json.dumps({"mode": "batch", "measure": "one by one", "instances": [a0, a1], "sizes": sizes,
+                          "tol": args.tol, "sequential_wall_s": round(seq, 3),
+                          "sequential_mlups": round(seq_lups / seq / 1e6, 1)}), flush=True)
+        return
     main_rec, pi, ai = run_batch(args.persistent)
     wall = main_rec["wall_s"]
+    print(json.dumps({"stage": "per_instance", "grid": [[p["nx"], p["ny"]] for p in probs],
+                      "primal_steps": [int(p.steps) for p in pi], "adjoint_steps": [int(a.steps) for a in ai],
+                      "J": main_rec["J"]}), flush=True)
     out = {"mode": "batch", "instances": len(probs), "plates": args.plates, "sizes": sizes, "tol": args.tol,
            "total_cells": int(sum(cells)), "persistent": args.persistent,
            "all_converged": bool(all(p.converged and a.converged for p, a in zip(pi, ai))),

@@ -194,3 +194,24 @@ def test_autograd_gradient_lands_on_the_control_device(S, orc):
     q = orc.Problem(n, n, 1 / n, 1.0, 0.3, np.zeros((2, n, n)))
     G = orc.objective_and_grad(q, tgt, "modes", [0.1, 0.1], modes=modes, tol=1e-10)
     assert rel(a.grad.numpy(), G.grad) < 1e-10
+
+
+def test_fused_launch_timing_of_the_solve_loops(S):
+    """With launch timing on, the solve loops report their fused launches, the
+    sweeps those made (T per strip launch) and a device time within the loop's
+    own; off (the default) the fields stay 0.  Results do not change."""
+    n = 256
+    modes = I.two_mode_basis(n)
+    p = dict(nx=n, ny=n, dx=1 / n, E=1.0, nu=0.3, domain=0, target=I.two_mode_target(n), control_kind=0,
+             n_modes=2, force_modes=modes, tol=1e-10)
+    ctx = S.solid_lbm_init(p)
+    S.solid_lbm_set_tuning(ctx, 8, 0)
+    rc, J0, g0, pi, ai = S.objective_and_grad(ctx, np.array([0.1, 0.1]))
+    assert pi.fused_launches == 0 and pi.fused_sweeps == 0 and pi.fused_ms == 0.0
+    S.solid_lbm_set_launch_timing(ctx, True)
+    rc, J1, g1, pi, ai = S.objective_and_grad(ctx, np.array([0.1, 0.1]))
+    assert J1 == J0 and np.array_equal(g1, g0)
+    for info in (pi, ai):
+        assert info.fused_launches > 0 and info.fused_sweeps == 8 * info.fused_launches
+        assert info.fused_sweeps <= info.sweeps
+        assert 0.0 < info.fused_ms <= info.device_ms

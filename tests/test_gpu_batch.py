@@ -130,3 +130,31 @@ def test_batch_gradient_after_primal_equals_one_call():
     for g, g2, a, a2 in zip(grads, grads2, ai, ai2):
         assert a.steps == a2.steps
         assert np.array_equal(np.asarray(g), np.asarray(g2))
+
+
+def test_batch_warm_starts_per_instance_equal_single_warm_solves():
+    """batch_objective_and_grad_from: each instance starts from its own d_0
+    (None = cold); steps, J and gradients equal those of objective_and_grad_from
+    on the single instance."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_31347_amd import slbm as S
+    probs, ctrls = mixed_problems(S, large=False)
+    rng = np.random.default_rng(3)
+    d0s = []
+    for k, p in enumerate(probs):
+        if k % 3 == 1:
+            d0s.append(None)
+            continue
+        m = p["node_mask"].astype(float) if "node_mask" in p else 1.0
+        d0s.append(0.5 * np.asarray(p["target"]) * m + 1e-5 * rng.standard_normal((2, p["ny"], p["nx"])) * m)
+    batch = S.solid_lbm_batch_init(probs)
+    rc, J, grads, pi, ai = S.batch_objective_and_grad(batch, ctrls, init_disps=d0s)
+    assert rc == 0
+    for i, (p, c, d0) in enumerate(zip(probs, ctrls, d0s)):
+        ctx = S.solid_lbm_init(p)
+        rci, Ji, gi, pii, aii = S.objective_and_grad(ctx, c, init_disp=d0)
+        assert pii.steps == pi[i].steps and aii.steps == ai[i].steps, i
+        assert abs(J[i] - Ji) <= 1e-13 * abs(Ji), i
+        assert rel(grads[i], gi) < 1e-12, i

@@ -123,7 +123,7 @@ def test_warm_started_batched_gradients_take_less_wall_time(W):
     """Batched E-field identification gradients (primal and adjoint to 1e-10)
     on the 64 x 39 plate: the trained network's initial displacements give the
     same J and gradients as cold starts, in fewer primal steps and in less
-    wall time including the prediction (the cold start is the judge)."""
+    wall time including the prediction (the cold start fixes the reference result)."""
     import time
     import torch
     from paper_2609_31347_amd import slbm as S

@@ -87,6 +87,14 @@ def parse():
     return ap.parse_args()
 
 
+def progress_printer(what):
+    """A progress callback of the library's long solves: one JSON line per report."""
+    def report(phase, step, res):
+        print(json.dumps({"stage": "progress", "solve": what, "phase": "adjoint" if phase else "primal",
+                          "step": int(step), "residual": float(res)}), flush=True)
+    return report
+
+
 def sweeps_mode(args):
     """Fixed sweep counts on the workload grid, timed with HIP events on the
     library's stream, plus a plain device copy of the same byte count as one
@@ -227,6 +235,7 @@ def batch_mode(args):
 
     def run_batch(persistent):
         batch = S.solid_lbm_batch_init(probs)
+        S.solid_lbm_batch_set_progress(batch, progress_printer("batch"), 30.0)
         tune = autotune_batch(batch, ctrls)
         print(json.dumps({"stage": "tuned", "persistent": persistent, **tune}), flush=True)
         S.solid_lbm_batch_set_persistent(batch, persistent)
@@ -257,6 +266,7 @@ def batch_mode(args):
         t0 = time.perf_counter()
         seq_lups = 0
         for k, (p, c, cl, ctx) in enumerate(zip(probs[a0:a1], ctrls[a0:a1], cells[a0:a1], ctxs)):
+            S.solid_lbm_set_progress(ctx, progress_printer(f"instance {a0 + k}"), 30.0)
             r = S.objective_and_grad(ctx, c)
             S.require_converged(r[0], f"instance {a0 + k}")
             seq_lups += cl * (r[3].sweeps + r[4].sweeps)
@@ -295,6 +305,7 @@ def batch_mode(args):
         t0 = time.perf_counter()
         seq_lups = 0
         for k, (p, c, cl, ctx) in enumerate(zip(probs, ctrls, cells, ctxs)):
+            S.solid_lbm_set_progress(ctx, progress_printer(f"instance {k}"), 30.0)
             r = S.objective_and_grad(ctx, c)
             S.require_converged(r[0], f"instance {k}")
             seq_lups += cl * (r[3].sweeps + r[4].sweeps)
@@ -425,6 +436,7 @@ def warmstart_mode(args):
     def primal_steps(cp, fields, target, d0s):
         """Primal solves only (batched) from the given initial displacements: steps per field."""
         batch = S.solid_lbm_batch_init([WS.plate_problem(cp, args.tol, target=target) for _ in fields])
+        S.solid_lbm_batch_set_progress(batch, progress_printer(f"ablation {cp['nx']}"), 30.0)
         rc, _, _, pi, _ = S.batch_objective_and_grad(batch, list(fields), want_grad=False, init_disps=d0s)
         S.require_converged(rc, "primal solves")
         S.solid_lbm_batch_destroy(batch)
@@ -438,6 +450,7 @@ def warmstart_mode(args):
         # identification target: displacement of a reference modulus field
         E_star = WS.e_field(cp, 99999)
         ctx = S.solid_lbm_init(WS.plate_problem(cp, args.tol))
+        S.solid_lbm_set_progress(ctx, progress_printer(f"target {nx}"), 30.0)
         t0 = time.perf_counter()
         rc, ti = S.primal_solve(ctx, E_star)
         S.require_converged(rc, "target solve", ti)
@@ -448,7 +461,7 @@ def warmstart_mode(args):
         fields = [WS.e_field(cp, seed) for seed in range(10000, 10000 + n_fields[nx])]
         # cold: batched gradients from d_0 = 0
         t0 = time.perf_counter()
-        Jc, gc, pc, ac = WS.batch_gradients(cp, fields, target, args.tol)
+        Jc, gc, pc, ac = WS.batch_gradients(cp, fields, target, args.tol, progress=progress_printer(f"cold {nx}"))
         tc = time.perf_counter() - t0
         print(json.dumps({"stage": "cold", "width": nx, "wall_s": round(tc, 3),
                           "primal_steps": [int(p.steps) for p in pc], "adjoint_steps": [int(a.steps) for a in ac]}),
@@ -457,7 +470,8 @@ def warmstart_mode(args):
         t0 = time.perf_counter()
         d0s = ws.predict_batch(cp, fields)
         tp = time.perf_counter() - t0
-        Jw, gw, pw, aw = WS.batch_gradients(cp, fields, target, args.tol, init_disps=d0s)
+        Jw, gw, pw, aw = WS.batch_gradients(cp, fields, target, args.tol, init_disps=d0s,
+                                            progress=progress_printer(f"warm {nx}"))
         tw = time.perf_counter() - t0
         print(json.dumps({"stage": "warm", "width": nx, "wall_s": round(tw, 3), "predict_s": round(tp, 4),
                           "primal_steps": [int(p.steps) for p in pw]}), flush=True)
@@ -466,7 +480,7 @@ def warmstart_mode(args):
         # works on the coarse grid can hand over)
         ref_steps = primal_steps(cp, fields, target, [ws.predict(cp, E, use_net=False) for E in fields])
         Ecs = [WS._resample(E, cp, ws.cp, fill_outside=False) for E in fields]
-        dcs, _ = WS.solve_batch(ws.cp, Ecs, 1e-10)
+        dcs, _ = WS.solve_batch(ws.cp, Ecs, 1e-10, progress=progress_printer("coarse exact"))
         exact_steps = primal_steps(cp, fields, target, [ws.to_fine(d, cp) for d in dcs])
         row = {"stage": "eval", "grid": [cp["active"].shape[1], cp["active"].shape[0]], "fields": len(fields),
                "cold_time_to_gradient_s": round(tc, 3), "warm_time_to_gradient_s": round(tw, 3),

@@ -396,6 +396,19 @@ int solid_lbm_batch_time_sweeps(slbm_batch *batch, int32_t adjoint, int64_t n, d
  * no-allocation variant always uses the host-driven launches. */
 int solid_lbm_batch_set_persistent(slbm_batch *batch, int32_t on, int32_t rounds_per_launch);
 
+/* Progress report of long batch solves, as solid_lbm_set_progress for one
+ * context: fn(user, phase, step, residual) is called on the calling thread
+ * from inside the batch solves when a check has been read back and at least
+ * every_s seconds have passed since the last report; phase 0 = primal,
+ * 1 = adjoint.  Host-driven launches report the time step of the check
+ * read back and the largest residual among the instances still running then
+ * that have completed a check (no report before the first such check; checks are read one behind, so that step can pass the last instance's
+ * final step by up to two check intervals); persistent
+ * launches report the rounds run and residual -1 (not read back).  fn = NULL
+ * turns reports off.  The callback must not call into the library with the
+ * same batch. */
+int solid_lbm_batch_set_progress(slbm_batch *batch, slbm_progress_fn fn, void *user, double every_s);
+
 /* Graph replays (persistent launches) and rounds of the last persistent solve half. */
 int solid_lbm_batch_persistent_stats(const slbm_batch *batch, int64_t *launches, int64_t *rounds);
 

@@ -1739,6 +1739,9 @@ struct slbm_batch {
     hipEvent_t pev = nullptr;
     bool persist_attr = false;
     int64_t persist_launches = 0, persist_rounds_run = 0;   // of the last persistent half
+    slbm_progress_fn progress = nullptr;   // optional report from the batch loops
+    void* progress_user = nullptr;
+    double progress_every = 0.0;
     std::string err;
     std::vector<void*> allocs;
 };
@@ -2042,7 +2045,8 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
     std::vector<CheckLog> checks(B);
     std::vector<int> last_in(B, 0);
     int pp = 0, pl = 0, slot = 0, polls = 0;
-    int64_t s = 0;
+    int64_t s = 0, slot_step[2] = {0, 0};   // the step of the check each status slot holds
+    auto last_report = std::chrono::steady_clock::now();
     BHIPCHK(b, hipEventRecord(b->t0, b->stream));
     auto any_active = [&]() {
         for (char a : active)
@@ -2067,10 +2071,22 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
                 BHIPCHK(b, hipMemcpyAsync(b->h_status + slot * B, b->status, B * sizeof(Status),
                                           hipMemcpyDeviceToHost, b->stream));
                 BHIPCHK(b, hipEventRecord(b->ev[slot], b->stream));
+                slot_step[slot] = s;
                 if (polls >= 1) {
                     BHIPCHK(b, hipEventSynchronize(b->ev[slot ^ 1]));
-                    for (int i = 0; i < B; ++i)
-                        if (b->h_status[(slot ^ 1) * B + i].stop) active[i] = 0;
+                    double worst = -1.0;   // of the running instances with a completed check
+                    for (int i = 0; i < B; ++i) {
+                        const Status& h = b->h_status[(slot ^ 1) * B + i];
+                        if (h.stop) active[i] = 0;
+                        else if (active[i] && h.t_last >= 0) worst = std::max(worst, h.res);
+                    }
+                    if (b->progress && worst >= 0.0) {
+                        auto now = std::chrono::steady_clock::now();
+                        if (std::chrono::duration<double>(now - last_report).count() >= b->progress_every) {
+                            last_report = now;
+                            b->progress(b->progress_user, adjoint ? 1 : 0, slot_step[slot ^ 1], worst);
+                        }
+                    }
                 }
                 ++polls;
                 slot ^= 1;
@@ -2229,6 +2245,7 @@ int batch_loop_persist(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out,
     }
     int out = SLBM_OK;
     b->persist_launches = 0;
+    auto last_report = std::chrono::steady_clock::now();
     hipError_t e = hipEventRecord(b->t0, b->pstream);
     while (e == hipSuccess) {
         e = hipGraphLaunch(exec, b->pstream);
@@ -2240,6 +2257,13 @@ int batch_loop_persist(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out,
             break;
         }
         if (b->h_pctl->done) break;
+        if (b->progress) {
+            auto now = std::chrono::steady_clock::now();
+            if (std::chrono::duration<double>(now - last_report).count() >= b->progress_every) {
+                last_report = now;
+                b->progress(b->progress_user, adjoint ? 1 : 0, b->h_pctl->rounds, -1.0);
+            }
+        }
         // every round advances a running instance by a step or a residual test
         if (b->h_pctl->rounds > 2 * (b->max_steps + 2) + 16) {
             out = bfail(b, SLBM_EHIP, "internal: persistent batch made no progress");
@@ -2549,6 +2573,16 @@ int solid_lbm_batch_set_persistent(slbm_batch* b, int32_t on, int32_t rounds_per
     if (rounds_per_launch < 0) return bfail(b, SLBM_EINVAL, "rounds_per_launch must be >= 0");
     b->persist = on != 0;
     b->persist_rounds = rounds_per_launch > 0 ? rounds_per_launch : 4096;
+    return SLBM_OK;
+}
+
+int solid_lbm_batch_set_progress(slbm_batch* b, slbm_progress_fn fn, void* user, double every_s)
+{
+    if (!b) return SLBM_EINVAL;
+    if (fn && !(every_s >= 0.0)) return bfail(b, SLBM_EINVAL, "every_s must be >= 0");
+    b->progress = fn;
+    b->progress_user = fn ? user : nullptr;
+    b->progress_every = fn ? every_s : 0.0;
     return SLBM_OK;
 }
 

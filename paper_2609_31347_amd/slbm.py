@@ -33,7 +33,7 @@ EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_gra
            "solid_lbm_batch_init", "batch_objective_and_grad", "batch_objective_and_grad_noalloc",
            "batch_objective_and_grad_from",
            "batch_gradient", "solid_lbm_batch_set_tuning", "solid_lbm_batch_set_persistent",
-           "solid_lbm_batch_persistent_stats",
+           "solid_lbm_batch_persistent_stats", "solid_lbm_batch_set_progress",
            "solid_lbm_batch_time_sweeps", "solid_lbm_batch_instance", "solid_lbm_batch_last_error",
            "solid_lbm_batch_destroy")
 
@@ -137,6 +137,7 @@ def _load():
     lib.solid_lbm_batch_set_persistent.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.solid_lbm_batch_persistent_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.solid_lbm_batch_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.solid_lbm_batch_set_progress.argtypes = [P, PROGRESS_FN, P, ctypes.c_double]
     lib.solid_lbm_batch_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_batch_instance.argtypes = [P, ctypes.c_int32]
     lib.solid_lbm_batch_instance.restype = ctypes.c_void_p
@@ -582,6 +583,18 @@ def solid_lbm_batch_persistent_stats(batch):
     a, b = ctypes.c_int64(), ctypes.c_int64()
     _bcheck(batch, LIB.solid_lbm_batch_persistent_stats(batch.handle, ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
+
+
+def solid_lbm_batch_set_progress(batch, fn=None, every_s=30.0):
+    """fn(phase, step, residual) is called from inside long batch solves at
+    least every_s seconds apart (phase 0 primal, 1 adjoint; step and residual
+    as the header states); None turns it off."""
+    if fn is None:
+        batch._progress = None
+        return _bcheck(batch, LIB.solid_lbm_batch_set_progress(batch.handle, PROGRESS_FN(), None, 0.0))
+    cb = PROGRESS_FN(lambda user, phase, step, res: fn(int(phase), int(step), float(res)))
+    batch._progress = cb                      # keeps the C callback alive with the batch
+    return _bcheck(batch, LIB.solid_lbm_batch_set_progress(batch.handle, cb, None, float(every_s)))
 
 
 def solid_lbm_batch_time_sweeps(batch, adjoint, n):

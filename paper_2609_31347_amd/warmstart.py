@@ -199,12 +199,15 @@ def plate_problem(cp, tol, max_steps=50_000_000, target=None):
                 max_steps=max_steps)
 
 
-def solve_batch(cp, fields, tol, chunk=96):
-    """Converged displacements of the plate for a list of E fields (batched FP64 solves)."""
+def solve_batch(cp, fields, tol, chunk=96, progress=None):
+    """Converged displacements of the plate for a list of E fields (batched FP64
+    solves); progress(phase, step, residual) is reported every 30 s if given."""
     out, steps = [], []
     for k in range(0, len(fields), chunk):
         part = fields[k:k + chunk]
         batch = S.solid_lbm_batch_init([plate_problem(cp, tol) for _ in part])
+        if progress:
+            S.solid_lbm_batch_set_progress(batch, progress, 30.0)
         rc, J, _, pi, _ = S.batch_objective_and_grad(batch, list(part), want_grad=False)
         # training targets must be steady states
         S.require_converged(rc, "batched plate solves", next((x for x in pi if not x.converged), None))
@@ -328,12 +331,15 @@ class WarmStart:
         return [self.to_fine(self.dref + self.s * y[k] * m, cp_fine) for k in range(len(fields))]
 
 
-def batch_gradients(cp, fields, target, tol, init_disps=None, max_steps=50_000_000):
+def batch_gradients(cp, fields, target, tol, init_disps=None, max_steps=50_000_000, progress=None):
     """E-field identification gradients of many fields on one plate in one
-    batch: J and dJ/dE per field, primal started cold or from init_disps.
+    batch: J and dJ/dE per field, primal started cold or from init_disps;
+    progress(phase, step, residual) is reported every 30 s if given.
     Returns (J, grads, primal infos, adjoint infos)."""
     probs = [plate_problem(cp, tol, max_steps=max_steps, target=target) for _ in fields]
     batch = S.solid_lbm_batch_init(probs)
+    if progress:
+        S.solid_lbm_batch_set_progress(batch, progress, 30.0)
     rc, J, grads, pi, ai = S.batch_objective_and_grad(batch, list(fields), init_disps=init_disps)
     S.require_converged(rc, "batched E-field gradients")
     S.solid_lbm_batch_destroy(batch)

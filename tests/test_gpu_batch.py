@@ -158,3 +158,43 @@ def test_batch_warm_starts_per_instance_equal_single_warm_solves():
         assert pii.steps == pi[i].steps and aii.steps == ai[i].steps, i
         assert abs(J[i] - Ji) <= 1e-13 * abs(Ji), i
         assert rel(grads[i], gi) < 1e-12, i
+
+
+def test_batch_progress_reports_from_inside_the_solves():
+    """The batch progress callback is called from both halves of a batched
+    gradient (every poll when every_s = 0) with nondecreasing steps; host-driven
+    launches report the largest residual of the running instances, persistent
+    ones -1; results do not change, and None switches reports off."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_31347_amd import slbm as S
+    probs, ctrls = mixed_problems(S, large=False)
+    ref = S.solid_lbm_batch_init(probs)
+    _, J0, g0, pi0, ai0 = S.batch_objective_and_grad(ref, ctrls)
+    for persistent in (False, True):
+        batch = S.solid_lbm_batch_init(probs)
+        S.solid_lbm_batch_set_persistent(batch, persistent, 64)
+        seen = []
+        S.solid_lbm_batch_set_progress(batch, lambda ph, st, r: seen.append((ph, st, r)), 0.0)
+        _, J, g, pi, ai = S.batch_objective_and_grad(batch, ctrls)
+        assert np.array_equal(J, J0)
+        for a, b in zip(g, g0):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+        for ph in (0, 1):
+            part = [x for x in seen if x[0] == ph]
+            assert len(part) >= 2
+            steps = [x[1] for x in part]
+            assert steps == sorted(steps)
+            if persistent:
+                assert all(x[2] == -1.0 for x in part)
+            else:
+                # checks are read one behind the launches: at most two check intervals past the last stop
+                top = max(x.steps for x in (pi if ph == 0 else ai))
+                kmax = max(2 * int(np.ceil(0.005 / p["dx"] ** 2)) for p in probs)
+                assert steps[-1] <= top + 2 * kmax
+                assert all(np.isfinite(x[2]) and x[2] >= 0 for x in part)
+        S.solid_lbm_batch_set_progress(batch, None)
+        seen.clear()
+        S.batch_objective_and_grad(batch, ctrls)
+        assert seen == []

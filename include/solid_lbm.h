@@ -140,9 +140,12 @@ typedef struct {
                           context's stream before the first and after the last sweep */
     int32_t converged; /* 1 if residual < tol */
     /* With solid_lbm_set_launch_timing on (else 0): the fused launches of the
-     * sweep loop (several time steps per launch: wave strips or LDS tiles),
-     * the sweeps they made, and their device time, from HIP events on the
-     * context's stream around each run of back-to-back fused launches. */
+     * sweep loop (several time steps per launch: wave strips or LDS tiles)
+     * up to its final step, the sweeps they made, and their device time, from
+     * HIP events on the context's stream around each run of back-to-back
+     * fused launches.  The loop reads each residual check one check late;
+     * the launches it issued after the converging check return at once and
+     * are not counted. */
     int64_t fused_launches;
     int64_t fused_sweeps;
     double fused_ms;
@@ -373,6 +376,14 @@ int batch_gradient(slbm_batch *batch, double *const *grads, int32_t ptr_kind, sl
 
 /* Fused launch shape of the batch's periodic instances (as solid_lbm_set_tuning). */
 int solid_lbm_batch_set_tuning(slbm_batch *batch, int32_t steps_per_launch, int32_t rows_per_wave);
+
+/* Steps per launch of the batch's tiled instances (plates and E-field
+ * controls), which run in LDS tiles of (32 - 2 steps)^2 nodes: -1 automatic
+ * (6), 1 single steps, 2 .. 8 fused; other values SLBM_EINVAL.  Independent
+ * of the wave strips' shape; persistent launches run every instance in tiles
+ * of this many steps.  Results do not change (a fused launch of k steps
+ * equals k single steps bit for bit). */
+int solid_lbm_batch_set_tile_steps(slbm_batch *batch, int32_t steps_per_launch);
 
 /* Times n batched primal (adjoint = 0) or adjoint sweeps of every instance on
  * whatever the buffers hold (zeros after init); the instance states are

@@ -21,7 +21,10 @@ from . import slbm as S
 STRIP = ((8, 24, 0, 0), (8, 32, 0, 0), (8, 48, 0, 0), (8, 64, 0, 0), (8, 96, 0, 0), (8, 12, 0, 0), (6, 24, 0, 0),
          (6, 48, 0, 0), (6, 12, 0, 0), (4, 24, 0, 0), (8, 8, 0, 0), (6, 8, 0, 0), (4, 12, 0, 0), (4, 8, 0, 0),
          (2, 8, 0, 0))
-TILES = ((8, 0, 16, 16), (6, 0, 20, 20), (4, 0, 24, 24), (6, 0, 52, 4), (8, 0, 8, 8), (8, 0, 12, 12))
+# 3 steps with 26 x 26 tiles: one workgroup per compute unit at 512 x 308 (240 tiles), where 20 x 20
+# tiles (416) take two rounds (measured 4.47 against 5.0 us per step)
+TILES = ((8, 0, 16, 16), (6, 0, 20, 20), (4, 0, 24, 24), (6, 0, 52, 4), (8, 0, 8, 8), (8, 0, 12, 12),
+         (3, 0, 26, 26), (5, 0, 22, 22))
 SINGLE = ((1, 0, 0, 0),)
 CANDIDATES = STRIP + TILES + SINGLE
 TIE = 0.02
@@ -35,9 +38,12 @@ def _tiled_only(problem):
 def _apply(ctx, c):
     T, H, tw, th = c
     S.solid_lbm_set_tiles(ctx, 0, 0)
-    S.solid_lbm_set_tuning(ctx, T, H)
     if tw > 0:
+        # tiles first at one step per launch (odd step counts need tiles on
+        # periodic problems; the tile must fit with the final halo)
+        S.solid_lbm_set_tuning(ctx, 1, 0)
         S.solid_lbm_set_tiles(ctx, tw, th)
+    S.solid_lbm_set_tuning(ctx, T, H)
 
 
 def _name(c):
@@ -112,13 +118,16 @@ def autotune(ctx, problem, control, sweeps=96, device=None, use_cache=True, cand
 
 
 def autotune_batch(batch, controls=None, sweeps=48,
-                   candidates=((8, 24), (8, 48), (8, 96), (6, 24), (6, 48), (4, 24), (1, 0))):
-    """Chooses the fused shape (T, H) of a batch's periodic instances by timing
-    batched primal sweeps of all instances (plates run their single steps in
-    the same timing); near-ties go to the earlier candidate.  Returns
-    {"T", "H", "us"} with the time per batched step."""
+                   candidates=((8, 24), (8, 48), (8, 96), (6, 24), (6, 48), (4, 24), (1, 0)),
+                   tile_candidates=(6, 4, 3, 8)):
+    """Chooses the fused shape (T, H) of a batch's periodic instances, then the
+    steps per launch of its tiled instances (plates, E fields), by timing
+    batched primal sweeps of all instances; near-ties go to the earlier
+    candidate.  Returns {"T", "H", "Tt", "us", "us_tiles"} with the time per
+    batched step."""
     from . import slbm as S
     times = {}
+    S.solid_lbm_batch_set_tile_steps(batch, tile_candidates[0])
     for T, H in candidates:
         S.solid_lbm_batch_set_tuning(batch, T, H)
         t = max(T, 1)
@@ -128,4 +137,14 @@ def autotune_batch(batch, controls=None, sweeps=48,
     fastest = min(times.values())
     best = next(c for c in candidates if times[c] <= fastest * (1.0 + TIE))
     S.solid_lbm_batch_set_tuning(batch, best[0], best[1])
-    return {"T": best[0], "H": best[1], "us": {f"{k[0]},{k[1]}": round(v, 3) for k, v in times.items()}}
+    tile_times = {}
+    n = 24 * max(sweeps // 24, 1)                 # a multiple of every candidate's steps
+    for Tt in tile_candidates:
+        S.solid_lbm_batch_set_tile_steps(batch, Tt)
+        S.solid_lbm_batch_time_sweeps(batch, 0, 2 * Tt)
+        tile_times[Tt] = S.solid_lbm_batch_time_sweeps(batch, 0, n) / n * 1e3
+    fastest = min(tile_times.values())
+    best_t = next(c for c in tile_candidates if tile_times[c] <= fastest * (1.0 + TIE))
+    S.solid_lbm_batch_set_tile_steps(batch, best_t)
+    return {"T": best[0], "H": best[1], "Tt": best_t, "us": {f"{k[0]},{k[1]}": round(v, 3) for k, v in times.items()},
+            "us_tiles": {str(k): round(v, 3) for k, v in tile_times.items()}}

@@ -29,10 +29,17 @@ thread_local std::string g_init_error;
 // launches between two residual checks); pairs are harvested once the host
 // has seen them complete and their events are reused.
 struct LaunchTimer {
+    struct Run {
+        hipEvent_t a, b;
+        int64_t start, launches, sweeps;                 // first step of the run, its launches and sweeps
+        double ms;
+    };
     bool on = false;
     std::vector<hipEvent_t> pool;                        // free events
-    std::deque<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::deque<Run> pending;                             // recorded, not yet read
+    std::vector<Run> runs;                               // read
     hipEvent_t open = nullptr;                           // start of the run being recorded
+    int64_t run_start = 0, run_launches = 0, run_sweeps = 0;
     int64_t launches = 0, sweeps = 0;                    // fused launches and the sweeps they made
     double ms = 0.0;                                     // device time of the completed runs
     hipError_t take(hipEvent_t* e)
@@ -48,14 +55,18 @@ struct LaunchTimer {
     {
         launches = sweeps = 0;
         ms = 0.0;
+        runs.clear();
     }
-    // before a fused launch of `k` sweeps on `stream`
-    hipError_t before(hipStream_t stream, int k)
+    // before a fused launch of `k` sweeps, starting at step `step`, on `stream`
+    hipError_t before(hipStream_t stream, int k, int64_t step)
     {
         if (!on) return hipSuccess;
         ++launches;
         sweeps += k;
+        ++run_launches;
+        run_sweeps += k;
         if (open) return hipSuccess;
+        run_start = step;
         hipError_t e = take(&open);
         return e != hipSuccess ? e : hipEventRecord(open, stream);
     }
@@ -67,36 +78,53 @@ struct LaunchTimer {
         hipError_t e = take(&end);
         if (e == hipSuccess) e = hipEventRecord(end, stream);
         if (e != hipSuccess) return e;
-        pending.emplace_back(open, end);
+        pending.push_back(Run{open, end, run_start, run_launches, run_sweeps, 0.0});
         open = nullptr;
+        run_launches = run_sweeps = 0;
         return hipSuccess;
     }
     // accumulates the runs that have completed (wait: block until all have)
     hipError_t harvest(bool wait)
     {
         while (!pending.empty()) {
-            auto pr = pending.front();
+            Run r = pending.front();
             if (wait) {
-                hipError_t e = hipEventSynchronize(pr.second);
+                hipError_t e = hipEventSynchronize(r.b);
                 if (e != hipSuccess) return e;
-            } else if (hipEventQuery(pr.second) != hipSuccess) {
+            } else if (hipEventQuery(r.b) != hipSuccess) {
                 break;
             }
             float f = 0.f;
-            hipError_t e = hipEventElapsedTime(&f, pr.first, pr.second);
+            hipError_t e = hipEventElapsedTime(&f, r.a, r.b);
             if (e != hipSuccess) return e;
+            r.ms = f;
             ms += f;
-            pool.push_back(pr.first);
-            pool.push_back(pr.second);
+            runs.push_back(r);
+            pool.push_back(r.a);
+            pool.push_back(r.b);
             pending.pop_front();
         }
         return hipSuccess;
     }
+    // keeps the runs that start at or before step t: the loop learns of a
+    // stop one check late, and the launches it issued after the stop return
+    // at once (call after harvest(true))
+    void trim(int64_t t)
+    {
+        launches = sweeps = 0;
+        ms = 0.0;
+        for (const Run& r : runs)
+            if (r.start <= t) {
+                launches += r.launches;
+                sweeps += r.sweeps;
+                ms += r.ms;
+            }
+    }
     void destroy()
     {
-        for (auto& pr : pending) {
-            pool.push_back(pr.first);
-            pool.push_back(pr.second);
+        for (auto& r : pending) {
+            pool.push_back(r.a);
+            pool.push_back(r.b);
         }
         pending.clear();
         if (open) pool.push_back(open);
@@ -680,7 +708,7 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
             if (!check && T > 1 && plain >= T) {
                 a.src = bufs[cur];
                 a.dst = bufs[cur ^ 1];
-                HIPCHK(c, c->lt.before(c->stream, T));
+                HIPCHK(c, c->lt.before(c->stream, T, s));
                 launch_fused(c, adjoint, a, T);
                 cur ^= 1;
                 s += T;
@@ -690,7 +718,7 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
                 const int k = (int)std::min<int64_t>(plain, TL);
                 a.src = bufs[cur];
                 a.dst = bufs[cur ^ 1];
-                HIPCHK(c, c->lt.before(c->stream, k));
+                HIPCHK(c, c->lt.before(c->stream, k, s));
                 launch_tile(c, adjoint, a, k, TL);
                 cur ^= 1;
                 s += k;
@@ -743,6 +771,7 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
     }
     Status st;
     HIPCHK(c, hipMemcpy(&st, c->status, sizeof(Status), hipMemcpyDeviceToHost));
+    if (c->lt.on) c->lt.trim(use_tol && st.stop ? st.t_conv : last);
     if (use_tol && st.stop) {
         *t_out = st.t_conv;
         *conv_out = true;
@@ -1712,15 +1741,18 @@ struct slbm_batch {
     Status* h_status = nullptr;    // pinned, 2 slots of B
     BatchInst* d_inst = nullptr;
     std::vector<BatchInst> h_inst;
-    int2* d_all = nullptr;         // every instance: (instance, block) of a single-step sweep
+    int2* d_all = nullptr;         // every instance: (instance, block) of a single-step sweep,
+                                   // wave-strip instances first (their single steps alone: n_all_strip)
     int2* d_tb = nullptr;          // wave-strip instances: (instance, strip) of a fused launch
     int2* d_tile = nullptr;        // tiled instances: (instance, tile) of a fused launch
     int2* static_tables = nullptr; // non-null during batch_objective_and_grad_noalloc: tables go there
     const int2* cur_tb = nullptr;  // tables of the current launches (own or static)
     const int2* cur_tile = nullptr;
-    int64_t n_all = 0, n_tb = 0, tb_cap = 0, n_tile = 0, tile_cap = 0;
-    int tb_T = -1, tb_H = 0;       // tuning (-1 / 0: automatic)
-    int T = 1, H = 0;              // effective fused shape of the current tables
+    int64_t n_all = 0, n_all_strip = 0, n_tb = 0, tb_cap = 0, n_tile = 0, tile_cap = 0;
+    int tb_T = -1, tb_H = 0;       // tuning of the wave strips (-1 / 0: automatic)
+    int tl_T = -1;                 // steps per launch of the tiled instances (-1: automatic)
+    int T = 1, H = 0;              // effective fused shape of the current tables (wave strips)
+    int Tt = 1;                    // effective steps per tile launch (halo of the tiles)
     std::vector<char> tiled;       // per instance: fused by the LDS-tiled kernel
     bool any_masked = false, tile_attr = false;
     double tol = 0.0;
@@ -1773,8 +1805,15 @@ int balloc(slbm_batch* b, void** p, size_t bytes)
 }
 
 // Fused shape for the batch: periodic instances share one (T, H).
-void batch_shape(slbm_batch* b, int* T, int* H)
+// Tiled instances fuse their own number of steps per launch (default 6: the
+// 20 x 20 tiles of 32 x 32 regions, measured fastest at 384 x 231 and within
+// a few per cent at 512 x 308, where 8 steps with 16 x 16 tiles take 1.1 -
+// 1.5 times longer per step).
+constexpr int kBatchTileSteps = 6;
+
+void batch_shape(slbm_batch* b, int* T, int* H, int* Tt)
 {
+    *Tt = b->tl_T < 0 ? kBatchTileSteps : std::max(1, std::min(8, b->tl_T));
     int t = b->tb_T < 0 ? 8 : b->tb_T;
     if (t != 2 && t != 4 && t != 6 && t != 8) t = 1;
     int h = b->tb_H;
@@ -1821,16 +1860,15 @@ int static_tables_of(slbm_batch* b, int2** out)
 // Entries of the fused strip and tile tables for the current tuning.
 int64_t batch_table_entries(slbm_batch* b)
 {
-    int T, H;
-    batch_shape(b, &T, &H);
-    if (T <= 1) return 0;
-    const int tw = std::max(2, 32 - 2 * T);
+    int T, H, Tt;
+    batch_shape(b, &T, &H, &Tt);
+    const int tw = std::max(2, 32 - 2 * Tt);
     int64_t n = 0;
     for (size_t i = 0; i < b->ctx.size(); ++i) {
         const slbm_ctx* c = b->ctx[i];
         if (b->tiled[i]) {
-            n += (int64_t)((c->nx + tw - 1) / tw) * ((c->ny + tw - 1) / tw);
-        } else {
+            if (Tt > 1) n += (int64_t)((c->nx + tw - 1) / tw) * ((c->ny + tw - 1) / tw);
+        } else if (T > 1) {
             const int V = 64 - 2 * T, h = std::min(H, c->ny);
             n += (int64_t)((c->nx + V - 1) / V) * ((c->ny + h - 1) / h);
         }
@@ -1838,15 +1876,16 @@ int64_t batch_table_entries(slbm_batch* b)
     return n;
 }
 
-// (Re)builds the per-instance table for the current controls and the fused
-// strip table for shape (T, H); uploads both.
+// (Re)builds the per-instance table for the current controls, the fused
+// strip table for shape (T, H) and the tile table for Tt steps per launch;
+// uploads them.
 int batch_tables(slbm_batch* b, bool adjoint)
 {
-    int T, H;
-    batch_shape(b, &T, &H);
+    int T, H, Tt;
+    batch_shape(b, &T, &H, &Tt);
     const int B = (int)b->ctx.size();
-    // tiled instances: halo = T, 32 x 32 regions
-    const int tw = std::max(2, 32 - 2 * T);
+    // tiled instances: halo = Tt, 32 x 32 regions
+    const int tw = std::max(2, 32 - 2 * Tt);
     std::vector<int2> tb, tl;
     for (int i = 0; i < B; ++i) {
         slbm_ctx* c = b->ctx[i];
@@ -1902,8 +1941,8 @@ int batch_tables(slbm_batch* b, bool adjoint)
                 l.scale = s.scale;
                 l.tw = tw;
                 l.th = tw;
-                l.halo = T;
-                l.steps = T;
+                l.halo = Tt;
+                l.steps = Tt;
                 l.maxb = kTileMaxB;
                 l.tiles_x = (c->nx + tw - 1) / tw;
                 (k ? I.ladj : I.lprim)[par] = l;
@@ -1921,7 +1960,7 @@ int batch_tables(slbm_batch* b, bool adjoint)
             I.sx = sx;
             for (int k = 0; k < sx * sy; ++k) tb.push_back(make_int2(i, k));
         }
-        if (b->tiled[i] && T > 1) {
+        if (b->tiled[i] && Tt > 1) {
             const int ntiles = ((c->nx + tw - 1) / tw) * ((c->ny + tw - 1) / tw);
             for (int k = 0; k < ntiles; ++k) tl.push_back(make_int2(i, k));
         }
@@ -1974,6 +2013,7 @@ int batch_tables(slbm_batch* b, bool adjoint)
     b->n_tile = (int64_t)tl.size();
     b->T = T;
     b->H = H;
+    b->Tt = Tt;
     return SLBM_OK;
 }
 
@@ -2008,16 +2048,50 @@ void launch_batch_fused(slbm_batch* b, bool adjoint, int pp)
 #undef BTB_CASE
 }
 
-void launch_batch_tile(slbm_batch* b, bool adjoint, int pl)
+// steps (1 .. Tt) sweeps of every tiled instance
+void launch_batch_tile(slbm_batch* b, bool adjoint, int pl, int steps)
 {
     if (b->n_tile <= 0) return;
-    const int R = (std::max(2, 32 - 2 * b->T) + 2 * b->T) * (std::max(2, 32 - 2 * b->T) + 2 * b->T);
-    const size_t lds = tile_lds_bytes(R, b->any_masked);
+    const int w = std::max(2, 32 - 2 * b->Tt) + 2 * b->Tt;
+    const size_t lds = tile_lds_bytes(w * w, b->any_masked);
     dim3 grid((unsigned)b->n_tile), block(kTileBlock);
     if (adjoint)
-        hipLaunchKernelGGL(k_sweep_tile_batch<true>, grid, block, lds, b->stream, b->d_inst, b->cur_tile, pl, b->T);
+        hipLaunchKernelGGL(k_sweep_tile_batch<true>, grid, block, lds, b->stream, b->d_inst, b->cur_tile, pl, steps);
     else
-        hipLaunchKernelGGL(k_sweep_tile_batch<false>, grid, block, lds, b->stream, b->d_inst, b->cur_tile, pl, b->T);
+        hipLaunchKernelGGL(k_sweep_tile_batch<false>, grid, block, lds, b->stream, b->d_inst, b->cur_tile, pl, steps);
+}
+
+// run plain steps (no checks) of every instance: the wave-strip class in
+// fused launches of T steps and single steps for the rest, the tiled class
+// in launches of up to Tt steps; each class flips its buffer parity per launch.
+void batch_plain_steps(slbm_batch* b, bool adjoint, int64_t run, int& pp, int& pl)
+{
+    const bool strips = b->n_all_strip > 0;
+    if (strips) {
+        int64_t left = run;
+        if (b->T > 1 && b->n_tb > 0)
+            for (; left >= b->T; left -= b->T) {
+                launch_batch_fused(b, adjoint, pp);
+                pp ^= 1;
+            }
+        for (; left > 0; --left) {
+            launch_batch_step(b, adjoint, b->d_all, b->n_all_strip, pp, pl, 0, 0);
+            pp ^= 1;
+        }
+    }
+    if (b->n_all > b->n_all_strip) {
+        if (b->Tt > 1 && b->n_tile > 0) {
+            for (int64_t left = run; left > 0; left -= b->Tt) {
+                launch_batch_tile(b, adjoint, pl, (int)std::min<int64_t>(left, b->Tt));
+                pl ^= 1;
+            }
+        } else {
+            for (int64_t j = 0; j < run; ++j) {
+                launch_batch_step(b, adjoint, b->d_all + b->n_all_strip, b->n_all - b->n_all_strip, pp, pl, 0, 0);
+                pl ^= 1;
+            }
+        }
+    }
 }
 
 // Advances every instance from buffer 0 in lock-step (step index s), each
@@ -2101,25 +2175,9 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
         if (use_tol)
             for (int i = 0; i < B; ++i)
                 if (active[i]) next = std::min(next, (s / K[i] + 1) * K[i]);
-        int64_t run = next - s;
-        const int T = b->T;
-        if (T > 1 && run >= T) {
-            int64_t nT = run / T;
-            for (int64_t j = 0; j < nT; ++j) {
-                if (b->n_tb > 0) launch_batch_fused(b, adjoint, pp);
-                pp ^= 1;
-                launch_batch_tile(b, adjoint, pl);
-                pl ^= 1;
-            }
-            s += nT * T;
-            run -= nT * T;
-        }
-        for (int64_t j = 0; j < run; ++j) {
-            launch_batch_step(b, adjoint, b->d_all, b->n_all, pp, pl, 0, 0);
-            pp ^= 1;
-            pl ^= 1;
-            ++s;
-        }
+        const int64_t run = next - s;
+        batch_plain_steps(b, adjoint, run, pp, pl);
+        s += run;
         BHIPCHK(b, hipGetLastError());
     }
     BHIPCHK(b, hipEventRecord(b->t1, b->stream));
@@ -2162,7 +2220,7 @@ int batch_loop_persist(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out,
     BHIPCHK(b, hipGetLastError());
     int rc = batch_tables(b, adjoint);
     if (rc) return rc;
-    const int T = b->T > 1 ? b->T : 1;
+    const int T = b->Tt > 1 ? b->Tt : 1;     // every instance runs as tiles of Tt steps
     const int tw = std::max(2, 32 - 2 * T);
     std::vector<PersistInst> pi(B);
     for (int i = 0; i < B; ++i) {
@@ -2435,8 +2493,15 @@ int solid_lbm_batch_init(const slbm_problem* problems, int32_t count, slbm_batch
         // 131 with tiles)
         b->tiled[i] = (c->masked || c->kind == SLBM_CTRL_E_NODAL) ? 1 : 0;
         if (c->masked) b->any_masked = true;
-        for (int64_t k = 0; k < c->nblk; ++k) all.push_back(make_int2(i, (int)k));
     }
+    // single-step table: wave-strip instances first, so their single steps
+    // alone are the table's first n_all_strip entries
+    for (int cls = 0; cls < 2; ++cls)
+        for (int i = 0; i < count; ++i)
+            if (b->tiled[i] == cls)
+                for (int64_t k = 0; k < b->ctx[i]->nblk; ++k) all.push_back(make_int2(i, (int)k));
+    for (const int2& e : all)
+        if (!b->tiled[e.x]) ++b->n_all_strip;
     if (!rc && !(rc = balloc(b, &q, all.size() * sizeof(int2)))) b->d_all = (int2*)q;
     if (!rc && hipMemcpy(b->d_all, all.data(), all.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
         rc = SLBM_EHIP;
@@ -2532,6 +2597,15 @@ int solid_lbm_batch_set_tuning(slbm_batch* b, int32_t steps_per_launch, int32_t 
     return SLBM_OK;
 }
 
+int solid_lbm_batch_set_tile_steps(slbm_batch* b, int32_t steps_per_launch)
+{
+    if (!b) return SLBM_EINVAL;
+    if (steps_per_launch != -1 && (steps_per_launch < 1 || steps_per_launch > 8))
+        return bfail(b, SLBM_EINVAL, "steps_per_launch must be -1 (automatic) or 1 .. 8");
+    b->tl_T = steps_per_launch;
+    return SLBM_OK;
+}
+
 int solid_lbm_batch_time_sweeps(slbm_batch* b, int32_t adjoint, int64_t n, double* ms)
 {
     if (!b || !ms) return SLBM_EINVAL;
@@ -2542,20 +2616,7 @@ int solid_lbm_batch_time_sweeps(slbm_batch* b, int32_t adjoint, int64_t n, doubl
     if (rc) return rc;
     int pp = 0, pl = 0;
     BHIPCHK(b, hipEventRecord(b->t0, b->stream));
-    for (int64_t s = 0; s < n;) {
-        if (b->T > 1 && n - s >= b->T) {
-            if (b->n_tb > 0) launch_batch_fused(b, adjoint != 0, pp);
-            pp ^= 1;
-            launch_batch_tile(b, adjoint != 0, pl);
-            pl ^= 1;
-            s += b->T;
-        } else {
-            launch_batch_step(b, adjoint != 0, b->d_all, b->n_all, pp, pl, 0, 0);
-            pp ^= 1;
-            pl ^= 1;
-            ++s;
-        }
-    }
+    batch_plain_steps(b, adjoint != 0, n, pp, pl);
     BHIPCHK(b, hipGetLastError());
     BHIPCHK(b, hipEventRecord(b->t1, b->stream));
     BHIPCHK(b, hipEventSynchronize(b->t1));

@@ -56,19 +56,20 @@ struct Relax {
 // Plane-stress moduli mu = E/(2(1+nu)), K = E/(2(1-nu)) (eq. mu, eq. K);
 // tau_11 = mu/theta, tau_s = 2K/(1+theta), tau_d = 2mu/(1-theta); omega =
 // 1/(tau + 1/2) (eq. relaxation); gamma of eq. gamma at boundary nodes.
+// With theta = 1/3 these reduce to tau_11 = tau_d = 3 mu = E * 3/(2(1+nu)),
+// tau_s = 3K/2 = E * 3/(4(1-nu)) and gamma = (theta tau_f/(1+theta)) /
+// (tau_s - tau_f) = (1/8)/(tau_s - 1/2): two divisions per node (one more at
+// boundary nodes) instead of nine, the same values up to rounding.
 template <class T>
 __host__ __device__ inline Relax<T> relax_from_E(T E, double nu, bool boundary)
 {
-    T mu = E / T(2.0 * (1.0 + nu));
-    T K = E / T(2.0 * (1.0 - nu));
-    T t11 = mu / T(kTheta);
-    T ts = T(2.0) * K / T(1.0 + kTheta);
-    T td = T(2.0) * mu / T(1.0 - kTheta);
+    const T t11 = E * T(1.5 / (1.0 + nu));      // tau_11 = tau_d
+    const T ts = E * T(0.75 / (1.0 - nu));
     Relax<T> r;
     r.k11 = T(1.0) - T(1.0) / (t11 + T(0.5));
+    r.kd = r.k11;
     r.ks = T(1.0) - T(1.0) / (ts + T(0.5));
-    r.kd = T(1.0) - T(1.0) / (td + T(0.5));
-    r.gam = boundary ? T(kTheta * kTauF) / (T(1.0 + kTheta) * (ts - T(kTauF))) : T(0.0);
+    r.gam = boundary ? T(kTheta * kTauF / (1.0 + kTheta)) / (ts - T(kTauF)) : T(0.0);
     return r;
 }
 

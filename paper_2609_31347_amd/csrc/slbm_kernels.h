@@ -1179,25 +1179,32 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
         if (i < R) {
             const int64_t n = (int64_t)wrapi(y0 + ry[j], ny) * nx + wrapi(x0 + rx[j], nx);
             gn[j] = n;
-            cd[j] = MASKED ? ldg(a.code + n) : 0;
+            // every load of the node is issued before any of them is used (one
+            // round trip; the planes cover the whole box, so outside nodes
+            // read defined values, which they do not use)
+            const int code = MASKED ? ldg(a.code + n) : 0;
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = ldg(a.src + q * N + n);
+            const double g0 = ldg(a.g + n), g1 = ldg(a.g + N + n);
+            const double Ev = EFIELD ? ldg(a.E + n) : a.E0;
+            cd[j] = code;
             // plates fill both copies: slots that no sweep writes (outside
             // nodes, which adjoint boundary nodes pull from) must read their
             // stored values
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const double v = ldg(a.src + q * N + n);
-                lds[q * R + i] = v;
-                if (MASKED) lds[(8 + q) * R + i] = v;
+                lds[q * R + i] = v[q];
+                if (MASKED) lds[(8 + q) * R + i] = v[q];
             }
-            if (cd[j] >= 0) {
-                if (ADJ) {
-                    c0[j] = a.scale * ldg(a.g + n);
-                    c1[j] = a.scale * ldg(a.g + N + n);
-                } else {
-                    c0[j] = ldg(a.g + n);
-                    c1[j] = ldg(a.g + N + n);
-                }
-                if (EFIELD || cd[j] > 0) rl[j] = relax_from_E<double>(EFIELD ? ldg(a.E + n) : a.E0, a.nu, cd[j] > 0);
+            const bool live = code >= 0;
+            c0[j] = live ? (ADJ ? a.scale * g0 : g0) : 0.0;
+            c1[j] = live ? (ADJ ? a.scale * g1 : g1) : 0.0;
+            if (EFIELD) {
+                const Relax<double> r = relax_from_E<double>(Ev, a.nu, code > 0);
+                if (live) rl[j] = r;
+            } else if (code > 0) {
+                rl[j] = relax_from_E<double>(a.E0, a.nu, true);
             }
         }
         bng[j] = a.bnodes;

@@ -32,7 +32,7 @@ EXPORTS = ("solid_lbm_init", "primal_solve", "adjoint_solve", "objective_and_gra
            "solid_lbm_destroy",
            "solid_lbm_batch_init", "batch_objective_and_grad", "batch_objective_and_grad_noalloc",
            "batch_objective_and_grad_from",
-           "batch_gradient", "solid_lbm_batch_set_tuning", "solid_lbm_batch_set_persistent",
+           "batch_gradient", "solid_lbm_batch_set_tuning", "solid_lbm_batch_set_tile_steps", "solid_lbm_batch_set_persistent",
            "solid_lbm_batch_persistent_stats", "solid_lbm_batch_set_progress",
            "solid_lbm_batch_time_sweeps", "solid_lbm_batch_instance", "solid_lbm_batch_last_error",
            "solid_lbm_batch_destroy")
@@ -137,6 +137,7 @@ def _load():
     lib.solid_lbm_batch_set_persistent.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.solid_lbm_batch_persistent_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.solid_lbm_batch_set_tuning.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.solid_lbm_batch_set_tile_steps.argtypes = [P, ctypes.c_int32]
     lib.solid_lbm_batch_set_progress.argtypes = [P, PROGRESS_FN, P, ctypes.c_double]
     lib.solid_lbm_batch_time_sweeps.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
     lib.solid_lbm_batch_instance.argtypes = [P, ctypes.c_int32]
@@ -571,6 +572,11 @@ def batch_gradient(batch, grads=None):
 def solid_lbm_batch_set_tuning(batch, steps_per_launch=-1, rows_per_wave=0):
     """Launch shape of the batch's shared launches (-1 / 0 automatic); results do not change."""
     return _bcheck(batch, LIB.solid_lbm_batch_set_tuning(batch.handle, int(steps_per_launch), int(rows_per_wave)))
+
+
+def solid_lbm_batch_set_tile_steps(batch, steps_per_launch=-1):
+    """Steps per launch of the batch's tiled instances (-1 automatic, 1 .. 8); results do not change."""
+    return _bcheck(batch, LIB.solid_lbm_batch_set_tile_steps(batch.handle, int(steps_per_launch)))
 
 
 def solid_lbm_batch_set_persistent(batch, on=True, rounds_per_launch=0):

@@ -90,7 +90,8 @@ def test_batch_equals_individual_solves_and_oracle(orc):
 
 
 def test_batch_fixed_steps_and_tuning():
-    """tol <= 0: every instance runs exactly max_steps; shapes from the tuner do not change results."""
+    """tol <= 0: every instance runs exactly max_steps; launch shapes (wave-strip
+    shape, steps per tile launch) do not change results."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -99,9 +100,10 @@ def test_batch_fixed_steps_and_tuning():
     for p in probs:
         p["max_steps"] = 333
     out = []
-    for T, H in ((1, 0), (8, 24), (4, 5)):
+    for T, H, Tt in ((1, 0, 1), (8, 24, -1), (4, 5, 3), (2, 8, 8), (6, 12, 5), (1, 0, 4)):
         batch = S.solid_lbm_batch_init(probs)
         S.solid_lbm_batch_set_tuning(batch, T, H)
+        S.solid_lbm_batch_set_tile_steps(batch, Tt)
         rc, J, grads, pi, ai = S.batch_objective_and_grad(batch, ctrls)
         assert all(x.steps == 333 for x in pi)
         out.append((J, grads))

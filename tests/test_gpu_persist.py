@@ -76,16 +76,17 @@ def test_persistent_batch_equals_host_driven_individual_and_oracle(S, orc):
 
 
 def test_persistent_batch_fixed_steps_and_replay_budgets(S):
-    """tol <= 0: exactly max_steps steps per instance; the rounds per replay do
-    not change any result."""
+    """tol <= 0: exactly max_steps steps per instance; the rounds per replay and
+    the steps per tile do not change any result."""
     probs, ctrls = mixed_problems(S, tol=0.0, large=False)
     for p in probs:
         p["max_steps"] = 333
     host = S.solid_lbm_batch_init(probs)
     rc, J, grads, pi, ai = S.batch_objective_and_grad(host, ctrls)
-    for budget in (7, 0):
+    for budget, Tt in ((7, -1), (0, 3), (0, 8)):
         b = S.solid_lbm_batch_init(probs)
         S.solid_lbm_batch_set_persistent(b, True, budget)
+        S.solid_lbm_batch_set_tile_steps(b, Tt)
         rcp, Jp, gp, pip, aip = S.batch_objective_and_grad(b, ctrls)
         assert all(x.steps == 333 for x in pip) and all(x.steps == 333 for x in aip)
         assert rel(Jp, J) <= 1e-13

@@ -275,7 +275,9 @@ int solid_lbm_time_sweeps(slbm_ctx *ctx, int32_t adjoint, int64_t n, double *ms)
  * kernel), 2 .. 8 for plates, E-field controls and problems given a tile by
  * solid_lbm_set_tiles (LDS-tiled kernel).  Automatic: the LDS-tiled kernel
  * for plates, E fields and periodic grids up to 131072 nodes (8 steps up to
- * 131072 nodes, 6 above), the wave-strip kernel with 8 steps for larger
+ * 131072 nodes; above, the most of 6, 5, 4, 3 steps whose (32 - 2 steps)^2
+ * tiles number no more than the device's compute units, else 6), the
+ * wave-strip kernel with 8 steps for larger
  * periodic grids, with as many rows per wave as keep the wave count at or
  * below the device's SIMD count.  rows_per_wave: rows each wave of a wave-strip launch
  * covers (0 = automatic).  Every setting gives the same result bit for bit:

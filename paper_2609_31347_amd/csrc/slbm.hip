@@ -382,12 +382,23 @@ void launch_fused(slbm_ctx* c, bool adjoint, const SweepArgs& s, int T)
 // single-step sweeps only).  Any count 1..halo works, so runs shorter than
 // the halo between residual checks are fused too.
 // Automatic: 8 steps per launch (32 x 32 regions, 16 x 16 tiles) up to ~128k
-// nodes, 6 (20 x 20 tiles) beyond -- measured on MI355X for plates of 64 to
-// 512 nodes across, primal and adjoint.
+// nodes; beyond, the most steps of 6, 5, 4, 3 whose (32 - 2h)^2 tiles all
+// fit the compute units at once (one workgroup each), else 6 with 20 x 20
+// tiles -- a workgroup's fixed cost (loads, relaxation rates, stores) is
+// several steps' worth, so one round of workgroups beats more steps in two
+// (measured on MI355X: the 512 x 308 plate 5.0 us per primal step with 6
+// steps in 416 tiles, 4.3 with 3 steps in 240; 384 x 231 keeps 6 steps in
+// 240 tiles, 3.0 us).
 int tile_halo(const slbm_ctx* c)
 {
-    if (c->tb_T < 0) return c->N <= 131072 ? 8 : 6;
-    return std::max(1, std::min(c->tb_T, 8));
+    if (c->tb_T >= 0) return std::max(1, std::min(c->tb_T, 8));
+    if (c->N <= 131072) return 8;
+    const int64_t cus = c->simds / 4;
+    for (int h : {6, 5, 4, 3}) {
+        const int t = 32 - 2 * h;
+        if ((int64_t)((c->nx + t - 1) / t) * ((c->ny + t - 1) / t) <= cus) return h;
+    }
+    return 6;
 }
 
 int tile_steps(const slbm_ctx* c) { return use_tiles(c) ? tile_halo(c) : 1; }

@@ -173,6 +173,13 @@ struct slbm_ctx {
     void* progress_user = nullptr;
     double progress_every = 0.0;          // seconds between reports
     bool tile_attr = false;      // LDS limits of the plate tile kernels raised
+    // launch plan of the current tile shape (k_tile_plan), for launches whose
+    // tiles all fit the compute units: capacity of one tile per compute unit
+    int4* plan = nullptr;
+    int32_t* plan_rec = nullptr;
+    int32_t* plan_nst = nullptr;
+    int64_t plan_cap = 0;        // tiles
+    int plan_key[4] = {0, 0, 0, 0};   // tw, th, halo, order of the plan held (tw = 0: none)
     int64_t nblk = 0;  // blocks of one sweep
     int64_t pcap = 0;  // capacity of the partial-sum buffer in blocks
     // state
@@ -449,9 +456,71 @@ int tile_lds_limits(slbm_ctx* c)
     return SLBM_OK;
 }
 
+// Launch plans (k_tile_plan) for tile shapes whose tiles all fit the
+// compute units at once, where each workgroup's fixed cost sets the launch
+// time: the sweeps then read their node assignment, codes and staged-record
+// list instead of forming them (one round trip fewer, no ordering pass).
+// Larger launches keep forming them: there a plan's 16 B per region node
+// would add to bandwidth-bound traffic.  Built once per shape (a shape
+// change rebuilds it); call before the launches of a loop.
+bool tile_plan_wanted(const slbm_ctx* c, int tw, int th)
+{
+    const int64_t tiles = (int64_t)((c->nx + tw - 1) / tw) * ((c->ny + th - 1) / th);
+    return tiles <= c->simds / 4 && c->N < (int64_t)INT32_MAX;
+}
+
+int ensure_tile_plan(slbm_ctx* c, int halo)
+{
+    int tw, th;
+    tile_shape(c, halo, &tw, &th);
+    if (!tile_plan_wanted(c, tw, th)) return SLBM_OK;
+    const int tiles_x = (c->nx + tw - 1) / tw, tiles = tiles_x * ((c->ny + th - 1) / th);
+    const int order = c->masked ? 1 : 0;
+    if (c->plan_key[0] == tw && c->plan_key[1] == th && c->plan_key[2] == halo && c->plan_key[3] == order)
+        return SLBM_OK;
+    if (!c->plan) {
+        const int64_t cap = std::max<int64_t>(1, c->simds / 4);
+        void* p = nullptr;
+        int rc = dalloc(c, &p, (size_t)cap * kTileMaxNodes * sizeof(int4));
+        if (rc) return rc;
+        c->plan = (int4*)p;
+        if ((rc = dalloc(c, &p, (size_t)cap * kTileMaxB * sizeof(int32_t)))) return rc;
+        c->plan_rec = (int32_t*)p;
+        if ((rc = dalloc(c, &p, (size_t)cap * sizeof(int32_t)))) return rc;
+        c->plan_nst = (int32_t*)p;
+        c->plan_cap = cap;
+    }
+    if (tiles > c->plan_cap) return fail(c, SLBM_EHIP, "internal: tile plan capacity");
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.code = c->code;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.N = c->N;
+    a.tw = tw;
+    a.th = th;
+    a.halo = halo;
+    a.tiles_x = tiles_x;
+    a.order_by_kind = order;
+    a.maxb = kTileMaxB;
+    if (c->masked)
+        hipLaunchKernelGGL(k_tile_plan<true>, dim3((unsigned)tiles), dim3(kTileBlock), 0, c->stream, a, c->plan,
+                           c->plan_rec, c->plan_nst);
+    else
+        hipLaunchKernelGGL(k_tile_plan<false>, dim3((unsigned)tiles), dim3(kTileBlock), 0, c->stream, a, c->plan,
+                           c->plan_rec, c->plan_nst);
+    HIPCHK(c, hipGetLastError());
+    c->plan_key[0] = tw;
+    c->plan_key[1] = th;
+    c->plan_key[2] = halo;
+    c->plan_key[3] = order;
+    return SLBM_OK;
+}
+
 void launch_tile(slbm_ctx* c, bool adjoint, const SweepArgs& s, int steps, int halo)
 {
     TileArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.src = s.src;
     a.dst = s.dst;
     a.g = s.g;
@@ -475,6 +544,12 @@ void launch_tile(slbm_ctx* c, bool adjoint, const SweepArgs& s, int steps, int h
     a.tiles_x = (c->nx + a.tw - 1) / a.tw;
     const int tiles_y = (c->ny + a.th - 1) / a.th;
     a.order_by_kind = c->masked && (int64_t)a.tiles_x * tiles_y <= c->simds / 4 ? 1 : 0;
+    if (c->plan && c->plan_key[0] == a.tw && c->plan_key[1] == a.th && c->plan_key[2] == halo &&
+        c->plan_key[3] == a.order_by_kind && tile_plan_wanted(c, a.tw, a.th)) {
+        a.plan = c->plan;
+        a.plan_rec = c->plan_rec;
+        a.plan_nst = c->plan_nst;
+    }
     const size_t lds = tile_lds_bytes((a.tw + 2 * halo) * (a.th + 2 * halo), c->masked);
     dim3 grid((unsigned)(a.tiles_x * tiles_y)), block(kTileBlock);
     int sel = (c->masked ? 4 : 0) | (c->efield_on ? 2 : 0) | (adjoint ? 1 : 0);
@@ -704,6 +779,10 @@ int run_loop(slbm_ctx* c, bool adjoint, int start, int64_t last, bool use_tol, i
     const int TL = tile_steps(c);
     if (TL > 1 && c->masked) {
         int rc = tile_lds_limits(c);
+        if (rc) return rc;
+    }
+    if (TL > 1) {
+        int rc = ensure_tile_plan(c, TL);
         if (rc) return rc;
     }
     CheckLog checks;                              // (step, input buffer) of the latest check sweeps
@@ -1525,6 +1604,10 @@ int solid_lbm_time_sweeps(slbm_ctx* c, int32_t adjoint, int64_t n, double* ms)
     const int TL = tile_steps(c);
     if (TL > 1 && c->masked) {
         int rc = tile_lds_limits(c);
+        if (rc) return rc;
+    }
+    if (TL > 1) {
+        int rc = ensure_tile_plan(c, TL);
         if (rc) return rc;
     }
     HIPCHK(c, hipEventRecord(c->t0, c->stream));

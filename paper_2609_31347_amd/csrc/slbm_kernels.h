@@ -1057,6 +1057,13 @@ struct TileArgs {
     int32_t tw, th, halo, steps, tiles_x;
     int32_t order_by_kind;           // plates: threads take bulk, then boundary, then outside nodes
     int32_t maxb;                    // boundary records staged in LDS (<= kTileMaxB; the rest from HBM)
+    // launch plan of the tile shape (null: formed in the kernel), written once
+    // by k_tile_plan: per tile and thread (node, code, region node | (staged
+    // slot + 1) << 16, rx | ry << 16); per tile the records of its staged
+    // slots and their count
+    const int4* plan;
+    const int32_t* plan_rec;
+    const int32_t* plan_nst;
 };
 
 constexpr int kTileBlock = 1024;
@@ -1071,10 +1078,66 @@ __host__ __device__ constexpr size_t tile_lds_bytes(int region, bool masked, int
     return (size_t)(masked ? 16 : 8) * region * sizeof(double) + (masked ? (size_t)maxb * sizeof(BNode) : 0);
 }
 
+// The stable order by kind of a plate tile's region nodes (bulk, boundary,
+// outside): ni[j] becomes the region node the thread runs in pass j.  Reads
+// the node codes (one round trip); ends with a barrier.
+__device__ __forceinline__ void tile_order(const TileArgs& a, int x0, int y0, int RX, int R, int ni[kTileNPT])
+{
+    const int nx = a.nx, ny = a.ny;
+    constexpr int W = kTileBlock / 64;
+    __shared__ int wcount[kTileNPT][2][W];      // bulk / boundary nodes per wave
+    __shared__ short order[kTileMaxNodes];      // region node of each slot
+    const int w = threadIdx.x / 64;
+    const uint64_t below = __lanemask_lt();
+    uint64_t b0[kTileNPT], b1[kTileNPT];
+    int kind[kTileNPT];                         // 0 bulk, 1 boundary, 2 outside or none
+#pragma unroll
+    for (int j = 0; j < kTileNPT; ++j) {
+        const int i = ni[j];
+        int c = -1;
+        if (i < R) c = ldg(a.code + (int64_t)wrapi(y0 + i / RX, ny) * nx + wrapi(x0 + i % RX, nx));
+        kind[j] = c < 0 ? 2 : (c > 0 ? 1 : 0);
+        b0[j] = __ballot(kind[j] == 0);
+        b1[j] = __ballot(kind[j] == 1);
+        if ((threadIdx.x & 63) == 0) {
+            wcount[j][0][w] = __popcll(b0[j]);
+            wcount[j][1][w] = __popcll(b1[j]);
+        }
+    }
+    __syncthreads();
+    // totals and the counts of earlier waves (pass j's waves come after pass j - 1's)
+    int tot0 = 0, tot1 = 0;
+    int pre0[kTileNPT], pre1[kTileNPT];
+#pragma unroll
+    for (int j = 0; j < kTileNPT; ++j) {
+        pre0[j] = tot0;
+        pre1[j] = tot1;
+        for (int v = 0; v < W; ++v) {
+            const int n0 = wcount[j][0][v], n1 = wcount[j][1][v];
+            if (v < w) {
+                pre0[j] += n0;
+                pre1[j] += n1;
+            }
+            tot0 += n0;
+            tot1 += n1;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kTileNPT; ++j) {
+        const int i = ni[j];
+        const int r0 = pre0[j] + __popcll(b0[j] & below), r1 = pre1[j] + __popcll(b1[j] & below);
+        const int slot = kind[j] == 0 ? r0 : kind[j] == 1 ? tot0 + r1 : tot0 + tot1 + (i - r0 - r1);
+        order[slot] = (short)i;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kTileNPT; ++j) ni[j] = order[threadIdx.x + j * kTileBlock];
+}
+
 // One tile (index `tile` of the problem's tiles_x x tiles_y) of a tiled launch;
 // lds: the region's 8 planes (two copies for plates), then the staged
-// boundary records.
-template <bool MASKED, bool EFIELD, bool ADJ>
+// boundary records.  PLAN: the launch has a plan (a.plan non-null).
+template <bool MASKED, bool EFIELD, bool ADJ, bool PLAN = false>
 __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* lds)
 {
     const int h = a.halo, RX = a.tw + 2 * h, RY = a.th + 2 * h, R = RX * RY;
@@ -1107,68 +1170,52 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
     // loads; measured, it pays where a launch has no more tiles than the GPU
     // has CUs (each workgroup's latency sets the time), not beyond.
     int ni[kTileNPT];
+    constexpr bool planned = PLAN;
+    int4 pe[kTileNPT];                           // this thread's plan entries
 #pragma unroll
     for (int j = 0; j < kTileNPT; ++j) ni[j] = threadIdx.x + j * kTileBlock;
-    if (MASKED) {
+    if (planned) {
+#pragma unroll
+        for (int j = 0; j < kTileNPT; ++j) {
+            pe[j] = a.plan[(int64_t)tile * kTileMaxNodes + threadIdx.x + j * kTileBlock];
+            ni[j] = pe[j].z & 0xffff;
+        }
+    } else if (MASKED) {
         if (threadIdx.x == 0) nstaged = 0;
-        if (a.order_by_kind) {
-            constexpr int W = kTileBlock / 64;
-            __shared__ int wcount[kTileNPT][2][W];      // bulk / boundary nodes per wave
-            __shared__ short order[kTileMaxNodes];      // region node of each slot
-            const int w = threadIdx.x / 64;
-            const uint64_t below = __lanemask_lt();
-            uint64_t b0[kTileNPT], b1[kTileNPT];
-            int kind[kTileNPT];                         // 0 bulk, 1 boundary, 2 outside or none
+        if (a.order_by_kind) tile_order(a, x0, y0, RX, R, ni);
+        else __syncthreads();
+    }
+    // planned launches copy the tile's staged records with all threads (each
+    // a few words), issued with the node loads: one round trip after the plan
+    constexpr int kRecWords = (int)(sizeof(BNode) / 8);
+    constexpr int kStageWords = (kTileMaxB * kRecWords + kTileBlock - 1) / kTileBlock;
+    double rw[MASKED ? kStageWords : 1];
+    int nwords = 0;
+    if (MASKED && planned) {
+        nwords = a.plan_nst[tile] * kRecWords;
+        int rec[kStageWords];
 #pragma unroll
-            for (int j = 0; j < kTileNPT; ++j) {
-                const int i = ni[j];
-                int c = -1;
-                if (i < R) c = ldg(a.code + (int64_t)wrapi(y0 + i / RX, ny) * nx + wrapi(x0 + i % RX, nx));
-                kind[j] = c < 0 ? 2 : (c > 0 ? 1 : 0);
-                b0[j] = __ballot(kind[j] == 0);
-                b1[j] = __ballot(kind[j] == 1);
-                if ((threadIdx.x & 63) == 0) {
-                    wcount[j][0][w] = __popcll(b0[j]);
-                    wcount[j][1][w] = __popcll(b1[j]);
-                }
-            }
-            __syncthreads();
-            // totals and the counts of earlier waves (pass j's waves come after pass j - 1's)
-            int tot0 = 0, tot1 = 0;
-            int pre0[kTileNPT], pre1[kTileNPT];
+        for (int p = 0; p < kStageWords; ++p) {
+            const int w = threadIdx.x + p * kTileBlock;
+            rec[p] = w < nwords ? a.plan_rec[(int64_t)tile * kTileMaxB + w / kRecWords] : 0;
+        }
+        const double* words = reinterpret_cast<const double*>(a.bnodes);
 #pragma unroll
-            for (int j = 0; j < kTileNPT; ++j) {
-                pre0[j] = tot0;
-                pre1[j] = tot1;
-                for (int v = 0; v < W; ++v) {
-                    const int n0 = wcount[j][0][v], n1 = wcount[j][1][v];
-                    if (v < w) {
-                        pre0[j] += n0;
-                        pre1[j] += n1;
-                    }
-                    tot0 += n0;
-                    tot1 += n1;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kTileNPT; ++j) {
-                const int i = ni[j];
-                const int r0 = pre0[j] + __popcll(b0[j] & below), r1 = pre1[j] + __popcll(b1[j] & below);
-                const int slot = kind[j] == 0 ? r0 : kind[j] == 1 ? tot0 + r1 : tot0 + tot1 + (i - r0 - r1);
-                order[slot] = (short)i;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kTileNPT; ++j) ni[j] = order[threadIdx.x + j * kTileBlock];
-        } else {
-            __syncthreads();
+        for (int p = 0; p < kStageWords; ++p) {
+            const int w = threadIdx.x + p * kTileBlock;
+            rw[p] = w < nwords ? ldg(words + (int64_t)rec[p] * kRecWords + w % kRecWords) : 0.0;
         }
     }
 #pragma unroll
     for (int j = 0; j < kTileNPT; ++j) {
         const int i = ni[j];
-        rx[j] = i % RX;
-        ry[j] = i / RX;
+        if (planned) {
+            rx[j] = pe[j].w & 0xffff;
+            ry[j] = pe[j].w >> 16;
+        } else {
+            rx[j] = i % RX;
+            ry[j] = i / RX;
+        }
         cd[j] = -1;
         gn[j] = 0;
         c0[j] = c1[j] = 0.0;
@@ -1177,12 +1224,12 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
         rl[j].kd = a.kd;
         rl[j].gam = 0.0;
         if (i < R) {
-            const int64_t n = (int64_t)wrapi(y0 + ry[j], ny) * nx + wrapi(x0 + rx[j], nx);
+            const int64_t n = planned ? (int64_t)pe[j].x : (int64_t)wrapi(y0 + ry[j], ny) * nx + wrapi(x0 + rx[j], nx);
             gn[j] = n;
             // every load of the node is issued before any of them is used (one
             // round trip; the planes cover the whole box, so outside nodes
             // read defined values, which they do not use)
-            const int code = MASKED ? ldg(a.code + n) : 0;
+            const int code = planned ? pe[j].y : (MASKED ? ldg(a.code + n) : 0);
             double v[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) v[q] = ldg(a.src + q * N + n);
@@ -1211,15 +1258,27 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
         bsl[j] = -1;
         if (MASKED && i < R && cd[j] > 0) {
             const int k = cd[j] - 1;
-            const int slot = atomicAdd(&nstaged, 1);
             bng[j] = a.bnodes + k;
-            if (slot < a.maxb) {
-                const double* s8 = reinterpret_cast<const double*>(a.bnodes + k);
-                double* d8 = reinterpret_cast<double*>(lbn + slot);
+            if (planned) {
+                bsl[j] = (pe[j].z >> 16) - 1;            // -1: past the cap, read from HBM
+            } else {
+                const int slot = atomicAdd(&nstaged, 1);
+                if (slot < a.maxb) {
+                    const double* s8 = reinterpret_cast<const double*>(a.bnodes + k);
+                    double* d8 = reinterpret_cast<double*>(lbn + slot);
 #pragma unroll
-                for (int w = 0; w < (int)(sizeof(BNode) / 8); ++w) d8[w] = ldg(s8 + w);
-                bsl[j] = slot;
+                    for (int w = 0; w < kRecWords; ++w) d8[w] = ldg(s8 + w);
+                    bsl[j] = slot;
+                }
             }
+        }
+    }
+    if (MASKED && planned) {
+        double* lw = reinterpret_cast<double*>(lbn);
+#pragma unroll
+        for (int p = 0; p < kStageWords; ++p) {
+            const int w = threadIdx.x + p * kTileBlock;
+            if (w < nwords) lw[w] = rw[p];
         }
     }
     __syncthreads();
@@ -1314,7 +1373,51 @@ __global__ __launch_bounds__(kTileBlock) void k_sweep_tile(TileArgs a)
 {
     if (a.status->stop) return;
     extern __shared__ __align__(16) double lds[];    // 8 planes of RX * RY doubles (2 copies for plates), then staged records
-    tile_body<MASKED, EFIELD, ADJ>(a, xcd_order(blockIdx.x, gridDim.x), lds);
+    if (a.plan) tile_body<MASKED, EFIELD, ADJ, true>(a, xcd_order(blockIdx.x, gridDim.x), lds);
+    else tile_body<MASKED, EFIELD, ADJ, false>(a, xcd_order(blockIdx.x, gridDim.x), lds);
+}
+
+// Launch plan of a tile shape (grid: one workgroup per tile, in tile order):
+// the node each thread of the sweep kernels runs (the order of tile_order for
+// plates with order_by_kind, else the region order), its grid index, code and
+// position, and the staged boundary records.  Written once per shape; the
+// sweeps then need no code load, ordering pass or index arithmetic before
+// their single round trip for the node data.
+template <bool MASKED>
+__global__ __launch_bounds__(kTileBlock) void k_tile_plan(TileArgs a, int4* plan, int32_t* plan_rec,
+                                                         int32_t* plan_nst)
+{
+    const int tile = blockIdx.x;
+    const int h = a.halo, RX = a.tw + 2 * h, RY = a.th + 2 * h, R = RX * RY;
+    const int x0 = (tile % a.tiles_x) * a.tw - h, y0 = (tile / a.tiles_x) * a.th - h;
+    __shared__ int nst;
+    int ni[kTileNPT];
+#pragma unroll
+    for (int j = 0; j < kTileNPT; ++j) ni[j] = threadIdx.x + j * kTileBlock;
+    if (threadIdx.x == 0) nst = 0;
+    if (MASKED && a.order_by_kind) tile_order(a, x0, y0, RX, R, ni);
+    else __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kTileNPT; ++j) {
+        const int i = ni[j];
+        const int rx = i % RX, ry = i / RX;
+        int n = 0, code = -1, slot1 = 0;
+        if (i < R) {
+            n = wrapi(y0 + ry, a.ny) * a.nx + wrapi(x0 + rx, a.nx);
+            code = MASKED ? ldg(a.code + n) : 0;
+            if (MASKED && code > 0) {
+                const int slot = atomicAdd(&nst, 1);
+                if (slot < a.maxb) {
+                    plan_rec[(int64_t)tile * kTileMaxB + slot] = code - 1;
+                    slot1 = slot + 1;
+                }
+            }
+        }
+        plan[(int64_t)tile * kTileMaxNodes + threadIdx.x + j * kTileBlock] =
+            make_int4(n, code, i | (slot1 << 16), rx | (ry << 16));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) plan_nst[tile] = min(nst, a.maxb);
 }
 
 }  // namespace slbm

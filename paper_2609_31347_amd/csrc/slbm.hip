@@ -456,30 +456,43 @@ int tile_lds_limits(slbm_ctx* c)
     return SLBM_OK;
 }
 
-// Launch plans (k_tile_plan) for tile shapes whose tiles all fit the
-// compute units at once, where each workgroup's fixed cost sets the launch
-// time: the sweeps then read their node assignment, codes and staged-record
-// list instead of forming them (one round trip fewer, no ordering pass).
-// Larger launches keep forming them: there a plan's 16 B per region node
-// would add to bandwidth-bound traffic.  Built once per shape (a shape
-// change rebuilds it); call before the launches of a loop.
+// Launch plans (k_tile_plan): the sweeps read their node assignment, codes
+// and staged-record list instead of forming them (one round trip fewer, no
+// ordering pass).  A single problem takes one for tile shapes whose tiles all
+// fit the compute units at once, where each workgroup's fixed cost sets the
+// launch time; larger single launches keep forming them (there a plan's 16 B
+// per region node would add to bandwidth-bound traffic).  Batches plan every
+// tiled instance (small plates, several rounds of workgroups).  Built once
+// per shape (a shape change rebuilds it); call before the launches of a loop.
 bool tile_plan_wanted(const slbm_ctx* c, int tw, int th)
 {
     const int64_t tiles = (int64_t)((c->nx + tw - 1) / tw) * ((c->ny + th - 1) / th);
     return tiles <= c->simds / 4 && c->N < (int64_t)INT32_MAX;
 }
 
-int ensure_tile_plan(slbm_ctx* c, int halo)
+void dfree(slbm_ctx* c, void* p)
 {
-    int tw, th;
-    tile_shape(c, halo, &tw, &th);
-    if (!tile_plan_wanted(c, tw, th)) return SLBM_OK;
+    if (!p) return;
+    (void)hipFree(p);
+    c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), p), c->allocs.end());
+}
+
+// Builds c's launch plan for tw x th tiles with the given halo and ordering
+// (kept if it is already the plan held; the buffers grow as needed).
+int build_tile_plan(slbm_ctx* c, int halo, int tw, int th, int order)
+{
     const int tiles_x = (c->nx + tw - 1) / tw, tiles = tiles_x * ((c->ny + th - 1) / th);
-    const int order = c->masked ? 1 : 0;
     if (c->plan_key[0] == tw && c->plan_key[1] == th && c->plan_key[2] == halo && c->plan_key[3] == order)
         return SLBM_OK;
-    if (!c->plan) {
-        const int64_t cap = std::max<int64_t>(1, c->simds / 4);
+    c->plan_key[0] = 0;
+    if (tiles > c->plan_cap) {
+        dfree(c, c->plan);
+        dfree(c, c->plan_rec);
+        dfree(c, c->plan_nst);
+        c->plan = nullptr;
+        c->plan_rec = c->plan_nst = nullptr;
+        c->plan_cap = 0;
+        const int64_t cap = tiles;
         void* p = nullptr;
         int rc = dalloc(c, &p, (size_t)cap * kTileMaxNodes * sizeof(int4));
         if (rc) return rc;
@@ -490,7 +503,6 @@ int ensure_tile_plan(slbm_ctx* c, int halo)
         c->plan_nst = (int32_t*)p;
         c->plan_cap = cap;
     }
-    if (tiles > c->plan_cap) return fail(c, SLBM_EHIP, "internal: tile plan capacity");
     TileArgs a;
     std::memset(&a, 0, sizeof(a));
     a.code = c->code;
@@ -515,6 +527,14 @@ int ensure_tile_plan(slbm_ctx* c, int halo)
     c->plan_key[2] = halo;
     c->plan_key[3] = order;
     return SLBM_OK;
+}
+
+int ensure_tile_plan(slbm_ctx* c, int halo)
+{
+    int tw, th;
+    tile_shape(c, halo, &tw, &th);
+    if (!tile_plan_wanted(c, tw, th)) return SLBM_OK;
+    return build_tile_plan(c, halo, tw, th, c->masked ? 1 : 0);
 }
 
 void launch_tile(slbm_ctx* c, bool adjoint, const SweepArgs& s, int steps, int halo)
@@ -1983,6 +2003,12 @@ int batch_tables(slbm_batch* b, bool adjoint)
     std::vector<int2> tb, tl;
     for (int i = 0; i < B; ++i) {
         slbm_ctx* c = b->ctx[i];
+        // tiled instances run with launch plans (not in the no-allocation call)
+        const bool planned = b->tiled[i] && Tt > 1 && !b->static_tables && c->N < (int64_t)INT32_MAX;
+        if (planned) {
+            int rc = build_tile_plan(c, Tt, tw, tw, c->masked ? 1 : 0);
+            if (rc) return bfail(b, rc, "instance " + std::to_string(i) + ": " + c->err);
+        }
         BatchInst I;
         std::memset(&I, 0, sizeof(I));
         SweepArgs a = base_args(c);
@@ -2039,6 +2065,11 @@ int batch_tables(slbm_batch* b, bool adjoint)
                 l.steps = Tt;
                 l.maxb = kTileMaxB;
                 l.tiles_x = (c->nx + tw - 1) / tw;
+                if (planned) {
+                    l.plan = c->plan;
+                    l.plan_rec = c->plan_rec;
+                    l.plan_nst = c->plan_nst;
+                }
                 (k ? I.ladj : I.lprim)[par] = l;
             }
         }

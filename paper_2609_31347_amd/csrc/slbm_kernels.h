@@ -1507,12 +1507,16 @@ __global__ __launch_bounds__(kTileBlock) void k_sweep_tile_batch(const BatchInst
     extern __shared__ __align__(16) double lds[];
     TileArgs a = ADJ ? I.ladj[par] : I.lprim[par];
     a.steps = steps;
-    const int sel = (I.masked ? 2 : 0) | (I.efield ? 1 : 0);
+    const int sel = (I.masked ? 2 : 0) | (I.efield ? 1 : 0) | (a.plan ? 4 : 0);
     switch (sel) {
         case 0: tile_body<false, false, ADJ>(a, e.y, lds); break;
         case 1: tile_body<false, true, ADJ>(a, e.y, lds); break;
         case 2: tile_body<true, false, ADJ>(a, e.y, lds); break;
-        default: tile_body<true, true, ADJ>(a, e.y, lds); break;
+        case 3: tile_body<true, true, ADJ>(a, e.y, lds); break;
+        case 4: tile_body<false, false, ADJ, true>(a, e.y, lds); break;
+        case 5: tile_body<false, true, ADJ, true>(a, e.y, lds); break;
+        case 6: tile_body<true, false, ADJ, true>(a, e.y, lds); break;
+        default: tile_body<true, true, ADJ, true>(a, e.y, lds); break;
     }
 }
 

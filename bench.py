@@ -38,7 +38,7 @@ PEAK_GBS = 8000.0           # MI355X HBM3E
 # plain copy of one population buffer reads in the same runs), mean per
 # dispatch of the fused primal sweep, with the hash of the kernel sources they
 # were taken with (profiles/k_sweep_tb_periodic_2048_bench.md).
-TRAFFIC = {(2048, 8, 96): {"bytes": (2.0 * 198630.6 + 271684.1) * 1024, "sources": "0027cf8311a2dd23"}}
+TRAFFIC = {(2048, 8, 96): {"bytes": (2.0 * 198503.6 + 271561.6) * 1024, "sources": "cf78a3080276f4bc"}}
 
 
 def parse():

@@ -36,9 +36,9 @@ PEAK_GBS = 8000.0           # MI355X HBM3E
 # Measured HBM bytes per launch of the dominant kernel, keyed by (N, T, H):
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors the benchmark's
 # plain copy of one population buffer reads in the same runs), mean per
-# dispatch of the fused primal sweep, with the hash of the kernel sources they
-# were taken with (profiles/k_sweep_tb_periodic_2048_bench.md).
-TRAFFIC = {(2048, 8, 96): {"bytes": (2.0 * 198503.6 + 271561.6) * 1024, "sources": "cf78a3080276f4bc"}}
+# dispatch of the fused primal sweep, with the hash of the kernel code they
+# were taken with (kernel_source_hash; profiles/k_sweep_tb_periodic_2048_bench.md).
+TRAFFIC = {(2048, 8, 96): {"bytes": (2.0 * 198503.6 + 271561.6) * 1024, "sources": "f2c868a50f8942ed"}}
 
 
 def parse():
@@ -522,14 +522,47 @@ def cpu_baseline(n, steps, F, tgt):
             "adjoint_mlups": round(steps * cells / (t3 - t2) / 1e6, 3)}
 
 
+def code_text(src):
+    """C++ source without its comments and with whitespace runs outside string
+    and character literals collapsed: what the compiler sees of the text."""
+    parts, code, i, n = [], [], 0, len(src)
+
+    def flush():
+        parts.extend("".join(code).split())
+        code.clear()
+
+    while i < n:
+        c = src[i]
+        if c in "\"'":                       # literal: kept verbatim through its closing quote
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            flush()
+            parts.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+            code.append(" ")
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            code.append(" ")
+        else:
+            code.append(c)
+            i += 1
+    flush()
+    return " ".join(parts)
+
+
 def kernel_source_hash():
-    """Hash of the sweep kernels' sources: counter figures taken with other
-    sources do not describe the running kernel."""
+    """Hash of the sweep kernels' code (comments and layout ignored): counter
+    figures taken with other code do not describe the running kernel."""
     import hashlib
     h = hashlib.sha256()
     for f in ("slbm_kernels.h", "slbm_device.h"):
-        with open(os.path.join(ROOT, "paper_2609_31347_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2609_31347_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1165,10 +1165,11 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, int tile, double* l
     // boundary nodes, then outside nodes -- so that the few boundary nodes
     // (whose node map is several times the bulk work) fill one or two waves
     // instead of diverging in many, and outside nodes leave whole waves idle.
-    // Each node's arithmetic is unchanged, only the thread that runs it.  The
-    // order costs a round trip to HBM for the node codes before the other
-    // loads; measured, it pays where a launch has no more tiles than the GPU
-    // has CUs (each workgroup's latency sets the time), not beyond.
+    // Each node's arithmetic is unchanged, only the thread that runs it.
+    // Formed here, the order costs a round trip to HBM for the node codes
+    // before the other loads (measured: it pays where a launch has no more
+    // tiles than the GPU has CUs, not beyond); with a launch plan (PLAN) the
+    // thread reads its node, code, position and staged-record slot instead.
     int ni[kTileNPT];
     constexpr bool planned = PLAN;
     int4 pe[kTileNPT];                           // this thread's plan entries

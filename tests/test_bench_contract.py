@@ -31,3 +31,15 @@ def test_kernel_source_hash_names_the_sweep_sources():
     import bench
     h = bench.kernel_source_hash()
     assert len(h) == 16 and h == bench.kernel_source_hash()
+
+
+def test_kernel_source_hash_ignores_comments_and_layout():
+    """Comment and whitespace edits keep the hash (the counters still describe
+    the kernel); code edits and string contents do not."""
+    sys.path.insert(0, ROOT)
+    import bench
+    a = 'int f(int x) { return x + 1; } // one\nconst char* s = "a // b";'
+    b = '/* note */ int  f(int x)\n{\n    return x + 1;   // other words\n}\nconst char* s = "a // b";'
+    assert bench.code_text(a) == bench.code_text(b)
+    assert bench.code_text(a) != bench.code_text(a.replace("x + 1", "x + 2"))
+    assert bench.code_text(a) != bench.code_text(a.replace('"a // b"', '"a  // b"'))

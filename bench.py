@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--train-iters", type=int, default=3000, help="warmstart mode: Adam iterations")
     ap.add_argument("--train-lr", type=float, default=5e-4, help="warmstart mode: peak Adam learning rate")
     ap.add_argument("--eval-sizes", default="64,128,256", help="warmstart mode: plate widths to evaluate")
+    ap.add_argument("--ws-primal", default="",
+                    help="warmstart mode: primal solves only, the listed parts of cold,warm (each field to tol "
+                         "from d_0 = 0 or from the prediction; no target, adjoint or ablations)")
     ap.add_argument("--eval-fields", default="4", help="warmstart mode: held-out E fields per size "
                                                          "(one number, or one per size)")
     ap.add_argument("--rows", type=int, default=0, help="rows per wave of fused launches (0 automatic)")
@@ -406,13 +409,19 @@ def warmstart_mode(args):
     adjoint to the residual tol, all held-out fields of a size in one batch,
     the prediction timed with the warm solves) at each evaluation size, with
     two ablations of the initial state (the E = 1 displacement alone, and the
-    exact solution of the coarse grid interpolated).  Every stage prints one
-    JSON line."""
+    exact solution of the coarse grid interpolated).  With --ws-primal, primal
+    solves only (cold and / or warm, in separate runs if need be: a cold run
+    trains no network).  Every stage prints one JSON line."""
     import torch
     from paper_2609_31347_amd import slbm as S
     from paper_2609_31347_amd import warmstart as WS
+    parts = set(p for p in args.ws_primal.split(",") if p)
+    if parts - {"cold", "warm"}:
+        raise SystemExit("--ws-primal takes cold, warm or cold,warm")
     torch.cuda.set_device(0)
     ws = WS.WarmStart(nx_coarse=64, seed=0)
+    if parts and "warm" not in parts:
+        return warmstart_primal(args, S, WS, ws, parts)
     t0 = time.perf_counter()
     ref_steps = ws.reference(tol=1e-10)
     print(json.dumps({"stage": "reference", "steps": int(ref_steps), "wall_s": round(time.perf_counter() - t0, 2)}),
@@ -431,6 +440,8 @@ def warmstart_mode(args):
     ws.train(X[nv:], Y[nv:], iters=args.train_iters, batch=32, lr=args.train_lr, log_every=500,
              log=lambda r: print(json.dumps({"stage": "train", **r}), flush=True), Xv=X[:nv], Yv=Y[:nv])
     print(json.dumps({"stage": "trained", "wall_s": round(time.perf_counter() - t0, 2)}), flush=True)
+    if parts:
+        return warmstart_primal(args, S, WS, ws, parts)
     rows = []
 
     def primal_steps(cp, fields, target, d0s):
@@ -495,6 +506,32 @@ def warmstart_mode(args):
                "grad_max_rel_diff": float(max(np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in zip(gw, gc)))}
         rows.append(row)
         print(json.dumps(row), flush=True)
+
+
+def warmstart_primal(args, S, WS, ws, parts):
+    """Primal solves of the held-out E fields of each evaluation size to the
+    residual tol, all fields of a size in one batch: cold (d_0 = 0) and / or
+    warm (d_0 from the network, the prediction timed with the solves)."""
+    sizes = [int(v) for v in args.eval_sizes.split(",")]
+    nf = [int(v) for v in str(args.eval_fields).split(",")]
+    for i, nx in enumerate(sizes):
+        cp = WS.plate(nx)
+        fields = [WS.e_field(cp, seed) for seed in range(10000, 10000 + nf[min(i, len(nf) - 1)])]
+        for part in ("cold", "warm"):
+            if part not in parts:
+                continue
+            t0 = time.perf_counter()
+            d0s = ws.predict_batch(cp, fields) if part == "warm" else None
+            tp = time.perf_counter() - t0
+            batch = S.solid_lbm_batch_init([WS.plate_problem(cp, args.tol) for _ in fields])
+            S.solid_lbm_batch_set_progress(batch, progress_printer(f"{part} primal {nx}"), 30.0)
+            rc, _, _, pi, _ = S.batch_objective_and_grad(batch, list(fields), want_grad=False, init_disps=d0s)
+            S.require_converged(rc, f"{part} primal solves")
+            S.solid_lbm_batch_destroy(batch)
+            print(json.dumps({"stage": f"primal_{part}", "grid": [cp["active"].shape[1], cp["active"].shape[0]],
+                              "fields": len(fields), "wall_s": round(time.perf_counter() - t0, 3),
+                              "predict_s": round(tp, 4), "primal_steps": [int(p.steps) for p in pi],
+                              "device_ms": round(pi[0].device_ms, 1)}), flush=True)
 
 
 def cpu_baseline(n, steps, F, tgt):

@@ -111,6 +111,11 @@ def test_batch_fixed_steps_and_tuning():
         assert rel(J, out[0][0]) < 1e-13
         for g, g0 in zip(grads, out[0][1]):
             assert rel(g, g0) < 1e-12
+    batch = S.solid_lbm_batch_init(probs)
+    for bad in (0, 9, -2):
+        with pytest.raises(S.SlbmError) as e:
+            S.solid_lbm_batch_set_tile_steps(batch, bad)
+        assert e.value.code == S.EINVAL
 
 
 def test_batch_gradient_after_primal_equals_one_call():

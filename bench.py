@@ -523,7 +523,7 @@ def warmstart_primal(args, S, WS, ws, parts):
             t0 = time.perf_counter()
             d0s = ws.predict_batch(cp, fields) if part == "warm" else None
             tp = time.perf_counter() - t0
-            batch = S.solid_lbm_batch_init([WS.plate_problem(cp, args.tol) for _ in fields])
+            batch = S.solid_lbm_batch_init([WS.plate_problem(cp, args.tol, max_steps=400_000_000) for _ in fields])
             S.solid_lbm_batch_set_progress(batch, progress_printer(f"{part} primal {nx}"), 30.0)
             rc, _, _, pi, _ = S.batch_objective_and_grad(batch, list(fields), want_grad=False, init_disps=d0s)
             S.require_converged(rc, f"{part} primal solves")

@@ -77,7 +77,7 @@ def test_batch_equals_individual_solves_and_oracle(orc):
         assert pii.steps == pi[i].steps and aii.steps == ai[i].steps, i
         assert abs(J[i] - Ji) <= 1e-13 * abs(Ji), i
         assert rel(grads[i], gi) < 1e-12, i
-    # two instances against the oracle
+    # three instances against the oracle: periodic modes, plate nodal force, plate E field
     n = 32
     q = orc.Problem(n, n, 1 / n, 1.0, 0.3, np.zeros((2, n, n)))
     G = orc.objective_and_grad(q, probs[0]["target"], "modes", ctrls[0], modes=probs[0]["force_modes"], tol=1e-10)
@@ -87,6 +87,16 @@ def test_batch_equals_individual_solves_and_oracle(orc):
                     bc=p["link_bc"], wall=p["link_wall"], normal=p["link_normal"])
     G = orc.objective_and_grad(q, p["target"], "nodal", ctrls[3], tol=1e-10, project=False)
     assert abs(J[3] - G.J) / G.J < 1e-12 and rel(np.asarray(grads[3]).reshape(G.grad.shape), G.grad) < 1e-10
+    # the E field on the clamped plate (tiled class with per-node moduli; about
+    # 100 s of oracle time)
+    p = probs[6]
+    q = orc.Problem(p["nx"], p["ny"], p["dx"], p["E"], p["nu"], np.zeros((2, p["ny"], p["nx"])),
+                    active=p["node_mask"], bc=p["link_bc"], wall=p["link_wall"], normal=p["link_normal"])
+    G = orc.objective_and_grad(q, p["target"], "E_nodal", ctrls[6], fixed_force=np.zeros((2, p["ny"], p["nx"])),
+                               tol=1e-10)
+    assert G.prim.steps == pi[6].steps
+    assert abs(J[6] - G.J) / abs(G.J) < 1e-12
+    assert rel(np.asarray(grads[6]).reshape(G.grad.shape), G.grad) < 1e-10
 
 
 def test_batch_fixed_steps_and_tuning():

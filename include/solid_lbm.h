@@ -293,9 +293,12 @@ int solid_lbm_set_tuning(slbm_ctx *ctx, int32_t steps_per_launch, int32_t rows_p
  * node per thread of a 1024-thread workgroup; 8 FP64 planes in 64 KiB of
  * LDS, two copies for plates).  0, 0 = automatic (a 32 x 32 region; with
  * 8 steps per launch, grids that 16 x 16 tiles would leave short of one
- * workgroup per compute unit take 8 x 8 or 12 x 12 tiles).  Does not
- * change results.  SLBM_EINVAL for one zero and one nonzero value, negative
- * values, or a region over 1024 nodes. */
+ * workgroup per compute unit take 8 x 8 or 12 x 12 tiles).  Shapes whose
+ * tiles all fit the device's compute units run with a launch plan (each
+ * thread's node, code and staged boundary record, 16 KiB per tile) built at
+ * the first solve of the shape.  Does not change results.  SLBM_EINVAL for
+ * one zero and one nonzero value, negative values, or a region over 1024
+ * nodes. */
 int solid_lbm_set_tiles(slbm_ctx *ctx, int32_t tile_w, int32_t tile_h);
 
 /* Progress report of long solves: fn(user, phase, step, residual) is called
@@ -332,7 +335,11 @@ void solid_lbm_destroy(slbm_ctx *ctx);
 typedef struct slbm_batch slbm_batch;
 
 /* Creates a batch from count problems (validated and copied as by
- * solid_lbm_init).  Returns SLBM_OK and *out or a negative code. */
+ * solid_lbm_init).  Returns SLBM_OK and *out or a negative code.  Beyond the
+ * per-instance buffers, the first batched solve of a tile shape gives each
+ * tiled instance (plates, E fields) a launch plan of 16 KiB per tile (plus
+ * 388 B of record list), kept until the shape changes or the batch is
+ * destroyed; the no-allocation call uses none. */
 int solid_lbm_batch_init(const slbm_problem *problems, int32_t count, slbm_batch **out);
 
 /* Objective and gradient of every instance: controls[i] (length per the

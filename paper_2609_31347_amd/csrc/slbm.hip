@@ -2221,9 +2221,9 @@ void batch_plain_steps(slbm_batch* b, bool adjoint, int64_t run, int& pp, int& p
 
 // Advances every instance from buffer 0 in lock-step (step index s), each
 // with its own residual checks every K_i steps and its own stop flag; plain
-// runs between checks are fused for periodic instances.  Afterwards, for each
-// instance: t (its final step), X (buffer holding its input of step t) and
-// whether it converged.
+// runs between checks are fused (wave strips T steps per launch, tiles Tt).
+// Afterwards, for each instance: t (its final step), X (buffer holding its
+// input of step t) and whether it converged.
 int batch_loop_persist(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::vector<int>& x_out,
                        std::vector<char>& conv, std::vector<double>& res, double* dev_ms);
 

@@ -1379,46 +1379,97 @@ __global__ __launch_bounds__(kTileBlock) void k_sweep_tile(TileArgs a)
 }
 
 // Launch plan of a tile shape (grid: one workgroup per tile, in tile order):
-// the node each thread of the sweep kernels runs (the order of tile_order for
-// plates with order_by_kind, else the region order), its grid index, code and
+// the node each thread of the sweep kernels runs, its grid index, code and
 // position, and the staged boundary records.  Written once per shape; the
 // sweeps then need no code load, ordering pass or index arithmetic before
 // their single round trip for the node data.
+//
+// Placement (plates with order_by_kind): a wave's time per sweep is that of
+// the costliest node kind among its lanes, and a SIMD's is the sum over its
+// waves (wave w of the workgroup runs on SIMD w % 4).  Boundary nodes (whose
+// node map is several times the bulk work) fill whole waves of their own, one
+// per SIMD from SIMD 0 on, and the waves of outside nodes (idle) share those
+// SIMDs, so that no SIMD runs a boundary wave on top of a full share of bulk
+// waves.  Where that does not fit (no boundary node, more than 4 boundary
+// waves, too many bulk waves), bulk nodes come first, then boundary nodes,
+// then outside nodes, in region order within each kind.  Unordered launches
+// keep the region order.
 template <bool MASKED>
 __global__ __launch_bounds__(kTileBlock) void k_tile_plan(TileArgs a, int4* plan, int32_t* plan_rec,
                                                          int32_t* plan_nst)
 {
+    static_assert(kTileNPT == 1, "the plan places one region node per thread");
+    constexpr int W = kTileBlock / 64;
     const int tile = blockIdx.x;
     const int h = a.halo, RX = a.tw + 2 * h, RY = a.th + 2 * h, R = RX * RY;
     const int x0 = (tile % a.tiles_x) * a.tw - h, y0 = (tile / a.tiles_x) * a.th - h;
-    __shared__ int nst;
-    int ni[kTileNPT];
+    const int i = threadIdx.x;                          // region node, region order
+    const int rx = i % RX, ry = i / RX;
+    int n = 0, code = -1;
+    if (i < R) {
+        n = wrapi(y0 + ry, a.ny) * a.nx + wrapi(x0 + rx, a.nx);
+        code = MASKED ? ldg(a.code + n) : 0;
+    }
+    const int kind = code < 0 ? 2 : (code > 0 ? 1 : 0);   // bulk, boundary, outside or none
+    // rank of the node within its kind (region order) and the totals
+    __shared__ int cnt[3][W];
+    __shared__ int wave_of[W];                          // placement sequence of the waves
+    const int w = threadIdx.x / 64;
+    const uint64_t below = __lanemask_lt();
+    uint64_t bal[3];
 #pragma unroll
-    for (int j = 0; j < kTileNPT; ++j) ni[j] = threadIdx.x + j * kTileBlock;
-    if (threadIdx.x == 0) nst = 0;
-    if (MASKED && a.order_by_kind) tile_order(a, x0, y0, RX, R, ni);
-    else __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kTileNPT; ++j) {
-        const int i = ni[j];
-        const int rx = i % RX, ry = i / RX;
-        int n = 0, code = -1, slot1 = 0;
-        if (i < R) {
-            n = wrapi(y0 + ry, a.ny) * a.nx + wrapi(x0 + rx, a.nx);
-            code = MASKED ? ldg(a.code + n) : 0;
-            if (MASKED && code > 0) {
-                const int slot = atomicAdd(&nst, 1);
-                if (slot < a.maxb) {
-                    plan_rec[(int64_t)tile * kTileMaxB + slot] = code - 1;
-                    slot1 = slot + 1;
-                }
-            }
-        }
-        plan[(int64_t)tile * kTileMaxNodes + threadIdx.x + j * kTileBlock] =
-            make_int4(n, code, i | (slot1 << 16), rx | (ry << 16));
+    for (int k = 0; k < 3; ++k) {
+        bal[k] = __ballot(kind == k);
+        if ((threadIdx.x & 63) == 0) cnt[k][w] = __popcll(bal[k]);
     }
     __syncthreads();
-    if (threadIdx.x == 0) plan_nst[tile] = min(nst, a.maxb);
+    int tot[3] = {0, 0, 0}, pre[3] = {0, 0, 0};
+    for (int v = 0; v < W; ++v)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (v < w) pre[k] += cnt[k][v];
+            tot[k] += cnt[k][v];
+        }
+    const int rank = (kind == 0 ? pre[0] : kind == 1 ? pre[1] : pre[2]) +
+                     __popcll((kind == 0 ? bal[0] : kind == 1 ? bal[1] : bal[2]) & below);
+    const int nb = (tot[1] + 63) / 64, n0w = (tot[0] + 63) / 64;
+    const bool ordered = MASKED && a.order_by_kind;
+    const bool balanced = ordered && nb >= 1 && nb <= 4 && nb + n0w <= W;
+    const int pad = 64 * nb - tot[1];                  // outside nodes completing the boundary waves
+    const int nI = balanced ? min(min(3 * nb, W - nb - n0w), max(0, tot[2] - pad) / 64) : 0;
+    if (threadIdx.x == 0) {
+        bool used[W] = {};
+        int k = 0;
+        if (balanced) {
+            for (int s = 0; s < nb; ++s) used[wave_of[k++] = s] = true;                  // boundary waves
+            for (int m = 1; m <= 3 && k < nb + nI; ++m)                                   // idle waves beside them
+                for (int s = 0; s < nb && k < nb + nI; ++s) used[wave_of[k++] = s + 4 * m] = true;
+        }
+        for (int v = 0; v < W; ++v)
+            if (!used[v]) wave_of[k++] = v;
+    }
+    __syncthreads();
+    int pos;                                            // place in the sequence of lanes
+    if (balanced) {
+        if (kind == 1) pos = rank;
+        else if (kind == 2) pos = rank < pad ? tot[1] + rank
+                                  : rank < pad + 64 * nI ? 64 * nb + (rank - pad)
+                                                         : 64 * (nb + nI) + tot[0] + (rank - pad - 64 * nI);
+        else pos = 64 * (nb + nI) + rank;
+    } else if (ordered) {
+        pos = kind == 0 ? rank : kind == 1 ? tot[0] + rank : tot[0] + tot[1] + rank;
+    } else {
+        pos = i;
+    }
+    const int slot = wave_of[pos / 64] * 64 + pos % 64;
+    // staged boundary records: the first maxb boundary nodes in region order
+    int slot1 = 0;
+    if (MASKED && kind == 1 && rank < a.maxb) {
+        plan_rec[(int64_t)tile * kTileMaxB + rank] = code - 1;
+        slot1 = rank + 1;
+    }
+    plan[(int64_t)tile * kTileMaxNodes + slot] = make_int4(n, code, i | (slot1 << 16), rx | (ry << 16));
+    if (threadIdx.x == 0) plan_nst[tile] = MASKED ? min(tot[1], a.maxb) : 0;
 }
 
 }  // namespace slbm

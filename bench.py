@@ -38,7 +38,7 @@ PEAK_GBS = 8000.0           # MI355X HBM3E
 # plain copy of one population buffer reads in the same runs), mean per
 # dispatch of the fused primal sweep, with the hash of the kernel code they
 # were taken with (kernel_source_hash; profiles/k_sweep_tb_periodic_2048_bench.md).
-TRAFFIC = {(2048, 8, 96): {"bytes": (2.0 * 198503.6 + 271561.6) * 1024, "sources": "f2c868a50f8942ed"}}
+TRAFFIC = {(2048, 8, 96): {"bytes": (2.0 * 198522.7 + 271613.1) * 1024, "sources": "bf581a3a5fc7624e"}}
 
 
 def parse():

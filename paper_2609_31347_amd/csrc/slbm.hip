@@ -458,16 +458,18 @@ int tile_lds_limits(slbm_ctx* c)
 
 // Launch plans (k_tile_plan): the sweeps read their node assignment, codes
 // and staged-record list instead of forming them (one round trip fewer, no
-// ordering pass).  A single problem takes one for tile shapes whose tiles all
-// fit the compute units at once, where each workgroup's fixed cost sets the
-// launch time; larger single launches keep forming them (there a plan's 16 B
+// ordering pass, boundary nodes placed for balanced SIMDs).  Plates always
+// take one (latency-bound at every size: 512 x 308 in two rounds of
+// workgroups 5.0 -> 3.8 us per primal step, 1024 x 615 11.7 -> 10.5), other
+// problems for tile shapes whose tiles all fit the compute units at once
+// (larger periodic launches keep forming the assignment: there a plan's 16 B
 // per region node would add to bandwidth-bound traffic).  Batches plan every
-// tiled instance (small plates, several rounds of workgroups).  Built once
-// per shape (a shape change rebuilds it); call before the launches of a loop.
+// tiled instance.  Built once per shape (a shape change rebuilds it); call
+// before the launches of a loop.
 bool tile_plan_wanted(const slbm_ctx* c, int tw, int th)
 {
     const int64_t tiles = (int64_t)((c->nx + tw - 1) / tw) * ((c->ny + th - 1) / th);
-    return tiles <= c->simds / 4 && c->N < (int64_t)INT32_MAX;
+    return (c->masked || tiles <= c->simds / 4) && c->N < (int64_t)INT32_MAX;
 }
 
 void dfree(slbm_ctx* c, void* p)
@@ -563,9 +565,10 @@ void launch_tile(slbm_ctx* c, bool adjoint, const SweepArgs& s, int steps, int h
     tile_shape(c, halo, &a.tw, &a.th);
     a.tiles_x = (c->nx + a.tw - 1) / a.tw;
     const int tiles_y = (c->ny + a.th - 1) / a.th;
-    a.order_by_kind = c->masked && (int64_t)a.tiles_x * tiles_y <= c->simds / 4 ? 1 : 0;
-    if (c->plan && c->plan_key[0] == a.tw && c->plan_key[1] == a.th && c->plan_key[2] == halo &&
-        c->plan_key[3] == a.order_by_kind && tile_plan_wanted(c, a.tw, a.th)) {
+    const bool want_plan = tile_plan_wanted(c, a.tw, a.th);
+    a.order_by_kind = c->masked && (want_plan || (int64_t)a.tiles_x * tiles_y <= c->simds / 4) ? 1 : 0;
+    if (want_plan && c->plan && c->plan_key[0] == a.tw && c->plan_key[1] == a.th && c->plan_key[2] == halo &&
+        c->plan_key[3] == a.order_by_kind) {
         a.plan = c->plan;
         a.plan_rec = c->plan_rec;
         a.plan_nst = c->plan_nst;

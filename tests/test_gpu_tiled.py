@@ -230,9 +230,9 @@ def test_full_size_e_field_plate_matches_oracle_steps(S, orc):
 
 def test_one_context_through_planned_and_unplanned_tile_shapes(S):
     """One context switched between tile shapes (launch plans built, rebuilt
-    for a new shape and grown; shapes with more tiles than compute units run
-    without a plan) gives, after every switch, the fixed-step populations and
-    gradient of single steps bit for bit."""
+    for a new shape, grown to 2496 tiles and reused) gives, after every
+    switch, the fixed-step populations and gradient of single steps bit for
+    bit."""
     cp = I.clamped_plate(128, 77)
     pd = dict(cp, E=1.0, nu=0.3)
     E = e_field(pd, 5)
@@ -243,7 +243,7 @@ def test_one_context_through_planned_and_unplanned_tile_shapes(S):
     _, J0, g0, _, _ = S.objective_and_grad(ref, E)
     pops0 = S.solid_lbm_get_field(ref, S.FIELD_POPS)
     ctx = S.solid_lbm_init(p)
-    # 20 x 20 (28 tiles), 26 x 26 (15), 2 x 2 (2496: no plan), 8 x 8 (160), 20 x 20 again
+    # 20 x 20 (28 tiles), 26 x 26 (15), 2 x 2 (2496), 8 x 8 (160), 20 x 20 again
     for T, tiles in ((6, (20, 20)), (3, (26, 26)), (2, (2, 2)), (8, (8, 8)), (6, (20, 20))):
         S.solid_lbm_set_tiles(ctx, 0, 0)
         S.solid_lbm_set_tuning(ctx, 1, 0)

@@ -405,9 +405,10 @@ int solid_lbm_batch_time_sweeps(slbm_batch *batch, int32_t adjoint, int64_t n, d
  * counters, replayed until every instance has stopped; rounds_per_launch
  * rounds per replay (0 = 4096).  In every round each running instance
  * takes its own next piece of work from one shared work-list -- a fused LDS
- * tile sweep of up to T steps (periodic instances are tiled too), a single
- * step (its residual-check step, or the plain steps before its next check or
- * its max_steps), or the reduction of its residual after a check -- so the
+ * tile sweep of up to the tile steps per launch (solid_lbm_batch_set_tile_steps;
+ * periodic instances are tiled too), a single step (its residual-check step,
+ * or the plain steps before its next check or its max_steps), or the
+ * reduction of its residual after a check -- so the
  * instances keep their own step counters and check intervals and a stopped
  * instance takes no more work; a grid barrier ends each round.  Results equal
  * the host-driven launches' bit for bit (same node arithmetic).  A barrier

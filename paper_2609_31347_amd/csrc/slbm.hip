@@ -2338,8 +2338,8 @@ int batch_loop(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::ve
 // replays of [reset of the launch's counters and barrier, the persistent
 // kernel, a copy of the control block to pinned memory] until every instance
 // has stopped.  Every instance runs as LDS tiles (periodic ones too), halo =
-// the batch's T; results equal the host-driven loop's bit for bit (same node
-// arithmetic, same checks).
+// the batch's tile steps Tt; results equal the host-driven loop's bit for bit
+// (same node arithmetic, same checks).
 int batch_loop_persist(slbm_batch* b, bool adjoint, std::vector<int64_t>& t_out, std::vector<int>& x_out,
                        std::vector<char>& conv, std::vector<double>& res, double* dev_ms)
 {

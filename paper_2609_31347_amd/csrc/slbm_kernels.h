@@ -1644,7 +1644,7 @@ enum { PT_NONE = 0, PT_FUSED = 1, PT_SINGLE = 2, PT_CHECK = 3, PT_RESID = 4 };
 struct PersistInst {
     int64_t K;          // check interval
     int64_t last;       // final step index (max_steps)
-    int32_t ntiles;     // tiles of a fused round (tile of 32 - 2 halo nodes, halo = the batch's T)
+    int32_t ntiles;     // tiles of a fused round (tile of 32 - 2 halo nodes, halo = the batch's tile steps Tt)
     int32_t nnb;        // 1024-node blocks of a single step
     int32_t halo;       // steps a fused round may take (tile halo)
     int32_t pad;

@@ -43,3 +43,10 @@ def test_kernel_source_hash_ignores_comments_and_layout():
     assert bench.code_text(a) == bench.code_text(b)
     assert bench.code_text(a) != bench.code_text(a.replace("x + 1", "x + 2"))
     assert bench.code_text(a) != bench.code_text(a.replace('"a // b"', '"a  // b"'))
+
+
+def test_primal_only_warm_start_parts_are_checked_before_any_device_call():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--mode", "warmstart", "--ws-primal",
+                          "cold,bogus"], capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert out.returncode != 0
+    assert "--ws-primal takes cold, warm or cold,warm" in out.stdout + out.stderr
